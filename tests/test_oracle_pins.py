@@ -1,0 +1,412 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle:
+hand-worked values (tests/golden), library routines (np.rot90, np.interp,
+scipy.ndimage.convolve), closed forms, invariants and a dense system matrix
+assembled a second way from library-built per-step matrices.
+
+Paper: Sec. II-A (rotation, Eq. (1), Alg. 1, Eq. (2), Alg. 2), Sec. II-B
+(Eq. (3)-(8)), Sec. III-A-3 (explicit system matrix / adjoint check).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.ndimage
+
+import oracle
+from oracle import geometry, rotation, attenuation, convolution, em
+from oracle.projector import Geometry
+from paper_2301_09710_amd import synth
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "hand_examples.json")))
+
+
+# ------------------------------------------------------------ hand examples
+
+def test_shear_row_hand_values():
+    g = GOLDEN["shear_row"]
+    row = np.array(g["row"])
+    for case in g["cases"]:
+        f = row[:, None]                                   # lines along axis 0, one line
+        out = rotation.shear_lines(f, np.array([case["shift"]]))[:, 0]
+        np.testing.assert_allclose(out, case["out"], rtol=0, atol=1e-15)
+
+
+def test_attenuation_hand_values():
+    g = GOLDEN["attenuation_column"]
+    mu = np.array(g["mu"]).reshape(1, -1, 1)
+    mb = attenuation.mubar(mu, g["dy"])[0, :, 0]
+    np.testing.assert_allclose(np.log(mb), g["log_mubar"], rtol=0, atol=1e-14)
+
+
+def test_quarter_turn_hand_values():
+    g = GOLDEN["quarter_turn_3x3"]
+    a = np.array(g["in"], dtype=np.float64)
+    np.testing.assert_array_equal(rotation.quarter_turn(a, 1), np.array(g["m1"]))
+    np.testing.assert_array_equal(rotation.quarter_turn(a, 2), np.array(g["m2"]))
+
+
+# ------------------------------------------------------------ geometry
+
+def test_angle_split_default_and_ties():
+    # 45 degrees is a view angle for 8 | nview; a tie rounds up: phi = -pi/4
+    for nview in (8, 16, 128):
+        for l in range(nview):
+            s = geometry.split_default(l, nview)
+            theta = 2 * math.pi * l / nview
+            assert -math.pi / 4 - 1e-15 <= s.phi < math.pi / 4
+            assert abs((s.m * math.pi / 2 + s.phi - theta + math.pi) % (2 * math.pi) - math.pi) < 1e-12
+            s2 = geometry.split_angle(theta)
+            if abs(abs(s.phi) - math.pi / 4) > 1e-9:         # away from ties both rules agree
+                assert s2.m == s.m and abs(s2.phi - s.phi) < 1e-12
+        s45 = geometry.split_default(nview // 8, nview)
+        assert s45.m == 1 and s45.phi == -math.pi / 4
+    assert geometry.split_angle(math.pi / 4).m == 1
+
+
+# ------------------------------------------------------------ rotation
+
+def test_zero_angle_is_identity():
+    x = synth.random_volume(9, 9, 3, seed=3).astype(np.float64).transpose(2, 1, 0)
+    s = geometry.split_default(0, 16)
+    assert s.m == 0 and s.t == 0 and s.s == 0
+    np.testing.assert_array_equal(rotation.rotate(x, s), x)
+    np.testing.assert_array_equal(rotation.rotate_T(x, s), x)
+
+
+@pytest.mark.parametrize("n", [6, 7, 16])
+def test_quarter_turn_matches_np_rot90(n):
+    a = np.random.default_rng(n).normal(size=(n, n, 2))
+    for m in range(4):
+        np.testing.assert_array_equal(rotation.quarter_turn(a, m), np.rot90(a, k=m, axes=(0, 1)))
+
+
+def test_shear_matches_np_interp():
+    rng = np.random.default_rng(0)
+    n = 13
+    f = rng.normal(size=(n, 5))
+    shifts = rng.uniform(-4, 4, size=5)
+    out = rotation.shear_lines(f, shifts)
+    for r in range(5):
+        ref = np.interp(np.arange(n) + shifts[r] + 1, np.arange(n + 2), np.pad(f[:, r], 1),
+                        left=0.0, right=0.0)
+        np.testing.assert_allclose(out[:, r], ref, rtol=0, atol=1e-13)
+
+
+def test_rotation_orientation_against_analytic_blob():
+    """A Gaussian blob at c + (r, 0) must land at c + R(theta) (r, 0)."""
+    n = 64
+    c = (n - 1) / 2
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    sig, r = 3.0, 14.0
+
+    def blob(x0, y0):
+        return np.exp(-((i - x0) ** 2 + (j - y0) ** 2) / (2 * sig ** 2))
+
+    f = blob(c + r, c)
+    for deg in (10.0, 37.0, 90.0, 135.0, 200.0, 333.0):
+        th = math.radians(deg)
+        out = rotation.rotate(f[:, :, None], geometry.split_angle(th))[:, :, 0]
+        ref = blob(c + r * math.cos(th), c + r * math.sin(th))
+        wrong = blob(c + r * math.cos(-th), c + r * math.sin(-th))
+        err = np.abs(out - ref).max()
+        assert err < 0.06, (deg, err)
+        assert np.abs(out - wrong).max() > 0.5
+
+
+def test_rotation_conserves_sum_inside_safe_disk():
+    n = 40
+    c = (n - 1) / 2
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    rng = np.random.default_rng(5)
+    f = rng.uniform(size=(n, n)) * (((i - c) ** 2 + (j - c) ** 2) < (0.8 * n / 2) ** 2)
+    for l in range(24):
+        g = rotation.rotate(f[:, :, None], geometry.split_default(l, 24))
+        assert abs(g.sum() - f.sum()) < 1e-11 * f.sum()
+
+
+def test_rotate_T_is_transpose():
+    n = 11
+    rng = np.random.default_rng(7)
+    for l in range(9):
+        s = geometry.split_default(l, 9)
+        a, b = rng.normal(size=(n, n, 2)), rng.normal(size=(n, n, 2))
+        lhs = (rotation.rotate(a, s) * b).sum()
+        rhs = (a * rotation.rotate_T(b, s)).sum()
+        assert abs(lhs - rhs) <= 1e-13 * (abs(lhs) + 1)
+
+
+# ------------------------------------------------------------ convolution
+
+@pytest.mark.parametrize("px,pz", [(1, 1), (3, 5), (7, 7), (9, 3), (15, 15)])
+def test_conv_matches_scipy_nearest(px, pz):
+    rng = np.random.default_rng(px * 100 + pz)
+    nx, ny, nz = 12, 3, 7                                      # kernels wider than the plane too
+    w = rng.normal(size=(nx, ny, nz))
+    p = rng.uniform(size=(px, pz, ny))                         # asymmetric kernels
+    c = convolution.conv_planes(w, p)
+    for jj in range(ny):
+        ref = scipy.ndimage.convolve(w[:, jj, :], p[:, :, jj], mode="nearest")
+        np.testing.assert_allclose(c[:, jj, :], ref, rtol=1e-13, atol=1e-13)
+
+
+def test_conv_T_is_transpose_and_fft_paths():
+    rng = np.random.default_rng(11)
+    nx, ny, nz, px, pz = 10, 4, 6, 7, 5
+    w = rng.normal(size=(nx, ny, nz))
+    g = rng.normal(size=(nx, ny, nz))
+    p = rng.uniform(size=(px, pz, ny))
+    lhs = (convolution.conv_planes(w, p) * g).sum()
+    rhs = (w * convolution.conv_planes_T(g, p)).sum()
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    np.testing.assert_allclose(convolution.conv_sum_fft(w, p, workers=1),
+                               convolution.conv_planes(w, p).sum(axis=1), rtol=0, atol=1e-12)
+    g2 = rng.normal(size=(nx, nz))
+    np.testing.assert_allclose(convolution.conv_planes_T_fft(g2, p, workers=1),
+                               convolution.conv_planes_T(np.repeat(g2[:, None, :], ny, 1), p),
+                               rtol=0, atol=1e-12)
+
+
+# ------------------------------------------------------------ projector special cases
+
+def test_line_sum_quarter_views_delta_psf_zero_mu():
+    """nview = 4, delta PSF, mu = 0: each view is np.rot90 of the slice summed over y."""
+    nx, nz = 10, 3
+    x = synth.random_volume(nx, nx, nz, seed=2)
+    mu = np.zeros_like(x)
+    psf = np.ones((4, nx, 1, 1), dtype=np.float32)
+    g = Geometry(nx, nx, nz, 4, 1, 1, 1.0)
+    v = oracle.forward(x, mu, psf, g)
+    xp = x.astype(np.float64).transpose(2, 1, 0)              # x[i, j, k]
+    for l in range(4):
+        ref = np.rot90(xp, k=l, axes=(0, 1)).sum(axis=1)      # (i, k)
+        np.testing.assert_allclose(v[l], ref.T, rtol=0, atol=1e-13)
+
+
+def test_counts_conserved_without_attenuation():
+    """mu = 0, normalised PSF, support inside the safe disk and at least half a
+    kernel away from the x/z edges: every view carries all the counts."""
+    _, _, psf, _ = synth.config_inputs("tiny", seed=1)
+    x = synth.random_volume(32, 32, 20, seed=9)
+    k, j, i = np.meshgrid(np.arange(20), np.arange(32), np.arange(32), indexing="ij")
+    x = x * ((((i - 15.5) ** 2 + (j - 15.5) ** 2) < 11.0 ** 2) & (k >= 3) & (k < 17))
+    psf = psf.astype(np.float64)
+    psf /= psf.sum(axis=(2, 3), keepdims=True)                # exactly normalised in FP64
+    g = Geometry(32, 32, 20, 16, 7, 7, 1.0)
+    v = oracle.forward(x, np.zeros_like(x), psf, g)
+    for l in range(16):
+        assert abs(v[l].sum() - x.astype(np.float64).sum()) < 1e-10 * x.sum()
+
+
+def test_uniform_attenuation_closed_form():
+    """theta = 0, x = 1, uniform mu0, normalised PSF: every bin equals
+    exp(-dy mu0 / 2) (1 - exp(-dy mu0 ny)) / (1 - exp(-dy mu0))."""
+    nx, nz, mu0, dy = 12, 5, 0.03, 4.8
+    x = np.ones((nz, nx, nx), dtype=np.float32)
+    mu = np.full_like(x, mu0)
+    psf = synth.gaussian_psf(5, 3, nx, 1, 0.7, 1.5).astype(np.float64)
+    psf /= psf.sum(axis=(2, 3), keepdims=True)
+    g = Geometry(nx, nx, nz, 1, 5, 3, dy)
+    v = oracle.forward(x, mu, psf, g)
+    q = math.exp(-dy * float(np.float32(mu0)))
+    ref = math.sqrt(q) * (1 - q ** nx) / (1 - q)
+    np.testing.assert_allclose(v[0], ref, rtol=1e-13)
+
+
+def test_point_source_depth_attenuation():
+    """A single voxel at depth j0 under uniform mu at theta = 0 is seen with
+    weight exp(-dy mu0 (1/2 + (ny - 1 - j0))): the detector is beyond j = ny-1."""
+    nx, nz, mu0, dy = 9, 3, 0.05, 2.0
+    for j0 in (0, 3, 8):
+        x = np.zeros((nz, nx, nx), dtype=np.float32)
+        x[1, j0, 4] = 1.0
+        mu = np.full_like(x, mu0)
+        g = Geometry(nx, nx, nz, 1, 1, 1, dy)
+        v = oracle.forward(x, mu, np.ones((1, nx, 1, 1), np.float32), g)
+        want = math.exp(-dy * float(np.float32(mu0)) * (0.5 + (nx - 1 - j0)))
+        assert abs(v[0, 1, 4] - want) < 1e-14
+        assert abs(v.sum() - want) < 1e-14
+
+
+# ------------------------------------------------------------ dense system matrix, two ways
+
+def _matrix_of(fn, n_in):
+    cols = []
+    e = np.zeros(n_in)
+    for c in range(n_in):
+        e[:] = 0
+        e[c] = 1
+        cols.append(np.array(fn(e), dtype=np.float64, copy=True).ravel())   # fn may return a view of e
+    return np.stack(cols, axis=1)
+
+
+def _steps_matrix(mu, psf, nx, nz, nview, dy, splits):
+    """A assembled from per-step matrices built with library routines only:
+    quarter turn (np.rot90), shear passes (np.interp), Eq. (1) as an explicit
+    triangular-sum matrix, convolution (scipy.ndimage.convolve, 'nearest'),
+    depth sum.  Volume vectors in paper order x[i, j, k] (C order)."""
+    n = nx
+    N = n * n * nz
+    c = (n - 1) / 2
+
+    def to_p(vec):
+        return vec.reshape(n, n, nz)
+
+    blocks = []
+    mu_p = mu.astype(np.float64).transpose(2, 1, 0).ravel()
+    # Eq. (1) sum operator T: (T m)[i,j,k] = m[i,j,k]/2 + sum_{s>j} m[i,s,k]
+    T1 = np.triu(np.ones((n, n)), 1) + 0.5 * np.eye(n)           # along j
+    T = np.kron(np.kron(np.eye(n), T1), np.eye(nz))
+    for l in range(nview):
+        s = splits[l]
+        Q = _matrix_of(lambda e: np.rot90(to_p(e), k=s.m, axes=(0, 1)), N)
+
+        def shear_i(e, d=s.t):
+            f = to_p(e).copy()
+            out = np.zeros_like(f)
+            for jj in range(n):
+                for kk in range(nz):
+                    out[:, jj, kk] = np.interp(np.arange(n) + d * (jj - c) + 1, np.arange(n + 2),
+                                               np.pad(f[:, jj, kk], 1), left=0.0, right=0.0)
+            return out
+
+        def shear_j(e, d=-s.s):
+            f = to_p(e).copy()
+            out = np.zeros_like(f)
+            for ii in range(n):
+                for kk in range(nz):
+                    out[ii, :, kk] = np.interp(np.arange(n) + d * (ii - c) + 1, np.arange(n + 2),
+                                               np.pad(f[ii, :, kk], 1), left=0.0, right=0.0)
+            return out
+
+        S1 = _matrix_of(shear_i, N)
+        S2 = _matrix_of(shear_j, N)
+        R = S1 @ S2 @ S1 @ Q                                     # pass 3 . pass 2 . pass 1 . P_m
+        mubar = np.exp(-dy * (T @ (R @ mu_p)))
+        p = psf[l].astype(np.float64)                            # [j][b][a]
+
+        def conv(e):
+            f = to_p(e)
+            out = np.zeros_like(f)
+            for jj in range(n):
+                out[:, jj, :] = scipy.ndimage.convolve(f[:, jj, :], p[jj].T, mode="nearest")
+            return out
+
+        C = _matrix_of(conv, N)
+        # depth sum into [k][i] order (storage order of one projection)
+        D = np.zeros((nz * n, N))
+        for ii in range(n):
+            for jj in range(n):
+                for kk in range(nz):
+                    D[kk * n + ii, (ii * n + jj) * nz + kk] = 1.0
+        blocks.append(D @ C @ (mubar[:, None] * R))
+    A_p = np.vstack(blocks)
+    # reorder columns from paper order (i, j, k) to storage order (k, j, i)
+    perm = np.arange(N).reshape(n, n, nz).transpose(2, 1, 0).ravel()
+    return A_p[:, perm]
+
+
+CASES = [
+    # (nx, nz, nview, px, pz, symmetric, angles)
+    (8, 6, 7, 3, 3, True, None),          # the paper's adjoint-check size
+    (7, 5, 8, 5, 3, False, None),         # 8 views -> exact 45-degree ties
+    (6, 4, 9, 9, 9, False, None),         # kernels wider than the plane
+    (6, 3, 5, 3, 5, False, [0.3, 1.7, 2.9, 4.4, 5.9]),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_dense_matrix_two_ways_and_transpose(case):
+    nx, nz, nview, px, pz, sym, angles = case
+    rng_seed = nx * 1000 + nview
+    mu = synth.random_volume(nx, nx, nz, seed=rng_seed, high=0.2)
+    psf = synth.random_psf(px, pz, nx, nview, seed=rng_seed + 1, symmetric=sym)
+    dy = 1.3
+    g = Geometry(nx, nx, nz, nview, px, pz, dy, angles=angles)
+    A = oracle.dense.forward_matrix(mu, psf, g)
+    A2 = _steps_matrix(mu, psf, nx, nz, nview, dy, g.splits)
+    assert np.abs(A - A2).max() <= 1e-14 * np.abs(A).max()
+    B = oracle.dense.back_matrix(mu, psf, g)
+    assert np.abs(B - A.T).max() <= 1e-14 * np.abs(A).max()
+
+
+def test_adjoint_identity_tiny_config():
+    x, mu, psf, dy = synth.config_inputs("tiny", seed=0, view_wobble=0.1)
+    g = Geometry(32, 32, 20, 16, 7, 7, dy)
+    y = np.random.default_rng(3).uniform(size=(16, 20, 32))
+    lhs = (oracle.forward(x, mu, psf, g) * y).sum()
+    rhs = (x.astype(np.float64) * oracle.back(y, mu, psf, g)).sum()
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_fft_path_matches_direct_mid_size():
+    nx, nz, nview, px = 48, 24, 24, 15
+    x, mu = synth.body_phantom(nx, nx, nz, seed=2)
+    psf = synth.gaussian_psf(px, px, nx, nview, 1.0, 3.0, view_wobble=0.1)
+    g = Geometry(nx, nx, nz, nview, px, px, 4.8 * 128 / nx)
+    views = [0, 3, 7, 13]
+    vd = oracle.forward(x, mu, psf, g, views=views)
+    vf = oracle.forward(x, mu, psf, g, views=views, conv="fft")
+    assert np.abs(vd - vf).max() <= 1e-12 * np.abs(vd).max()
+    y = np.random.default_rng(0).uniform(size=vd.shape) * (np.arange(nview) % 2 == 0)[:, None, None]
+    bd = oracle.back(y, mu, psf, g, views=views)
+    bf = oracle.back(y, mu, psf, g, views=views, conv="fft")
+    assert np.abs(bd - bf).max() <= 1e-12 * np.abs(bd).max()
+
+
+# ------------------------------------------------------------ EM (Sec. II-B)
+
+def _tiny_problem(seed=0):
+    nx, nz, nview = 10, 4, 6
+    x, mu = synth.body_phantom(nx, nx, nz, seed=seed)
+    psf = synth.gaussian_psf(3, 3, nx, nview, 0.5, 1.0)
+    g = Geometry(nx, nx, nz, nview, 3, 3, 4.8 * 128 / nx)
+
+    def A(v):
+        return oracle.forward(v.reshape(nz, nx, nx), mu, psf, g)
+
+    def At(v):
+        return oracle.back(v, mu, psf, g)
+
+    return x.astype(np.float64) + 0.1, A, At, g
+
+
+def test_em_fixed_point_count_preservation_and_monotone_likelihood():
+    xt, A, At, g = _tiny_problem()
+    sens = At(np.ones((g.nview, g.nz, g.nx)))
+    y_clean = A(xt)
+    # noiseless consistent data: the truth is a fixed point
+    x1 = em.mlem_step(xt, y_clean, None, sens, A, At)
+    np.testing.assert_allclose(x1, xt, rtol=1e-12)
+    # noisy data with background: counts preserved and NLL non-increasing
+    r = np.full(y_clean.shape, 0.05 * y_clean.mean())
+    y = synth.poisson_counts(y_clean * 50 + r, seed=4)
+    x = np.ones_like(xt)
+    nll = em.neg_log_likelihood(A(x) + r, y)
+    for _ in range(5):
+        xn = em.mlem_step(x, y, r, sens, A, At)
+        ybar = A(x) + r
+        # 1'A x+ = sum_i y_i (A x)_i / ybar_i (exact EM identity)
+        assert abs(A(xn).sum() - (y * A(x) / ybar).sum()) < 1e-9 * y.sum()
+        nll_n = em.neg_log_likelihood(A(xn) + r, y)
+        assert nll_n <= nll + 1e-9 * abs(nll)
+        x, nll = xn, nll_n
+    # r = 0: 1'A x+ = 1'y
+    x0 = np.ones_like(xt)
+    xr = em.mlem_step(x0, y, None, sens, A, At)
+    assert abs(A(xr).sum() - y.sum()) < 1e-9 * y.sum()
+
+
+def test_regularized_update_limit_and_quadratic():
+    rng = np.random.default_rng(2)
+    x = rng.uniform(0.1, 2, 50)
+    e = rng.uniform(0.1, 2, 50)
+    s = rng.uniform(0.5, 2, 50)
+    u = rng.uniform(0, 3, 50)
+    for beta in (1e-3, 0.5, 4.0):
+        xh = em.reg_em_update(x, e, s, u, beta)
+        d = s - beta * u
+        np.testing.assert_allclose(beta * xh ** 2 + d * xh - x * e, 0, atol=1e-12)
+        assert (xh >= 0).all()
+    np.testing.assert_allclose(em.reg_em_update(x, e, s, u, 1e-12), x * e / s, rtol=1e-9)
