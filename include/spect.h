@@ -1,0 +1,134 @@
+/*
+ * spect.h -- C ABI of the MI355X (gfx950) rotation-based SPECT projector pair.
+ *
+ * Operator (Z. Li, Y. K. Dewaraja, J. A. Fessler, "Training End-to-End
+ * Unrolled Iterative Neural Networks for SPECT Image Reconstruction"):
+ *
+ *   forward A (Sec. II-A, Alg. 1): for every view l, rotate the activity x and
+ *     the attenuation map mu about z by theta_l (exact quarter turn, then three
+ *     1-D linear-interpolation shears, zero outside the grid); form the
+ *     accumulated attenuation factor of Eq. (1); weight; convolve every depth
+ *     plane j with its PSF p(:,:,j,l) using replicate padding; sum over depth.
+ *   back A' (Eq. (2), Alg. 2): the exact transpose of every one of those steps
+ *     (transposed interpolation, the fold that is the adjoint of replicate
+ *     padding), summed over views.
+ *   EM (Sec. II-B, Eq. (7)-(8) with beta -> 0):
+ *     x <- x * A'(y / (A x + r)) / A'1.
+ *
+ * Layouts (C order, float32, 0-based indices):
+ *   volume      x[k][j][i]          nz x ny x nx   (i = x fastest, j = depth y)
+ *   projection  v[l][k][i]          nview x nz x nx
+ *   PSF         p[l][j][b][a]       nview x ny x pz x px (a along x fastest)
+ * Plane j = ny-1 is nearest the detector.  Rotation centre c = (nx-1)/2.
+ *
+ * Memory ownership: the caller owns every device buffer (x, v, mu, psf, y, r,
+ * sens, workspace).  A plan borrows mu, psf and the workspace; they must stay
+ * valid and unmodified until spect_plan_destroy.  The library allocates only
+ * the small host-side plan object; forward / back / em_step never allocate.
+ * Outputs are overwritten, never accumulated.  Input and output buffers of one
+ * call must not overlap (except x of spect_em_step, which is updated in place).
+ *
+ * Streams: every call enqueues work on the given HIP stream and returns without
+ * synchronising.  A plan has one workspace, so at most one call per plan may
+ * be in flight at a time; ordering across streams is the caller's business.
+ *
+ * Errors: argument, shape, alignment and workspace problems are reported
+ * synchronously, before anything is enqueued (so they can be tested without a
+ * GPU).  A failed launch returns SPECT_ERR_HIP.  Device faults surface at the
+ * caller's next synchronisation.  No C++ exception crosses this ABI.
+ */
+#ifndef SPECT_H_
+#define SPECT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spect_plan_s* spect_plan;
+
+typedef enum {
+  SPECT_OK = 0,
+  SPECT_ERR_NULL = 1,        /* a required pointer is NULL */
+  SPECT_ERR_SHAPE = 2,       /* nx != ny, non-positive size, even PSF size */
+  SPECT_ERR_VALUE = 3,       /* dy <= 0 or not finite, non-finite angle, bad flag */
+  SPECT_ERR_WORKSPACE = 4,   /* workspace smaller than spect_workspace_bytes */
+  SPECT_ERR_UNSUPPORTED = 5, /* size outside what this build supports */
+  SPECT_ERR_HIP = 6,         /* a HIP runtime call or launch failed */
+  SPECT_ERR_ALIGN = 7        /* device pointer not aligned as documented */
+} spect_status;
+
+/* flags */
+#define SPECT_CACHE_MUBAR 0x1u  /* keep the attenuation factor of Eq. (1) for all
+                                   views in the workspace (nview*nx*ny*nz floats),
+                                   computed once at plan creation */
+
+/* Geometry of one plan (host struct, copied by spect_plan_create). */
+typedef struct {
+  int32_t nx, ny, nz;     /* volume size; nx == ny (rotation about z) */
+  int32_t nview;          /* number of projection views */
+  int32_t px, pz;         /* PSF size along x and z; both odd */
+  double dy;              /* voxel size along y (same length unit as 1/mu), Eq. (1) */
+  const double* angles;   /* host array of nview angles in radians, or NULL for
+                             theta_l = 2 pi l / nview (Sec. II-A); read only
+                             during spect_plan_create */
+  uint32_t flags;         /* SPECT_CACHE_MUBAR or 0 */
+  int32_t view_batch;     /* views processed per internal batch; 0 = all.
+                             Smaller batches need less workspace. */
+} spect_geom;
+
+/* Workspace bytes a plan with geometry g needs (host only, no GPU call).
+ * Returns SPECT_ERR_* for an invalid geometry. */
+spect_status spect_workspace_bytes(const spect_geom* g, size_t* bytes);
+
+/* Create a plan.  d_mu: [nz][ny][nx] attenuation map (units of 1/dy),
+ * d_psf: [nview][ny][pz][px], d_workspace: device memory of ws_bytes
+ * (>= spect_workspace_bytes, 256-byte aligned).  All three are borrowed.
+ * Enqueues the upload of the per-view shear tables (and, with
+ * SPECT_CACHE_MUBAR, the attenuation-factor precomputation) on `stream`. */
+spect_status spect_plan_create(spect_plan* out, const spect_geom* g,
+                               const float* d_mu, const float* d_psf,
+                               void* d_workspace, size_t ws_bytes,
+                               hipStream_t stream);
+
+/* v = A x.  d_x: [nz][ny][nx], d_v: [nview][nz][nx] (overwritten).  Alg. 1. */
+spect_status spect_forward(spect_plan plan, const float* d_x, float* d_v,
+                           hipStream_t stream);
+
+/* x = A' v.  d_v: [nview][nz][nx], d_x: [nz][ny][nx] (overwritten).
+ * Exact transpose of spect_forward; Eq. (2), Alg. 2. */
+spect_status spect_back(spect_plan plan, const float* d_v, float* d_x,
+                        hipStream_t stream);
+
+/* One ML-EM update in place (Eq. (7)-(8), beta -> 0):
+ *   ybar = A x + r;  rho = y / ybar (0 where ybar <= 0);
+ *   x <- x * A' rho / sens (0 where sens <= 0).
+ * d_y: [nview][nz][nx] measured counts; d_r: background of the same shape or
+ * NULL for zero; d_sens: A'1, [nz][ny][nx] (caller computes it once with
+ * spect_back on a projection of ones). */
+spect_status spect_em_step(spect_plan plan, float* d_x, const float* d_y,
+                           const float* d_r, const float* d_sens,
+                           hipStream_t stream);
+
+/* Release the host plan object (does not free borrowed device memory). */
+spect_status spect_plan_destroy(spect_plan plan);
+
+/* Human-readable text of a status code (static storage). */
+const char* spect_status_string(spect_status s);
+
+/* Test support: *d_out = sum_i (double)a[i] * (double)b[i] for float32 device
+ * arrays of n elements, accumulated in FP64 in a fixed order (deterministic).
+ * d_out is a device pointer to one double.  Used for adjoint-identity checks. */
+spect_status spect_dot_f64(const float* d_a, const float* d_b, size_t n,
+                           double* d_out, hipStream_t stream);
+
+/* Library version string. */
+const char* spect_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPECT_H_ */

@@ -1,0 +1,65 @@
+// Element-wise EM kernels (Sec. II-B, Eq. (7)-(8) with beta -> 0) and the
+// FP64 inner product used by adjoint checks.
+#include "internal.h"
+
+namespace spect {
+namespace {
+
+// rho = y / (v + r), 0 where the mean v + r <= 0.
+__global__ void em_ratio_kernel(const float* __restrict__ v, const float* __restrict__ y,
+                                const float* __restrict__ r, float* __restrict__ rho, size_t m) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  const float ybar = v[q] + (r ? r[q] : 0.0f);
+  rho[q] = ybar > 0.0f ? y[q] / ybar : 0.0f;
+}
+
+// x <- x * e / sens, 0 where sens <= 0.
+__global__ void em_update_kernel(float* __restrict__ x, const float* __restrict__ e,
+                                 const float* __restrict__ sens, size_t n) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const float s = sens[q];
+  x[q] = s > 0.0f ? x[q] * e[q] / s : 0.0f;
+}
+
+constexpr int kDotThreads = 1024;
+
+// Single workgroup, fixed order: thread t sums elements t, t+T, ... in FP64,
+// then a tree reduction in LDS.  Deterministic for a given n.
+__global__ __launch_bounds__(kDotThreads) void dot_f64_kernel(const float* __restrict__ a,
+                                                              const float* __restrict__ b,
+                                                              size_t n, double* __restrict__ out) {
+  __shared__ double red[kDotThreads];
+  double s = 0.0;
+  for (size_t q = threadIdx.x; q < n; q += kDotThreads) s += (double)a[q] * (double)b[q];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kDotThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+}  // namespace
+
+hipError_t launch_em_ratio(const float* v, const float* y, const float* r, float* rho, size_t m,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(em_ratio_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, v, y, r,
+                     rho, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_em_update(float* x, const float* e, const float* sens, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(em_update_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, e,
+                     sens, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot_f64(const float* a, const float* b, size_t n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(dot_f64_kernel, dim3(1), dim3(kDotThreads), 0, s, a, b, n, out);
+  return hipGetLastError();
+}
+
+}  // namespace spect

@@ -1,0 +1,259 @@
+// C ABI of libspect: plan creation (host FP64 geometry tables, workspace
+// layout, argument validation) and the entry points that chain the kernels.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace spect {
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static spect_status validate(const spect_geom* g) {
+  if (!g) return SPECT_ERR_NULL;
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1 || g->nview < 1 || g->px < 1 || g->pz < 1)
+    return SPECT_ERR_SHAPE;
+  if (g->nx != g->ny) return SPECT_ERR_SHAPE;              // rotation about z needs a square slice
+  if ((g->px & 1) == 0 || (g->pz & 1) == 0) return SPECT_ERR_SHAPE;  // centred odd kernels
+  if (!(std::isfinite(g->dy) && g->dy > 0.0)) return SPECT_ERR_VALUE;
+  if (g->flags & ~SPECT_CACHE_MUBAR) return SPECT_ERR_VALUE;
+  if (g->view_batch < 0) return SPECT_ERR_VALUE;
+  if (g->angles)
+    for (int l = 0; l < g->nview; ++l)
+      if (!std::isfinite(g->angles[l])) return SPECT_ERR_VALUE;
+  if (g->nx > kMaxLdsN) return SPECT_ERR_UNSUPPORTED;
+  // index arithmetic inside a plane / slice uses 32-bit ints
+  if ((int64_t)g->nx * g->nz > (1 << 30) || (int64_t)g->px * g->pz > (1 << 20))
+    return SPECT_ERR_UNSUPPORTED;
+  return SPECT_OK;
+}
+
+spect_status compute_layout(const spect_geom& g, Layout* lay, int* view_batch, int* nchunk) {
+  spect_status st = validate(&g);
+  if (st != SPECT_OK) return st;
+  const size_t n = (size_t)g.nx;
+  const size_t N = n * g.ny * g.nz;
+  const size_t M = (size_t)g.nview * g.nz * g.nx;
+  const int vb = (g.view_batch > 0 && g.view_batch < g.nview) ? g.view_batch : g.nview;
+  const int nc = (g.ny + kFwdJChunk - 1) / kFwdJChunk;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t at = off; off += align256(bytes); return at; };
+  lay->tables_quarter = take((size_t)g.nview * sizeof(int32_t));
+  lay->tables_off = take((size_t)g.nview * 2 * n * sizeof(int32_t));
+  lay->tables_w = take((size_t)g.nview * 2 * n * sizeof(float2));
+  lay->vol_batch = take((size_t)vb * N * sizeof(float));
+  lay->fwd_partial = take((size_t)nc * vb * g.nz * g.nx * sizeof(float));
+  lay->back_partial = take((size_t)kBackGroups * N * sizeof(float));
+  lay->mubar_cache = (g.flags & SPECT_CACHE_MUBAR) ? take((size_t)g.nview * N * sizeof(float)) : 0;
+  lay->em_proj = take(M * sizeof(float));
+  lay->em_vol = take(N * sizeof(float));
+  lay->total = off;
+  *view_batch = vb;
+  *nchunk = nc;
+  return SPECT_OK;
+}
+
+// theta = M pi/2 + phi, phi in [-pi/4, pi/4); integer rule for default angles.
+static void split_view(const spect_geom& g, int l, int* m, double* phi) {
+  long long M;
+  if (!g.angles) {
+    M = (8LL * l + g.nview) / (2LL * g.nview);
+    *phi = (M_PI / 2.0) * (double)(4LL * l - M * g.nview) / (double)g.nview;
+  } else {
+    const double th = g.angles[l];
+    M = (long long)std::floor(th / (M_PI / 2.0) + 0.5);
+    *phi = th - (double)M * (M_PI / 2.0);
+  }
+  *m = (int)(((M % 4) + 4) % 4);
+}
+
+static void fill_tables(const spect_geom& g, int32_t* q, int32_t* off, float2* w) {
+  const int n = g.nx;
+  const double c = (n - 1) / 2.0;
+  for (int l = 0; l < g.nview; ++l) {
+    int m;
+    double phi;
+    split_view(g, l, &m, &phi);
+    q[l] = m;
+    const double t = std::tan(phi / 2.0), s = std::sin(phi);
+    for (int r = 0; r < n; ++r) {
+      const double d13 = t * ((double)r - c);    // passes 1, 3: shift along i for row j = r
+      const double d2 = -s * ((double)r - c);    // pass 2: shift along j for column i = r
+      const double ds[2] = {d13, d2};
+      for (int ps = 0; ps < 2; ++ps) {
+        const double fl = std::floor(ds[ps]);
+        const double f = ds[ps] - fl;
+        off[((size_t)l * 2 + ps) * n + r] = (int32_t)fl;
+        w[((size_t)l * 2 + ps) * n + r] = make_float2((float)(1.0 - f), (float)f);
+      }
+    }
+  }
+}
+
+}  // namespace spect
+
+using namespace spect;
+
+extern "C" {
+
+const char* spect_version(void) { return "libspect 0.1 (gfx950)"; }
+
+const char* spect_status_string(spect_status s) {
+  switch (s) {
+    case SPECT_OK: return "ok";
+    case SPECT_ERR_NULL: return "null pointer argument";
+    case SPECT_ERR_SHAPE: return "invalid shape (nx != ny, non-positive size or even PSF size)";
+    case SPECT_ERR_VALUE: return "invalid value (dy, angles, flags or view_batch)";
+    case SPECT_ERR_WORKSPACE: return "workspace too small";
+    case SPECT_ERR_UNSUPPORTED: return "size not supported by this build";
+    case SPECT_ERR_HIP: return "HIP runtime error";
+    case SPECT_ERR_ALIGN: return "misaligned device pointer";
+  }
+  return "unknown status";
+}
+
+spect_status spect_workspace_bytes(const spect_geom* g, size_t* bytes) {
+  if (!g || !bytes) return SPECT_ERR_NULL;
+  Layout lay;
+  int vb, nc;
+  spect_status st = compute_layout(*g, &lay, &vb, &nc);
+  if (st != SPECT_OK) return st;
+  *bytes = lay.total;
+  return SPECT_OK;
+}
+
+static bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+spect_status spect_plan_create(spect_plan* out, const spect_geom* g, const float* d_mu,
+                               const float* d_psf, void* d_workspace, size_t ws_bytes,
+                               hipStream_t stream) {
+  if (!out || !g || !d_mu || !d_psf || !d_workspace) return SPECT_ERR_NULL;
+  *out = nullptr;
+  Layout lay;
+  int vb, nc;
+  spect_status st = compute_layout(*g, &lay, &vb, &nc);
+  if (st != SPECT_OK) return st;
+  if (!aligned(d_workspace, 256) || !aligned(d_mu, 4) || !aligned(d_psf, 4)) return SPECT_ERR_ALIGN;
+  if (ws_bytes < lay.total) return SPECT_ERR_WORKSPACE;
+
+  Plan* p = new (std::nothrow) Plan();
+  if (!p) return SPECT_ERR_HIP;
+  p->g = *g;
+  p->g.angles = nullptr;
+  p->view_batch = vb;
+  p->nchunk = nc;
+  p->mu = d_mu;
+  p->psf = d_psf;
+  p->ws = static_cast<char*>(d_workspace);
+  p->lay = lay;
+  const size_t n = (size_t)g->nx;
+  p->h_quarter = static_cast<int32_t*>(std::malloc(g->nview * sizeof(int32_t)));
+  p->h_off = static_cast<int32_t*>(std::malloc(g->nview * 2 * n * sizeof(int32_t)));
+  p->h_w = static_cast<float2*>(std::malloc(g->nview * 2 * n * sizeof(float2)));
+  if (!p->h_quarter || !p->h_off || !p->h_w) {
+    spect_plan_destroy(reinterpret_cast<spect_plan>(p));
+    return SPECT_ERR_HIP;
+  }
+  fill_tables(*g, p->h_quarter, p->h_off, p->h_w);
+  p->tab.quarter = reinterpret_cast<const int32_t*>(p->ws + lay.tables_quarter);
+  p->tab.off = reinterpret_cast<const int32_t*>(p->ws + lay.tables_off);
+  p->tab.w = reinterpret_cast<const float2*>(p->ws + lay.tables_w);
+  hipError_t e = hipMemcpyAsync(p->ws + lay.tables_quarter, p->h_quarter,
+                                g->nview * sizeof(int32_t), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->ws + lay.tables_off, p->h_off, g->nview * 2 * n * sizeof(int32_t),
+                       hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->ws + lay.tables_w, p->h_w, g->nview * 2 * n * sizeof(float2),
+                       hipMemcpyHostToDevice, stream);
+  p->mubar = nullptr;
+  if (e == hipSuccess && (g->flags & SPECT_CACHE_MUBAR)) {
+    float* cache = reinterpret_cast<float*>(p->ws + lay.mubar_cache);
+    e = launch_mubar_cache(*p, cache, stream);
+    p->mubar = cache;
+  }
+  if (e != hipSuccess) {
+    // make sure no queued copy still reads the host tables before freeing them
+    (void)hipStreamSynchronize(stream);
+    spect_plan_destroy(reinterpret_cast<spect_plan>(p));
+    return SPECT_ERR_HIP;
+  }
+  *out = reinterpret_cast<spect_plan>(p);
+  return SPECT_OK;
+}
+
+spect_status spect_plan_destroy(spect_plan plan) {
+  if (!plan) return SPECT_ERR_NULL;
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  std::free(p->h_quarter);
+  std::free(p->h_off);
+  std::free(p->h_w);
+  delete p;
+  return SPECT_OK;
+}
+
+static spect_status forward_impl(const Plan& p, const float* x, float* v, hipStream_t s) {
+  float* W = reinterpret_cast<float*>(p.ws + p.lay.vol_batch);
+  float* part = reinterpret_cast<float*>(p.ws + p.lay.fwd_partial);
+  for (int v0 = 0; v0 < p.g.nview; v0 += p.view_batch) {
+    const int nvb = (p.g.nview - v0 < p.view_batch) ? p.g.nview - v0 : p.view_batch;
+    if (launch_rot_fwd(p, x, W, v0, nvb, s) != hipSuccess) return SPECT_ERR_HIP;
+    if (launch_conv_fwd(p, W, part, v0, nvb, s) != hipSuccess) return SPECT_ERR_HIP;
+    if (launch_fwd_reduce(p, part, v, v0, nvb, s) != hipSuccess) return SPECT_ERR_HIP;
+  }
+  return SPECT_OK;
+}
+
+static spect_status back_impl(const Plan& p, const float* v, float* x, hipStream_t s) {
+  float* U = reinterpret_cast<float*>(p.ws + p.lay.vol_batch);
+  float* part = reinterpret_cast<float*>(p.ws + p.lay.back_partial);
+  for (int v0 = 0; v0 < p.g.nview; v0 += p.view_batch) {
+    const int nvb = (p.g.nview - v0 < p.view_batch) ? p.g.nview - v0 : p.view_batch;
+    if (launch_conv_back(p, v, U, v0, nvb, s) != hipSuccess) return SPECT_ERR_HIP;
+    if (launch_rot_back(p, U, part, v0, nvb, v0 > 0, s) != hipSuccess) return SPECT_ERR_HIP;
+  }
+  if (launch_back_reduce(p, part, x, s) != hipSuccess) return SPECT_ERR_HIP;
+  return SPECT_OK;
+}
+
+spect_status spect_forward(spect_plan plan, const float* d_x, float* d_v, hipStream_t stream) {
+  if (!plan || !d_x || !d_v) return SPECT_ERR_NULL;
+  if (!aligned(d_x, 4) || !aligned(d_v, 4)) return SPECT_ERR_ALIGN;
+  return forward_impl(*reinterpret_cast<Plan*>(plan), d_x, d_v, stream);
+}
+
+spect_status spect_back(spect_plan plan, const float* d_v, float* d_x, hipStream_t stream) {
+  if (!plan || !d_v || !d_x) return SPECT_ERR_NULL;
+  if (!aligned(d_x, 4) || !aligned(d_v, 4)) return SPECT_ERR_ALIGN;
+  return back_impl(*reinterpret_cast<Plan*>(plan), d_v, d_x, stream);
+}
+
+spect_status spect_em_step(spect_plan plan, float* d_x, const float* d_y, const float* d_r,
+                           const float* d_sens, hipStream_t stream) {
+  if (!plan || !d_x || !d_y || !d_sens) return SPECT_ERR_NULL;
+  if (!aligned(d_x, 4) || !aligned(d_y, 4) || !aligned(d_sens, 4) || (d_r && !aligned(d_r, 4)))
+    return SPECT_ERR_ALIGN;
+  const Plan& p = *reinterpret_cast<Plan*>(plan);
+  const size_t N = (size_t)p.g.nx * p.g.ny * p.g.nz;
+  const size_t M = (size_t)p.g.nview * p.g.nz * p.g.nx;
+  float* ybar = reinterpret_cast<float*>(p.ws + p.lay.em_proj);
+  float* e = reinterpret_cast<float*>(p.ws + p.lay.em_vol);
+  spect_status st = forward_impl(p, d_x, ybar, stream);
+  if (st != SPECT_OK) return st;
+  if (launch_em_ratio(ybar, d_y, d_r, ybar, M, stream) != hipSuccess) return SPECT_ERR_HIP;
+  st = back_impl(p, ybar, e, stream);
+  if (st != SPECT_OK) return st;
+  if (launch_em_update(d_x, e, d_sens, N, stream) != hipSuccess) return SPECT_ERR_HIP;
+  return SPECT_OK;
+}
+
+spect_status spect_dot_f64(const float* d_a, const float* d_b, size_t n, double* d_out,
+                           hipStream_t stream) {
+  if (!d_a || !d_b || !d_out) return SPECT_ERR_NULL;
+  if (!aligned(d_a, 4) || !aligned(d_b, 4) || !aligned(d_out, 8)) return SPECT_ERR_ALIGN;
+  return launch_dot_f64(d_a, d_b, n, d_out, stream) == hipSuccess ? SPECT_OK : SPECT_ERR_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,244 @@
+"""ctypes binding of libspect (include/spect.h).
+
+Argument marshalling only: every step of the projector runs in the HIP
+kernels of libspect.so.  PyTorch supplies device memory and the stream.
+The functions ``spect_*`` mirror the C ABI one to one (raw device pointers
+as ints); ``Plan`` wraps them for torch tensors.
+
+If libspect.so is missing this module raises at first use: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int, c_int32, c_size_t, c_uint32, c_void_p
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspect.so")
+
+SPECT_OK = 0
+SPECT_CACHE_MUBAR = 0x1
+STATUS_NAMES = {
+    0: "SPECT_OK", 1: "SPECT_ERR_NULL", 2: "SPECT_ERR_SHAPE", 3: "SPECT_ERR_VALUE",
+    4: "SPECT_ERR_WORKSPACE", 5: "SPECT_ERR_UNSUPPORTED", 6: "SPECT_ERR_HIP", 7: "SPECT_ERR_ALIGN",
+}
+EXPORTED = ("spect_workspace_bytes", "spect_plan_create", "spect_forward", "spect_back",
+            "spect_em_step", "spect_plan_destroy", "spect_status_string", "spect_dot_f64",
+            "spect_version")
+
+
+class SpectError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)} "
+                         f"({_lib().spect_status_string(status).decode()})")
+
+
+class spect_geom(ctypes.Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32), ("nview", c_int32),
+                ("px", c_int32), ("pz", c_int32), ("dy", c_double),
+                ("angles", POINTER(c_double)), ("flags", c_uint32), ("view_batch", c_int32)]
+
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2301_09710_amd.build`"
+                               " (there is no CPU fallback)")
+        lib = ctypes.CDLL(LIB_PATH)
+        lib.spect_workspace_bytes.argtypes = [POINTER(spect_geom), POINTER(c_size_t)]
+        lib.spect_plan_create.argtypes = [POINTER(c_void_p), POINTER(spect_geom), c_void_p, c_void_p,
+                                          c_void_p, c_size_t, c_void_p]
+        lib.spect_forward.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
+        lib.spect_back.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
+        lib.spect_em_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+        lib.spect_plan_destroy.argtypes = [c_void_p]
+        lib.spect_dot_f64.argtypes = [c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]
+        for name in ("spect_workspace_bytes", "spect_plan_create", "spect_forward", "spect_back",
+                     "spect_em_step", "spect_plan_destroy", "spect_dot_f64"):
+            getattr(lib, name).restype = c_int
+        lib.spect_status_string.argtypes = [c_int]
+        lib.spect_status_string.restype = c_char_p
+        lib.spect_version.argtypes = []
+        lib.spect_version.restype = c_char_p
+        _LIB = lib
+    return _LIB
+
+
+def load():
+    """Load libspect.so (raises if it is not built)."""
+    return _lib()
+
+
+def make_geom(nx, ny, nz, nview, px, pz, dy, angles=None, flags=0, view_batch=0):
+    """Build a spect_geom; returns (geom, keepalive) -- keep the second item
+    alive while the geom is in use (it owns the angles array)."""
+    g = spect_geom(nx, ny, nz, nview, px, pz, float(dy), None, flags, view_batch)
+    keep = None
+    if angles is not None:
+        keep = (c_double * nview)(*[float(a) for a in angles])
+        g.angles = ctypes.cast(keep, POINTER(c_double))
+    return g, keep
+
+
+# ---------------------------------------------------------------- raw C ABI
+
+def spect_workspace_bytes(geom: spect_geom) -> int:
+    out = c_size_t(0)
+    st = _lib().spect_workspace_bytes(ctypes.byref(geom), ctypes.byref(out))
+    if st != SPECT_OK:
+        raise SpectError(st, "spect_workspace_bytes")
+    return out.value
+
+
+def spect_plan_create(geom, d_mu: int, d_psf: int, d_ws: int, ws_bytes: int, stream: int) -> int:
+    plan = c_void_p(0)
+    st = _lib().spect_plan_create(ctypes.byref(plan), ctypes.byref(geom), d_mu, d_psf, d_ws,
+                                  ws_bytes, stream)
+    if st != SPECT_OK:
+        raise SpectError(st, "spect_plan_create")
+    return plan.value
+
+
+def spect_forward(plan: int, d_x: int, d_v: int, stream: int) -> None:
+    st = _lib().spect_forward(plan, d_x, d_v, stream)
+    if st != SPECT_OK:
+        raise SpectError(st, "spect_forward")
+
+
+def spect_back(plan: int, d_v: int, d_x: int, stream: int) -> None:
+    st = _lib().spect_back(plan, d_v, d_x, stream)
+    if st != SPECT_OK:
+        raise SpectError(st, "spect_back")
+
+
+def spect_em_step(plan: int, d_x: int, d_y: int, d_r, d_sens: int, stream: int) -> None:
+    st = _lib().spect_em_step(plan, d_x, d_y, d_r, d_sens, stream)
+    if st != SPECT_OK:
+        raise SpectError(st, "spect_em_step")
+
+
+def spect_plan_destroy(plan: int) -> None:
+    st = _lib().spect_plan_destroy(plan)
+    if st != SPECT_OK:
+        raise SpectError(st, "spect_plan_destroy")
+
+
+def spect_dot_f64(d_a: int, d_b: int, n: int, d_out: int, stream: int) -> None:
+    st = _lib().spect_dot_f64(d_a, d_b, n, d_out, stream)
+    if st != SPECT_OK:
+        raise SpectError(st, "spect_dot_f64")
+
+
+def spect_version() -> str:
+    return _lib().spect_version().decode()
+
+
+# ---------------------------------------------------------------- torch wrapper
+
+def _stream(torch, device):
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _check(t, shape, name, device):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous() or t.device != device:
+        raise ValueError(f"{name} must be contiguous float32 on {device}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+class Plan:
+    """A projector plan over torch tensors (borrowed mu / psf, owned workspace).
+
+    x: [nz][ny][nx], v: [nview][nz][nx], mu: [nz][ny][nx], psf: [nview][ny][pz][px].
+    """
+
+    def __init__(self, mu, psf, dy, angles=None, cache_mubar=False, view_batch=0):
+        import torch
+        self.device = mu.device
+        if self.device.type != "cuda":
+            raise ValueError("mu must live on a GPU")
+        nz, ny, nx = mu.shape
+        nview, ny2, pz, px = psf.shape
+        if ny2 != ny:
+            raise ValueError("psf depth does not match mu")
+        _check(mu, (nz, ny, nx), "mu", self.device)
+        _check(psf, (nview, ny, pz, px), "psf", self.device)
+        self.shape = (nx, ny, nz, nview, px, pz)
+        self.nx, self.ny, self.nz, self.nview, self.px, self.pz = self.shape
+        flags = SPECT_CACHE_MUBAR if cache_mubar else 0
+        self._geom, self._keep = make_geom(nx, ny, nz, nview, px, pz, dy, angles, flags, view_batch)
+        self.ws_bytes = spect_workspace_bytes(self._geom)
+        self._mu, self._psf = mu, psf
+        self._ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self._plan = spect_plan_create(self._geom, mu.data_ptr(), psf.data_ptr(),
+                                       self._ws.data_ptr(), self.ws_bytes,
+                                       _stream(torch, self.device))
+
+    @property
+    def vol_shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    @property
+    def proj_shape(self):
+        return (self.nview, self.nz, self.nx)
+
+    def forward(self, x, out=None):
+        import torch
+        _check(x, self.vol_shape, "x", self.device)
+        if out is None:
+            out = torch.empty(self.proj_shape, dtype=torch.float32, device=self.device)
+        _check(out, self.proj_shape, "out", self.device)
+        spect_forward(self._plan, x.data_ptr(), out.data_ptr(), _stream(torch, self.device))
+        return out
+
+    def back(self, v, out=None):
+        import torch
+        _check(v, self.proj_shape, "v", self.device)
+        if out is None:
+            out = torch.empty(self.vol_shape, dtype=torch.float32, device=self.device)
+        _check(out, self.vol_shape, "out", self.device)
+        spect_back(self._plan, v.data_ptr(), out.data_ptr(), _stream(torch, self.device))
+        return out
+
+    def em_step(self, x, y, sens, r=None):
+        import torch
+        _check(x, self.vol_shape, "x", self.device)
+        _check(y, self.proj_shape, "y", self.device)
+        _check(sens, self.vol_shape, "sens", self.device)
+        if r is not None:
+            _check(r, self.proj_shape, "r", self.device)
+        spect_em_step(self._plan, x.data_ptr(), y.data_ptr(), None if r is None else r.data_ptr(),
+                      sens.data_ptr(), _stream(torch, self.device))
+        return x
+
+    def close(self):
+        if getattr(self, "_plan", None):
+            spect_plan_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dot_f64(a, b) -> float:
+    """FP64 inner product of two float32 device tensors, on the GPU."""
+    import torch
+    if a.numel() != b.numel():
+        raise ValueError("size mismatch")
+    a = a.contiguous()
+    b = b.contiguous()
+    out = torch.empty(1, dtype=torch.float64, device=a.device)
+    spect_dot_f64(a.data_ptr(), b.data_ptr(), a.numel(), out.data_ptr(), _stream(torch, a.device))
+    return float(out.item())

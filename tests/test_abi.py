@@ -1,0 +1,110 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/spect.h declares, and rejects bad arguments synchronously, before
+any HIP call (so these run on a machine without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2301_09710_amd import spect
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "spect.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(spect_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = spect.load()
+    names = declared_functions()
+    assert {"spect_plan_create", "spect_forward", "spect_back", "spect_em_step"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(spect.EXPORTED)
+    assert "gfx950" in spect.spect_version()
+
+
+def test_status_strings():
+    lib = spect.load()
+    for s in range(8):
+        assert lib.spect_status_string(s)
+    assert lib.spect_status_string(0) == b"ok"
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(ny=30), 2),                 # nx != ny
+    (dict(px=6), 2),                  # even PSF
+    (dict(pz=0), 2),
+    (dict(nz=0), 2),
+    (dict(nview=0), 2),
+    (dict(dy=0.0), 3),
+    (dict(dy=float("nan")), 3),
+    (dict(flags=0x10), 3),
+    (dict(view_batch=-1), 3),
+    (dict(nx=200, ny=200), 5),        # slice larger than the LDS rotation path supports
+])
+def test_workspace_bytes_validation(kw, status):
+    args = dict(nx=32, ny=32, nz=20, nview=16, px=7, pz=7, dy=1.0, angles=None, flags=0, view_batch=0)
+    args.update(kw)
+    g, _keep = spect.make_geom(**args)
+    with pytest.raises(spect.SpectError) as e:
+        spect.spect_workspace_bytes(g)
+    assert e.value.status == status
+
+
+def test_nonfinite_angle_rejected():
+    g, _keep = spect.make_geom(8, 8, 6, 3, 3, 3, 1.0, angles=[0.0, float("inf"), 1.0])
+    with pytest.raises(spect.SpectError) as e:
+        spect.spect_workspace_bytes(g)
+    assert e.value.status == 3
+
+
+def test_workspace_grows_with_cache_and_shrinks_with_batch():
+    g0, _ = spect.make_geom(128, 128, 80, 128, 37, 37, 4.8)
+    g1, _ = spect.make_geom(128, 128, 80, 128, 37, 37, 4.8, flags=spect.SPECT_CACHE_MUBAR)
+    g2, _ = spect.make_geom(128, 128, 80, 128, 37, 37, 4.8, view_batch=16)
+    b0, b1, b2 = (spect.spect_workspace_bytes(g) for g in (g0, g1, g2))
+    N = 128 * 128 * 80 * 4
+    assert b1 - b0 >= 128 * N
+    assert b2 < b0 - 100 * N
+    assert b0 % 256 == 0
+
+
+def test_plan_create_rejects_before_any_gpu_call():
+    lib = spect.load()
+    g, _ = spect.make_geom(32, 32, 20, 16, 7, 7, 1.0)
+    need = spect.spect_workspace_bytes(g)
+    fake = 1 << 40                      # never dereferenced: validation fails first
+    plan = ctypes.c_void_p(0)
+    # null pointers
+    assert lib.spect_plan_create(ctypes.byref(plan), ctypes.byref(g), None, fake, fake, need, None) == 1
+    assert lib.spect_plan_create(None, ctypes.byref(g), fake, fake, fake, need, None) == 1
+    # workspace too small
+    assert lib.spect_plan_create(ctypes.byref(plan), ctypes.byref(g), fake, fake, fake,
+                                 need - 1, None) == 4
+    # misaligned workspace / mu
+    assert lib.spect_plan_create(ctypes.byref(plan), ctypes.byref(g), fake, fake, fake + 16,
+                                 need, None) == 7
+    assert lib.spect_plan_create(ctypes.byref(plan), ctypes.byref(g), fake + 2, fake, fake,
+                                 need, None) == 7
+    # bad geometry
+    gb, _ = spect.make_geom(32, 32, 20, 16, 8, 7, 1.0)
+    assert lib.spect_plan_create(ctypes.byref(plan), ctypes.byref(gb), fake, fake, fake,
+                                 need, None) == 2
+    assert plan.value is None
+
+
+def test_entry_points_reject_null():
+    lib = spect.load()
+    fake = 1 << 40
+    assert lib.spect_forward(None, fake, fake, None) == 1
+    assert lib.spect_back(None, fake, fake, None) == 1
+    assert lib.spect_em_step(None, fake, fake, None, fake, None) == 1
+    assert lib.spect_plan_destroy(None) == 1
+    assert lib.spect_dot_f64(None, fake, 4, fake, None) == 1
+    assert lib.spect_dot_f64(fake, fake, 4, fake + 4, None) == 7
