@@ -1,0 +1,238 @@
+#!/usr/bin/env python3
+"""Projector-pair benchmark on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+A step is one forward projection plus one back projection (a "pair") of the
+paper-scale workload: 128x128x80 volume at 4.8 mm, 128 views over 360
+degrees, 37x37 depth/view-dependent Gaussian PSFs (sigma 1 -> 6 voxels), an
+ellipsoidal body phantom with hot lesions and a tissue/lung/bone attenuation
+map (synthetic, seeded).  Inputs are resident in HBM before the timed
+region.  Prints ONE JSON line with pairs/s, the per-pair latency
+distribution, EM reconstruction latency, the roofline of the dominant kernel
+(timed live with HIP events on the launch stream) and the FP64 oracle timed
+on the host cores on a bounded sample of views.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_PEAK_TFLOPS = 157.3          # MI355X published FP32 (vector and matrix)
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cache-mubar", type=int, default=1,
+                    help="1: keep the Eq. (1) attenuation factor of all views in HBM (plan flag)")
+    ap.add_argument("--em-recons", type=int, default=5, help="EM reconstructions timed for latency")
+    ap.add_argument("--em-iters", type=int, default=8, help="EM iterations per reconstruction")
+    ap.add_argument("--cpu-views", type=int, default=24,
+                    help="views in the bounded oracle sample (0 disables the CPU baseline)")
+    ap.add_argument("--seed", type=int, default=0)
+    return ap.parse_args()
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q / 100.0
+    lo = int(k)
+    hi = min(lo + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def source_sha(path):
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+
+
+def traffic_for(kernel, launches_flops):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE / WRITE_SIZE scaled by a copy-kernel calibration),
+    or None if absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(kernel)
+        if not rec:
+            return None
+        src = os.path.join(ROOT, rec["source"])
+        if source_sha(src) != rec["source_sha256"]:
+            return None
+        return rec["hbm_bytes_per_launch"]
+    except Exception:
+        return None
+
+
+def cpu_baseline(x, mu, psf, dy, nviews_sample, seed):
+    """The FP64 oracle as it stands (FFT convolution path), forward + back of
+    `nviews_sample` views, scaled to whole pairs."""
+    import numpy as np
+    import oracle
+    from oracle import convolution
+    from oracle.projector import Geometry
+
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except Exception:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    convolution.FFT_WORKERS = cores
+    nz, ny, nx = x.shape
+    nview, _, pz, px = psf.shape
+    g = Geometry(nx, ny, nz, nview, px, pz, dy)
+    step = max(1, nview // nviews_sample)
+    views = list(range(0, nview, step))[:nviews_sample]
+    y = np.random.default_rng(seed + 7).uniform(0.5, 1.5, size=(nview, nz, nx))
+    t0 = time.perf_counter()
+    oracle.forward(x, mu, psf, g, views=views, conv="fft")
+    oracle.back(y, mu, psf, g, views=views, conv="fft")
+    dt = time.perf_counter() - t0
+    sec_per_pair = dt * nview / len(views)
+    return {"value": 1.0 / sec_per_pair, "unit": "pairs/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 oracle (numpy + scipy.fft, FFT convolution) forward+back of "
+                      f"{len(views)} of {nview} views at {nx}x{ny}x{nz}, {px}x{pz} PSF, "
+                      f"{dt:.1f} s, scaled to a full pair",
+            "seconds_per_pair": sec_per_pair}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this projector build runs on one GPU only (no multi-GPU path); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2301_09710_amd import spect, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    spect.load()
+
+    cfg = synth.CONFIGS["paper"]
+    x, mu, psf, dy = synth.config_inputs("paper", seed=args.seed)
+    nx, ny, nz, nview, px, pz = cfg["nx"], cfg["ny"], cfg["nz"], cfg["nview"], cfg["px"], cfg["pz"]
+    xd = torch.from_numpy(x).to(dev)
+    mud = torch.from_numpy(mu).to(dev)
+    psfd = torch.from_numpy(psf).to(dev)
+    plan = spect.Plan(mud, psfd, dy, cache_mubar=bool(args.cache_mubar))
+    vd = torch.empty(plan.proj_shape, dtype=torch.float32, device=dev)
+    bd = torch.empty(plan.vol_shape, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+
+    def pair():
+        plan.forward(xd, out=vd)
+        plan.back(vd, out=bd)
+
+    for _ in range(args.warmup):
+        pair()
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    plan.profile_start(max_launches=64 * K + 64)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    for s in range(K):
+        ev[s][0].record()
+        pair()
+        ev[s][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    kern = plan.profile_stop()
+    step_ms = [a.elapsed_time(b) for a, b in ev]
+    total_ms = ev[0][0].elapsed_time(ev[-1][1])
+    ms_per_step = total_ms / K
+    value = 1000.0 / ms_per_step
+
+    # dominant kernel and its roofline (algorithmic FLOPs per launch / average duration)
+    N = nx * ny * nz
+    views_per_launch = plan.nview  # one launch covers all views (view_batch = all)
+    conv_flops = 2.0 * px * pz * N * views_per_launch
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    avg_ms = {k: v["total_ms"] / v["launches"] for k, v in kern.items()}
+    if dom in ("conv_fwd", "conv_back"):
+        achieved = conv_flops / (avg_ms[dom] * 1e-3) / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+                "traffic": traffic_for(dom, conv_flops),
+                "algorithmic_per_launch": conv_flops, "avg_launch_ms": avg_ms[dom]}
+    else:
+        byts = 3.0 * 4 * N * views_per_launch
+        achieved = byts / (avg_ms[dom] * 1e-3) / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(dom, byts),
+                "algorithmic_per_launch": byts, "avg_launch_ms": avg_ms[dom]}
+
+    # EM reconstruction latency (not part of `value`)
+    em = None
+    if args.em_recons > 0:
+        ones = torch.ones(plan.proj_shape, dtype=torch.float32, device=dev)
+        sens = plan.back(ones)
+        yd = torch.poisson(vd * 1.0)
+        rd = torch.full_like(yd, 0.05 * float(yd.mean()))
+        lat = []
+        for _ in range(args.em_recons):
+            xe = torch.ones(plan.vol_shape, dtype=torch.float32, device=dev)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(args.em_iters):
+                plan.em_step(xe, yd, sens, rd)
+            b.record()
+            torch.cuda.synchronize()
+            lat.append(a.elapsed_time(b))
+        em = {"iters": args.em_iters, "recons": args.em_recons, "p50_ms": pct(lat, 50),
+              "p99_ms": pct(lat, 99)}
+
+    cpu = None
+    if args.cpu_views > 0:
+        cpu = cpu_baseline(x, mu, psf, dy, args.cpu_views, args.seed)
+
+    out = {
+        "metric": "fwd+back projector pairs/s at 128x128x80, 128 views; p50/p99 recon latency",
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "paper-scale FP32 projector pair: 128x128x80 volume (4.8 mm), "
+                               "128 views over 360 deg, 37x37 depth/view-dependent Gaussian PSF",
+                   "nx": nx, "ny": ny, "nz": nz, "nview": nview, "px": px, "pz": pz,
+                   "cache_mubar": bool(args.cache_mubar)},
+        "pair_latency_ms": {"p50": pct(step_ms, 50), "p99": pct(step_ms, 99),
+                            "p10": pct(step_ms, 10), "p90": pct(step_ms, 90)},
+        "wall_s_timed": wall,
+        "em_recon_latency": em,
+        "kernels_ms_per_launch": avg_ms,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -125,6 +125,25 @@ const char* spect_status_string(spect_status s);
 spect_status spect_dot_f64(const float* d_a, const float* d_b, size_t n,
                            double* d_out, hipStream_t stream);
 
+/* Per-kernel timing of one plan, for benchmarks.  spect_profile_start creates
+ * a pool of 2*max_launches HIP events (host-side runtime objects, no device
+ * memory); while it is active every kernel the plan launches is bracketed by
+ * an event pair recorded on the caller's stream (launches beyond the pool are
+ * not timed).  spect_profile_stop waits for the recorded events, writes one
+ * entry per kernel name (at most max_out) to `out`, sets *n_out, releases the
+ * pool and ends profiling.  Not for use while another call on the plan is
+ * being enqueued from a different host thread. */
+typedef struct {
+  char name[32];          /* kernel name, e.g. "conv_fwd" */
+  int32_t launches;       /* timed launches */
+  double total_ms;        /* sum of the launch durations */
+  double min_ms, max_ms;  /* shortest and longest launch */
+} spect_kernel_time;
+
+spect_status spect_profile_start(spect_plan plan, int32_t max_launches);
+spect_status spect_profile_stop(spect_plan plan, spect_kernel_time* out, int32_t max_out,
+                                int32_t* n_out);
+
 /* Library version string. */
 const char* spect_version(void);
 

@@ -24,6 +24,9 @@ from __future__ import annotations
 import numpy as np
 import scipy.fft
 
+# Threads scipy.fft may use in the FFT form (None -> scipy's default of 1).
+FFT_WORKERS = None
+
 
 def _clamp_index(n: int, h: int, taps: int):
     """idx[t, o] = clamp(o - t + h, 0, n-1): source of output o for tap t."""
@@ -80,12 +83,13 @@ def _fft_shape(nx, nz, px, pz):
             scipy.fft.next_fast_len(nz + 2 * ((pz - 1) // 2) + pz - 1, real=True))
 
 
-def conv_sum_fft(w: np.ndarray, p: np.ndarray, workers=-1) -> np.ndarray:
+def conv_sum_fft(w: np.ndarray, p: np.ndarray, workers=None) -> np.ndarray:
     """sum_j conv_planes(w, p)[:, j, :] via FFT, summing depths in the
     frequency domain (edge-padded linear convolution, then crop).
 
     Padded w: W[q] = w[clamp(q - ha)], q in [0, nx + 2 ha).  The linear
     convolution full[s] = sum_a p[a] W[s - a] equals c[i] at s = i + 2 ha."""
+    workers = FFT_WORKERS if workers is None else workers
     w = np.asarray(w, dtype=np.float64)
     p = np.asarray(p, dtype=np.float64)
     nx, ny, nz = w.shape
@@ -99,7 +103,7 @@ def conv_sum_fft(w: np.ndarray, p: np.ndarray, workers=-1) -> np.ndarray:
     return full[2 * ha: 2 * ha + nx, 2 * hb: 2 * hb + nz]
 
 
-def conv_planes_T_fft(g2: np.ndarray, p: np.ndarray, workers=-1) -> np.ndarray:
+def conv_planes_T_fft(g2: np.ndarray, p: np.ndarray, workers=None) -> np.ndarray:
     """Transpose of conv_sum_fft applied to a projection g2[i, k]: returns
     u[i, j, k] = (conv_planes^T of g broadcast to every j).
 
@@ -107,6 +111,7 @@ def conv_planes_T_fft(g2: np.ndarray, p: np.ndarray, workers=-1) -> np.ndarray:
     correlation U[q] = sum_i g[i] p[i + 2 ha - q] = (g * flip(p))[q]; the
     adjoint of the edge padding then folds the border rows/columns of U onto
     the edge rows/columns."""
+    workers = FFT_WORKERS if workers is None else workers
     g2 = np.asarray(g2, dtype=np.float64)
     p = np.asarray(p, dtype=np.float64)
     nx, nz = g2.shape

@@ -15,10 +15,32 @@ namespace spect {
 constexpr int kMaxLdsN = 140;
 // Threads per workgroup of the rotation kernels.
 constexpr int kRotThreads = 1024;
-// Depth planes per partial sum of the forward convolution.
-constexpr int kFwdJChunk = 8;
+// Depth planes per workgroup (one partial sum each) of the forward convolution.
+constexpr int kFwdJChunk = 16;
+// Depth planes per workgroup of the adjoint convolution.
+constexpr int kBackJChunk = 16;
 // View groups (partial volumes) of the back rotation.
 constexpr int kBackGroups = 16;
+// Views a rotation workgroup processes for its slice.
+constexpr int kRotViewsPerGroup = 8;
+// Largest number of 4-deep k-steps of the MFMA convolution (pz <= 65).
+constexpr int kMaxMfmaKSteps = 20;
+// LDS of one gfx950 compute unit.
+constexpr size_t kLdsBytes = 163840;
+
+// Tiling of the MFMA convolution (see conv_mfma.hip).
+struct ConvShape {
+  int nx, ny, nz, px, pz, ha, hb;
+  int KS;               // k-steps per 16-row M-block: ceil((15 + pz) / 4)
+  int WK, WI;           // waves of a workgroup along k and along i (WK * WI = 4)
+  int tiles_k, tiles_i; // workgroup tiles of 16 WK x 32 WI output bins
+  int RK, RI;           // staged region rows (k) and columns (i)
+  int RSI, RSI_back;    // LDS row strides (forward, adjoint)
+  int PL, Z;            // PSF row length in LDS and its zero offset (forward)
+  int jc, nchunk;       // forward depth chunk
+  int jc_back, nchunk_back;
+  long long nview_ny_pz_px;  // size of one PSF array (offset of the prefix sums)
+};
 
 // Per-view geometry tables, on the device (inside the workspace).
 //   quarter[l]             : m, number of quarter turns (0..3)
@@ -39,9 +61,24 @@ struct Layout {
   size_t fwd_partial;   // nchunk * view_batch * nz * nx floats
   size_t back_partial;  // kBackGroups * N floats
   size_t mubar_cache;   // nview * N floats (only with SPECT_CACHE_MUBAR)
+  size_t mubar_batch;   // view_batch * N floats (only without SPECT_CACHE_MUBAR)
+  size_t psf_cum;       // 2 * nview * ny * pz * px floats: suffix, prefix sums along b
   size_t em_proj;       // nview * nz * nx floats
   size_t em_vol;        // N floats
   size_t total;
+};
+
+// Kernel identities for the optional per-launch timing.
+enum KernelId {
+  K_MUBAR = 0, K_ROT_FWD, K_CONV_FWD, K_FWD_REDUCE, K_CONV_BACK, K_ROT_BACK,
+  K_BACK_REDUCE, K_EM_RATIO, K_EM_UPDATE, K_COUNT
+};
+extern const char* const kKernelNames[K_COUNT];
+
+struct Profiler {
+  int cap = 0, used = 0;
+  hipEvent_t* ev = nullptr;   // 2 * cap events
+  int* kid = nullptr;         // cap kernel ids
 };
 
 struct Plan {
@@ -54,26 +91,56 @@ struct Plan {
   Layout lay;
   Tables tab;
   const float* mubar;   // cache or nullptr
+  float* mubar_batch;   // per-batch attenuation factors when not cached
+  const float* psf_cum; // suffix / prefix sums of the PSF along b
+  bool use_mfma;        // MFMA convolution path (else the direct kernels)
+  ConvShape conv;
+  Profiler* prof;       // non-null while spect_profile_start is active
   // host copies of the tables (kept alive for the asynchronous upload)
   int32_t* h_quarter;
   int32_t* h_off;
   float2* h_w;
 };
 
+// Run `launch` (which enqueues one kernel on s), bracketed by profiling
+// events when the plan's profiler is active.
+template <class F>
+hipError_t timed(const Plan& p, KernelId id, hipStream_t s, F&& launch) {
+  Profiler* pr = p.prof;
+  const bool rec = pr && pr->used < pr->cap;
+  if (rec && hipEventRecord(pr->ev[2 * pr->used], s) != hipSuccess) return hipErrorUnknown;
+  hipError_t e = launch();
+  if (rec && e == hipSuccess) {
+    if (hipEventRecord(pr->ev[2 * pr->used + 1], s) != hipSuccess) return hipErrorUnknown;
+    pr->kid[pr->used++] = id;
+  }
+  return e;
+}
+
 spect_status compute_layout(const spect_geom& g, Layout* lay, int* view_batch, int* nchunk);
 
+bool conv_mfma_supported(const spect_geom& g);
+ConvShape make_conv_shape(const spect_geom& g, int jc_fwd, int jc_back);
+size_t conv_mfma_lds_bytes(const ConvShape& cs, bool back);
+
 // ---- kernel launchers (return hipGetLastError() of the launch) ----
-hipError_t launch_mubar_cache(const Plan& p, float* out, hipStream_t s);
-hipError_t launch_rot_fwd(const Plan& p, const float* x, float* W, int view0, int nvb,
-                          hipStream_t s);
+hipError_t launch_mubar(const Plan& p, float* out, int view0, int nviews, int out_view0,
+                        hipStream_t s);
+hipError_t launch_psf_cum(const Plan& p, float* out, hipStream_t s);
+hipError_t launch_rot_fwd(const Plan& p, const float* x, const float* mb, int mb_off, float* W,
+                          int view0, int nvb, hipStream_t s);
+hipError_t launch_conv_fwd_mfma(const Plan& p, const float* W, float* partial, int view0, int nvb,
+                                hipStream_t s);
+hipError_t launch_conv_back_mfma(const Plan& p, const float* v, float* U, int view0, int nvb,
+                                 hipStream_t s);
 hipError_t launch_conv_fwd(const Plan& p, const float* W, float* partial, int view0, int nvb,
                            hipStream_t s);
 hipError_t launch_fwd_reduce(const Plan& p, const float* partial, float* v, int view0, int nvb,
                              hipStream_t s);
 hipError_t launch_conv_back(const Plan& p, const float* v, float* U, int view0, int nvb,
                             hipStream_t s);
-hipError_t launch_rot_back(const Plan& p, const float* U, float* partial, int view0, int nvb,
-                           bool accumulate, hipStream_t s);
+hipError_t launch_rot_back(const Plan& p, const float* U, const float* mb, int mb_off,
+                           float* partial, int view0, int nvb, bool accumulate, hipStream_t s);
 hipError_t launch_back_reduce(const Plan& p, const float* partial, float* x, hipStream_t s);
 hipError_t launch_em_ratio(const float* v, const float* y, const float* r, float* rho, size_t m,
                            hipStream_t s);

@@ -37,7 +37,7 @@ spect_status compute_layout(const spect_geom& g, Layout* lay, int* view_batch, i
   const size_t N = n * g.ny * g.nz;
   const size_t M = (size_t)g.nview * g.nz * g.nx;
   const int vb = (g.view_batch > 0 && g.view_batch < g.nview) ? g.view_batch : g.nview;
-  const int nc = (g.ny + kFwdJChunk - 1) / kFwdJChunk;
+  const int nc = (g.ny + kFwdJChunk - 1) / kFwdJChunk;   // same chunking for both conv paths
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t at = off; off += align256(bytes); return at; };
   lay->tables_quarter = take((size_t)g.nview * sizeof(int32_t));
@@ -46,7 +46,10 @@ spect_status compute_layout(const spect_geom& g, Layout* lay, int* view_batch, i
   lay->vol_batch = take((size_t)vb * N * sizeof(float));
   lay->fwd_partial = take((size_t)nc * vb * g.nz * g.nx * sizeof(float));
   lay->back_partial = take((size_t)kBackGroups * N * sizeof(float));
-  lay->mubar_cache = (g.flags & SPECT_CACHE_MUBAR) ? take((size_t)g.nview * N * sizeof(float)) : 0;
+  const bool cache = (g.flags & SPECT_CACHE_MUBAR) != 0;
+  lay->mubar_cache = cache ? take((size_t)g.nview * N * sizeof(float)) : 0;
+  lay->mubar_batch = cache ? 0 : take((size_t)vb * N * sizeof(float));
+  lay->psf_cum = take((size_t)2 * g.nview * g.ny * g.pz * g.px * sizeof(float));
   lay->em_proj = take(M * sizeof(float));
   lay->em_vol = take(N * sizeof(float));
   lay->total = off;
@@ -92,6 +95,22 @@ static void fill_tables(const spect_geom& g, int32_t* q, int32_t* off, float2* w
   }
 }
 
+}  // namespace spect
+
+namespace spect {
+const char* const kKernelNames[K_COUNT] = {"mubar", "rot_fwd",  "conv_fwd",
+                                           "fwd_reduce",  "conv_back", "rot_back",
+                                           "back_reduce", "em_ratio", "em_update"};
+
+static void profiler_free(Profiler* pr) {
+  if (!pr) return;
+  if (pr->ev)
+    for (int i = 0; i < 2 * pr->cap; ++i)
+      if (pr->ev[i]) (void)hipEventDestroy(pr->ev[i]);
+  std::free(pr->ev);
+  std::free(pr->kid);
+  delete pr;
+}
 }  // namespace spect
 
 using namespace spect;
@@ -169,10 +188,20 @@ spect_status spect_plan_create(spect_plan* out, const spect_geom* g, const float
     e = hipMemcpyAsync(p->ws + lay.tables_w, p->h_w, g->nview * 2 * n * sizeof(float2),
                        hipMemcpyHostToDevice, stream);
   p->mubar = nullptr;
-  if (e == hipSuccess && (g->flags & SPECT_CACHE_MUBAR)) {
+  p->mubar_batch = nullptr;
+  p->use_mfma = conv_mfma_supported(*g);
+  p->conv = make_conv_shape(*g, kFwdJChunk, kBackJChunk);
+  float* cum = reinterpret_cast<float*>(p->ws + lay.psf_cum);
+  p->psf_cum = cum;
+  if (e == hipSuccess) e = timed(*p, K_MUBAR, stream, [&] { return launch_psf_cum(*p, cum, stream); });
+  if (g->flags & SPECT_CACHE_MUBAR) {
     float* cache = reinterpret_cast<float*>(p->ws + lay.mubar_cache);
-    e = launch_mubar_cache(*p, cache, stream);
+    if (e == hipSuccess)
+      e = timed(*p, K_MUBAR, stream,
+                [&] { return launch_mubar(*p, cache, 0, g->nview, 0, stream); });
     p->mubar = cache;
+  } else {
+    p->mubar_batch = reinterpret_cast<float*>(p->ws + lay.mubar_batch);
   }
   if (e != hipSuccess) {
     // make sure no queued copy still reads the host tables before freeing them
@@ -187,6 +216,7 @@ spect_status spect_plan_create(spect_plan* out, const spect_geom* g, const float
 spect_status spect_plan_destroy(spect_plan plan) {
   if (!plan) return SPECT_ERR_NULL;
   Plan* p = reinterpret_cast<Plan*>(plan);
+  profiler_free(p->prof);
   std::free(p->h_quarter);
   std::free(p->h_off);
   std::free(p->h_w);
@@ -194,14 +224,40 @@ spect_status spect_plan_destroy(spect_plan plan) {
   return SPECT_OK;
 }
 
+// Attenuation factors of views [v0, v0 + nvb): the cache (computed at plan
+// creation) or the batch buffer, filled here.  Returns the base pointer and
+// the view offset to add to a batch-relative view index.
+static hipError_t mubar_for_batch(const Plan& p, int v0, int nvb, hipStream_t s,
+                                  const float** mb, int* off) {
+  if (p.mubar) {
+    *mb = p.mubar;
+    *off = v0;
+    return hipSuccess;
+  }
+  *mb = p.mubar_batch;
+  *off = 0;
+  return timed(p, K_MUBAR, s, [&] { return launch_mubar(p, p.mubar_batch, v0, nvb, v0, s); });
+}
+
 static spect_status forward_impl(const Plan& p, const float* x, float* v, hipStream_t s) {
   float* W = reinterpret_cast<float*>(p.ws + p.lay.vol_batch);
   float* part = reinterpret_cast<float*>(p.ws + p.lay.fwd_partial);
   for (int v0 = 0; v0 < p.g.nview; v0 += p.view_batch) {
     const int nvb = (p.g.nview - v0 < p.view_batch) ? p.g.nview - v0 : p.view_batch;
-    if (launch_rot_fwd(p, x, W, v0, nvb, s) != hipSuccess) return SPECT_ERR_HIP;
-    if (launch_conv_fwd(p, W, part, v0, nvb, s) != hipSuccess) return SPECT_ERR_HIP;
-    if (launch_fwd_reduce(p, part, v, v0, nvb, s) != hipSuccess) return SPECT_ERR_HIP;
+    const float* mb;
+    int mb_off;
+    if (mubar_for_batch(p, v0, nvb, s, &mb, &mb_off) != hipSuccess) return SPECT_ERR_HIP;
+    if (timed(p, K_ROT_FWD, s, [&] { return launch_rot_fwd(p, x, mb, mb_off, W, v0, nvb, s); }) !=
+        hipSuccess)
+      return SPECT_ERR_HIP;
+    if (timed(p, K_CONV_FWD, s, [&] {
+          return p.use_mfma ? launch_conv_fwd_mfma(p, W, part, v0, nvb, s)
+                            : launch_conv_fwd(p, W, part, v0, nvb, s);
+        }) != hipSuccess)
+      return SPECT_ERR_HIP;
+    if (timed(p, K_FWD_REDUCE, s, [&] { return launch_fwd_reduce(p, part, v, v0, nvb, s); }) !=
+        hipSuccess)
+      return SPECT_ERR_HIP;
   }
   return SPECT_OK;
 }
@@ -211,10 +267,21 @@ static spect_status back_impl(const Plan& p, const float* v, float* x, hipStream
   float* part = reinterpret_cast<float*>(p.ws + p.lay.back_partial);
   for (int v0 = 0; v0 < p.g.nview; v0 += p.view_batch) {
     const int nvb = (p.g.nview - v0 < p.view_batch) ? p.g.nview - v0 : p.view_batch;
-    if (launch_conv_back(p, v, U, v0, nvb, s) != hipSuccess) return SPECT_ERR_HIP;
-    if (launch_rot_back(p, U, part, v0, nvb, v0 > 0, s) != hipSuccess) return SPECT_ERR_HIP;
+    if (timed(p, K_CONV_BACK, s, [&] {
+          return p.use_mfma ? launch_conv_back_mfma(p, v, U, v0, nvb, s)
+                            : launch_conv_back(p, v, U, v0, nvb, s);
+        }) != hipSuccess)
+      return SPECT_ERR_HIP;
+    const float* mb;
+    int mb_off;
+    if (mubar_for_batch(p, v0, nvb, s, &mb, &mb_off) != hipSuccess) return SPECT_ERR_HIP;
+    if (timed(p, K_ROT_BACK, s, [&] {
+          return launch_rot_back(p, U, mb, mb_off, part, v0, nvb, v0 > 0, s);
+        }) != hipSuccess)
+      return SPECT_ERR_HIP;
   }
-  if (launch_back_reduce(p, part, x, s) != hipSuccess) return SPECT_ERR_HIP;
+  if (timed(p, K_BACK_REDUCE, s, [&] { return launch_back_reduce(p, part, x, s); }) != hipSuccess)
+    return SPECT_ERR_HIP;
   return SPECT_OK;
 }
 
@@ -242,11 +309,78 @@ spect_status spect_em_step(spect_plan plan, float* d_x, const float* d_y, const 
   float* e = reinterpret_cast<float*>(p.ws + p.lay.em_vol);
   spect_status st = forward_impl(p, d_x, ybar, stream);
   if (st != SPECT_OK) return st;
-  if (launch_em_ratio(ybar, d_y, d_r, ybar, M, stream) != hipSuccess) return SPECT_ERR_HIP;
+  if (timed(p, K_EM_RATIO, stream, [&] { return launch_em_ratio(ybar, d_y, d_r, ybar, M, stream); }) !=
+      hipSuccess)
+    return SPECT_ERR_HIP;
   st = back_impl(p, ybar, e, stream);
   if (st != SPECT_OK) return st;
-  if (launch_em_update(d_x, e, d_sens, N, stream) != hipSuccess) return SPECT_ERR_HIP;
+  if (timed(p, K_EM_UPDATE, stream, [&] { return launch_em_update(d_x, e, d_sens, N, stream); }) !=
+      hipSuccess)
+    return SPECT_ERR_HIP;
   return SPECT_OK;
+}
+
+spect_status spect_profile_start(spect_plan plan, int32_t max_launches) {
+  if (!plan) return SPECT_ERR_NULL;
+  if (max_launches < 1 || max_launches > (1 << 20)) return SPECT_ERR_VALUE;
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  profiler_free(p->prof);
+  p->prof = nullptr;
+  Profiler* pr = new (std::nothrow) Profiler();
+  if (!pr) return SPECT_ERR_HIP;
+  pr->cap = max_launches;
+  pr->ev = static_cast<hipEvent_t*>(std::calloc(2 * (size_t)max_launches, sizeof(hipEvent_t)));
+  pr->kid = static_cast<int*>(std::calloc((size_t)max_launches, sizeof(int)));
+  if (!pr->ev || !pr->kid) {
+    profiler_free(pr);
+    return SPECT_ERR_HIP;
+  }
+  for (int i = 0; i < 2 * max_launches; ++i)
+    if (hipEventCreate(&pr->ev[i]) != hipSuccess) {
+      profiler_free(pr);
+      return SPECT_ERR_HIP;
+    }
+  p->prof = pr;
+  return SPECT_OK;
+}
+
+spect_status spect_profile_stop(spect_plan plan, spect_kernel_time* out, int32_t max_out,
+                                int32_t* n_out) {
+  if (!plan || !n_out || (max_out > 0 && !out)) return SPECT_ERR_NULL;
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  Profiler* pr = p->prof;
+  *n_out = 0;
+  if (!pr) return SPECT_OK;
+  p->prof = nullptr;
+  spect_kernel_time acc[K_COUNT];
+  std::memset(acc, 0, sizeof(acc));
+  spect_status st = SPECT_OK;
+  for (int r = 0; r < pr->used; ++r) {
+    if (hipEventSynchronize(pr->ev[2 * r + 1]) != hipSuccess) { st = SPECT_ERR_HIP; break; }
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, pr->ev[2 * r], pr->ev[2 * r + 1]) != hipSuccess) {
+      st = SPECT_ERR_HIP;
+      break;
+    }
+    spect_kernel_time& a = acc[pr->kid[r]];
+    if (a.launches == 0 || ms < a.min_ms) a.min_ms = ms;
+    if (a.launches == 0 || ms > a.max_ms) a.max_ms = ms;
+    a.launches += 1;
+    a.total_ms += ms;
+  }
+  int n = 0;
+  for (int k = 0; k < K_COUNT && st == SPECT_OK; ++k) {
+    if (acc[k].launches == 0) continue;
+    if (n < max_out) {
+      out[n] = acc[k];
+      std::strncpy(out[n].name, kKernelNames[k], sizeof(out[n].name) - 1);
+      out[n].name[sizeof(out[n].name) - 1] = 0;
+    }
+    ++n;
+  }
+  *n_out = n < max_out ? n : max_out;
+  profiler_free(pr);
+  return st;
 }
 
 spect_status spect_dot_f64(const float* d_a, const float* d_b, size_t n, double* d_out,

@@ -25,7 +25,7 @@ STATUS_NAMES = {
 }
 EXPORTED = ("spect_workspace_bytes", "spect_plan_create", "spect_forward", "spect_back",
             "spect_em_step", "spect_plan_destroy", "spect_status_string", "spect_dot_f64",
-            "spect_version")
+            "spect_profile_start", "spect_profile_stop", "spect_version")
 
 
 class SpectError(RuntimeError):
@@ -39,6 +39,11 @@ class spect_geom(ctypes.Structure):
     _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32), ("nview", c_int32),
                 ("px", c_int32), ("pz", c_int32), ("dy", c_double),
                 ("angles", POINTER(c_double)), ("flags", c_uint32), ("view_batch", c_int32)]
+
+
+class spect_kernel_time(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", c_int32), ("total_ms", c_double),
+                ("min_ms", c_double), ("max_ms", c_double)]
 
 
 _LIB = None
@@ -59,8 +64,12 @@ def _lib():
         lib.spect_em_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
         lib.spect_plan_destroy.argtypes = [c_void_p]
         lib.spect_dot_f64.argtypes = [c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]
+        lib.spect_profile_start.argtypes = [c_void_p, c_int32]
+        lib.spect_profile_stop.argtypes = [c_void_p, POINTER(spect_kernel_time), c_int32,
+                                           POINTER(c_int32)]
         for name in ("spect_workspace_bytes", "spect_plan_create", "spect_forward", "spect_back",
-                     "spect_em_step", "spect_plan_destroy", "spect_dot_f64"):
+                     "spect_em_step", "spect_plan_destroy", "spect_dot_f64",
+                     "spect_profile_start", "spect_profile_stop"):
             getattr(lib, name).restype = c_int
         lib.spect_status_string.argtypes = [c_int]
         lib.spect_status_string.restype = c_char_p
@@ -133,6 +142,24 @@ def spect_dot_f64(d_a: int, d_b: int, n: int, d_out: int, stream: int) -> None:
     st = _lib().spect_dot_f64(d_a, d_b, n, d_out, stream)
     if st != SPECT_OK:
         raise SpectError(st, "spect_dot_f64")
+
+
+def spect_profile_start(plan: int, max_launches: int) -> None:
+    st = _lib().spect_profile_start(plan, max_launches)
+    if st != SPECT_OK:
+        raise SpectError(st, "spect_profile_start")
+
+
+def spect_profile_stop(plan: int) -> dict:
+    """Returns {kernel name: dict(launches, total_ms, min_ms, max_ms)}."""
+    out = (spect_kernel_time * 16)()
+    n = c_int32(0)
+    st = _lib().spect_profile_stop(plan, out, 16, ctypes.byref(n))
+    if st != SPECT_OK:
+        raise SpectError(st, "spect_profile_stop")
+    return {out[i].name.decode(): dict(launches=out[i].launches, total_ms=out[i].total_ms,
+                                       min_ms=out[i].min_ms, max_ms=out[i].max_ms)
+            for i in range(n.value)}
 
 
 def spect_version() -> str:
@@ -219,6 +246,12 @@ class Plan:
         spect_em_step(self._plan, x.data_ptr(), y.data_ptr(), None if r is None else r.data_ptr(),
                       sens.data_ptr(), _stream(torch, self.device))
         return x
+
+    def profile_start(self, max_launches=4096):
+        spect_profile_start(self._plan, max_launches)
+
+    def profile_stop(self):
+        return spect_profile_stop(self._plan)
 
     def close(self):
         if getattr(self, "_plan", None):
