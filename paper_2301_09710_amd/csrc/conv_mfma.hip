@@ -46,6 +46,128 @@ __device__ __forceinline__ floatx4 mfma(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// The MFMA operands of one PSF tap a: KS A values (Toeplitz band of PSF row
+// a) and KS B values for each of the two N-blocks.  Loads are issued per
+// k-step so that a short prefetch distance can be kept in flight: the LDS
+// wait counter of gfx9 counts at most 15 outstanding LDS instructions, so
+// prefetching a whole tap (about 20 of them) would force full waits.
+template <int KS>
+struct Ops {
+  float av[KS], b0[KS], b1[KS];
+  // forward: A = P[a][aoff - 4s], B = R[boff - a + 4s RSI (+16)]
+  __device__ __forceinline__ void load_fwd(int s, const float* Pa, const float* Rb, int a, int PL,
+                                           int RSI) {
+    av[s] = Pa[a * PL - 4 * s];
+    b0[s] = Rb[4 * s * RSI - a];
+    b1[s] = Rb[4 * s * RSI - a + 16];
+  }
+  // adjoint: A = P[var][a][aoff + 4s], B = R[row + colb + a + 4s RSI]
+  __device__ __forceinline__ void load_back(int s, const float* Pa, const float* B0,
+                                            const float* B1, int a, int PL, int RSI) {
+    av[s] = Pa[a * PL + 4 * s];
+    b0[s] = B0[a + 4 * s * RSI];
+    b1[s] = B1[a + 4 * s * RSI];
+  }
+  // even and odd k-steps feed separate accumulators: four independent MFMA
+  // dependency chains per wave
+  __device__ __forceinline__ void step(int s, floatx4 (&acc)[4]) const {
+    acc[(s & 1) * 2 + 0] = mfma(av[s], b0[s], acc[(s & 1) * 2 + 0]);
+    acc[(s & 1) * 2 + 1] = mfma(av[s], b1[s], acc[(s & 1) * 2 + 1]);
+  }
+};
+
+constexpr int kPrefetch = 4;   // k-steps of operands kept in flight
+
+// One tap `a` held in X: run its KS k-steps while loading the remaining
+// steps of X and the first kPrefetch steps of the next tap into Y.
+template <int KS, class LoadX, class LoadY>
+__device__ __forceinline__ void tap_block(Ops<KS>& X, Ops<KS>& Y, floatx4 (&acc)[4],
+                                          LoadX&& lx, LoadY&& ly) {
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const int t = s + kPrefetch;
+    if (t < KS) lx(X, t);
+    else ly(Y, t - KS);
+    X.step(s, acc);
+    // keep this order: the scheduler would otherwise sink the prefetch next
+    // to its use and the wait counter would stall every step
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Workgroup id -> (tile, chunk, view) so that consecutive logical ids, which
+// share input planes, land on the same XCD (the hardware deals workgroups to
+// the 8 XCDs round-robin).
+__device__ __forceinline__ int xcd_remap(int wg, int total) {
+  const int per = total / 8, rem = total % 8, x = wg % 8, slot = wg / 8;
+  // XCDs x < rem own per + 1 logical ids, the others per
+  const int base = x * per + min(x, rem);
+  return base + slot;
+}
+
+// Depth planes of chunk c: [c ny / nchunk, (c+1) ny / nchunk).
+__device__ __forceinline__ void chunk_range(int c, int nchunk, int ny, int& j0, int& j1) {
+  j0 = (int)(((long long)c * ny) / nchunk);
+  j1 = (int)(((long long)(c + 1) * ny) / nchunk);
+}
+
+// Per-thread staging of one forward plane: the (RK = 4 KS) x RI input region
+// (one M-block of rows, WK = 1) and the px x PL PSF rows.  Wave w stages
+// region rows w, w+4, ...; lane l of a row covers columns l, l+64, l+128, so
+// row offsets are wave-uniform and column offsets are per-lane constants
+// that do not change from plane to plane.  The values of plane j+1 are loaded
+// into registers while plane j is being computed.
+constexpr int kStageCols = 3;    // 64-column sweeps per region row (RI <= 192)
+constexpr int kStagePsf = 16;    // PSF elements per thread (px * PL <= 4096)
+
+template <int KS>
+struct FwdStage {
+  float r[KS][kStageCols];
+  float q[kStagePsf];
+  __device__ __forceinline__ void load(const ConvShape& cs, const float* __restrict__ Wl,
+                                       const float* __restrict__ pj, int j, int k0, int i0,
+                                       size_t plane_stride, int w, int lane) {
+    const float* Wj = Wl + (size_t)j * cs.nx;
+#pragma unroll
+    for (int r8 = 0; r8 < KS; ++r8) {
+      const int rk = w + 4 * r8;                                   // < 4 KS = RK
+      const float* row = Wj + (size_t)clampi(k0 - cs.hb + rk, 0, cs.nz - 1) * plane_stride;
+#pragma unroll
+      for (int u = 0; u < kStageCols; ++u) {
+        const int ri = lane + 64 * u;
+        r[r8][u] = (ri < cs.RI) ? row[clampi(i0 - cs.ha + ri, 0, cs.nx - 1)] : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kStagePsf; ++t) {
+      const int e = threadIdx.x + 256 * t;
+      float v = 0.0f;
+      if (e < cs.px * cs.PL) {
+        const int a = e / cs.PL, b = e - a * cs.PL - cs.Z;
+        if (b >= 0 && b < cs.pz) v = pj[b * cs.px + a];
+      }
+      q[t] = v;
+    }
+  }
+  __device__ __forceinline__ void store(const ConvShape& cs, float* R, float* P, int w,
+                                        int lane) const {
+#pragma unroll
+    for (int r8 = 0; r8 < KS; ++r8) {
+      const int rk = w + 4 * r8;
+#pragma unroll
+      for (int u = 0; u < kStageCols; ++u) {
+        const int ri = lane + 64 * u;
+        if (ri < cs.RI) R[rk * cs.RSI + ri] = r[r8][u];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kStagePsf; ++t) {
+      const int e = threadIdx.x + 256 * t;
+      if (e < cs.px * cs.PL) P[e] = q[t];
+    }
+  }
+};
+
 // ---------------------------------------------------------------- forward
 template <int KS>
 __global__ __launch_bounds__(256, 2) void conv_fwd_mfma(const float* __restrict__ W,
@@ -55,52 +177,74 @@ __global__ __launch_bounds__(256, 2) void conv_fwd_mfma(const float* __restrict_
   extern __shared__ float sm[];
   float* R = sm;                               // RK x RSI: input region of one plane
   float* P = sm + cs.RK * cs.RSI;              // px x PL: zero-padded PSF rows
-  const int tile = blockIdx.x;
+  const int ntile = cs.tiles_k * cs.tiles_i;
+  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = logical % ntile, rest = logical / ntile;
   const int tk = tile / cs.tiles_i, ti = tile - tk * cs.tiles_i;
-  const int c = blockIdx.y, lb = blockIdx.z, l = view0 + lb;
+  const int c = rest % cs.nchunk, lb = rest / cs.nchunk, l = view0 + lb;
   const int k0 = tk * 16 * cs.WK, i0 = ti * 32 * cs.WI;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
   const int wk = w / cs.WI, wi = w - wk * cs.WI;
-  const int j0 = c * cs.jc, j1 = min(cs.ny, j0 + cs.jc);
+  int j0, j1;
+  chunk_range(c, cs.nchunk, cs.ny, j0, j1);
   const size_t plane_stride = (size_t)cs.ny * cs.nx;
   const float* Wl = W + (size_t)lb * cs.nz * plane_stride;
+  const float* psf_l = psf + (size_t)l * cs.ny * cs.pz * cs.px;
+  const bool prefetch = cs.WK == 1 && cs.RI <= 64 * kStageCols && cs.px * cs.PL <= 256 * kStagePsf;
 
   floatx4 tot0 = {0.f, 0.f, 0.f, 0.f}, tot1 = {0.f, 0.f, 0.f, 0.f};
   const int aoff = n - g + 2 * cs.hb + cs.Z;                         // A: P[a][aoff - 4s]
   const int boff = (wk * 16 + g) * cs.RSI + wi * 32 + n + 2 * cs.ha;  // B: R[boff - a + 4s RSI]
+  FwdStage<KS> st;
+  if (prefetch && j0 < j1)
+    st.load(cs, Wl, psf_l + (size_t)j0 * cs.pz * cs.px, j0, k0, i0, plane_stride, w, lane);
   for (int j = j0; j < j1; ++j) {
     __syncthreads();                                                 // previous plane consumed
-    for (int e = threadIdx.x; e < cs.RK * cs.RI; e += 256) {
-      const int rk = e / cs.RI, ri = e - rk * cs.RI;
-      const int kk = clampi(k0 - cs.hb + rk, 0, cs.nz - 1);
-      const int ii = clampi(i0 - cs.ha + ri, 0, cs.nx - 1);
-      R[rk * cs.RSI + ri] = Wl[(size_t)kk * plane_stride + (size_t)j * cs.nx + ii];
-    }
-    const float* pj = psf + ((size_t)l * cs.ny + j) * cs.pz * cs.px;
-    for (int e = threadIdx.x; e < cs.px * cs.PL; e += 256) {
-      const int a = e / cs.PL, b = e - a * cs.PL - cs.Z;
-      P[e] = (b >= 0 && b < cs.pz) ? pj[b * cs.px + a] : 0.0f;
-    }
-    __syncthreads();
-    floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-    for (int a = 0; a < cs.px; ++a) {
-      const float* Ap = P + a * cs.PL + aoff;
-      const float* Bp = R + boff - a;
-      float av[KS], b0[KS], b1[KS];
-#pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        av[s] = Ap[-4 * s];
-        b0[s] = Bp[4 * s * cs.RSI];
-        b1[s] = Bp[4 * s * cs.RSI + 16];
+    if (prefetch) {
+      st.store(cs, R, P, w, lane);
+      __syncthreads();
+      if (j + 1 < j1)
+        st.load(cs, Wl, psf_l + (size_t)(j + 1) * cs.pz * cs.px, j + 1, k0, i0, plane_stride, w,
+                lane);
+    } else {
+      // general shapes: stage straight from memory
+      const float* Wj = Wl + (size_t)j * cs.nx;
+      int rk = threadIdx.x / cs.RI, ri = threadIdx.x - (threadIdx.x / cs.RI) * cs.RI;
+      for (; rk < cs.RK;) {
+        const int kk = clampi(k0 - cs.hb + rk, 0, cs.nz - 1);
+        const int ii = clampi(i0 - cs.ha + ri, 0, cs.nx - 1);
+        R[rk * cs.RSI + ri] = Wj[(size_t)kk * plane_stride + ii];
+        ri += 256;
+        while (ri >= cs.RI) { ri -= cs.RI; ++rk; }
       }
-#pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        acc0 = mfma(av[s], b0[s], acc0);
-        acc1 = mfma(av[s], b1[s], acc1);
+      const float* pj = psf_l + (size_t)j * cs.pz * cs.px;
+      for (int e = threadIdx.x; e < cs.px * cs.PL; e += 256) {
+        const int a = e / cs.PL, b = e - a * cs.PL - cs.Z;
+        P[e] = (b >= 0 && b < cs.pz) ? pj[b * cs.px + a] : 0.0f;
       }
+      __syncthreads();
     }
-    tot0 += acc0;
-    tot1 += acc1;
+    floatx4 acc[4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f},
+                      {0.f, 0.f, 0.f, 0.f}};
+    // taps a along x, software-pipelined: the operands of the next k-steps are
+    // read from LDS while the MFMAs of the current one run
+    Ops<KS> A, B;
+    const float* Pa = P + aoff;
+    const float* Rb = R + boff;
+#pragma unroll
+    for (int s = 0; s < kPrefetch; ++s) A.load_fwd(s, Pa, Rb, 0, cs.PL, cs.RSI);
+    for (int a = 0; a < cs.px; a += 2) {
+      const int a1 = min(a + 1, cs.px - 1), a2 = min(a + 2, cs.px - 1);
+      tap_block<KS>(A, B, acc,
+                    [&](Ops<KS>& o, int t) { o.load_fwd(t, Pa, Rb, a, cs.PL, cs.RSI); },
+                    [&](Ops<KS>& o, int t) { o.load_fwd(t, Pa, Rb, a1, cs.PL, cs.RSI); });
+      if (a + 1 < cs.px)
+        tap_block<KS>(B, A, acc,
+                      [&](Ops<KS>& o, int t) { o.load_fwd(t, Pa, Rb, a1, cs.PL, cs.RSI); },
+                      [&](Ops<KS>& o, int t) { o.load_fwd(t, Pa, Rb, a2, cs.PL, cs.RSI); });
+    }
+    tot0 += acc[0] + acc[2];
+    tot1 += acc[1] + acc[3];
   }
   // D[4g + v][n]: output k = k0 + 16 wk + 4g + v, i = i0 + 32 wi + 16 nb + n
   float* out = partial + ((size_t)c * nvb + lb) * cs.nz * cs.nx;
@@ -115,6 +259,59 @@ __global__ __launch_bounds__(256, 2) void conv_fwd_mfma(const float* __restrict_
   }
 }
 
+// Per-thread staging of one adjoint plane's PSF rows: P[0] the rows
+// themselves (offset 15: index b + 15), on z-edge tiles also P[1] the suffix
+// sums (b' >= b) and P[2] the prefix sums (b' <= b) along b; nz = 1 uses the
+// full row sum for both.
+struct BackPsf {
+  float v0[kStagePsf], v1[kStagePsf], v2[kStagePsf];
+  __device__ __forceinline__ void load_range(const ConvShape& cs, const float* __restrict__ psf,
+                                             const float* __restrict__ psf_cum, int l, int j,
+                                             bool kedge, int base) {
+    const size_t off = ((size_t)l * cs.ny + j) * cs.pz * cs.px;
+    const float* pj = psf + off;
+    const float* suf = psf_cum + off;
+    const float* pre = suf + (size_t)cs.nview_ny_pz_px;
+#pragma unroll
+    for (int t = 0; t < kStagePsf; ++t) {
+      const int e = base + threadIdx.x + 256 * t;
+      float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
+      if (e < cs.px * cs.PL) {
+        const int a = e / cs.PL, b = e - a * cs.PL - 15;
+        if (b >= 0 && b < cs.pz) x0 = pj[b * cs.px + a];
+        if (kedge) {
+          const float tot = suf[a];
+          if (cs.nz == 1) { x1 = tot; x2 = tot; }
+          else {
+            x1 = (b < 0) ? tot : (b < cs.pz ? suf[b * cs.px + a] : 0.0f);
+            x2 = (b < 0) ? 0.0f : pre[min(b, cs.pz - 1) * cs.px + a];
+          }
+        }
+      }
+      v0[t] = x0; v1[t] = x1; v2[t] = x2;
+    }
+  }
+  __device__ __forceinline__ void store_range(const ConvShape& cs, float* P, bool kedge,
+                                              int base) const {
+    const int m = cs.px * cs.PL;
+#pragma unroll
+    for (int t = 0; t < kStagePsf; ++t) {
+      const int e = base + threadIdx.x + 256 * t;
+      if (e < m) {
+        P[e] = v0[t];
+        if (kedge) { P[m + e] = v1[t]; P[2 * m + e] = v2[t]; }
+      }
+    }
+  }
+  __device__ __forceinline__ void load(const ConvShape& cs, const float* psf, const float* psf_cum,
+                                       int l, int j, bool kedge) {
+    load_range(cs, psf, psf_cum, l, j, kedge, 0);
+  }
+  __device__ __forceinline__ void store(const ConvShape& cs, float* P, bool kedge) const {
+    store_range(cs, P, kedge, 0);
+  }
+};
+
 // ---------------------------------------------------------------- adjoint
 template <int KS>
 __global__ __launch_bounds__(256, 2) void conv_back_mfma(const float* __restrict__ v,
@@ -125,13 +322,16 @@ __global__ __launch_bounds__(256, 2) void conv_back_mfma(const float* __restrict
   extern __shared__ float sm[];
   float* R = sm;                               // RK x RSI: projection region + edge columns
   float* P = sm + cs.RK * cs.RSI;              // 3 x px x PL: PSF rows, suffix sums, prefix sums
-  const int tile = blockIdx.x;
+  const int ntile = cs.tiles_k * cs.tiles_i;
+  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = logical % ntile, rest = logical / ntile;
   const int tk = tile / cs.tiles_i, ti = tile - tk * cs.tiles_i;
-  const int c = blockIdx.y, lb = blockIdx.z, l = view0 + lb;
+  const int c = rest % cs.nchunk, lb = rest / cs.nchunk, l = view0 + lb;
   const int k0 = tk * 16 * cs.WK, i0 = ti * 32 * cs.WI;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
   const int wk = w / cs.WI, wi = w - wk * cs.WI;
-  const int j0 = c * cs.jc, j1 = min(cs.ny, j0 + cs.jc);
+  int j0, j1;
+  chunk_range(c, cs.nchunk, cs.ny, j0, j1);
   const float* vl = v + (size_t)l * cs.nz * cs.nx;
   const int ELO = cs.RI, EHI = cs.RI + cs.px;  // edge column blocks
   const bool kedge = (k0 == 0) || (k0 + 16 * cs.WK >= cs.nz);
@@ -188,49 +388,41 @@ __global__ __launch_bounds__(256, 2) void conv_back_mfma(const float* __restrict
   }
   const int rowb = (wk * 16 + g) * cs.RSI;
 
+  // PSF rows of the next plane are prefetched into registers during the
+  // current plane (with their suffix / prefix sums on z-edge tiles)
+  const bool prefetch = cs.px * cs.PL <= 256 * kStagePsf;
+  BackPsf pf;
+  if (prefetch && j0 < j1) pf.load(cs, psf, psf_cum, l, j0, kedge);
   for (int j = j0; j < j1; ++j) {
     __syncthreads();                                               // region staged / plane consumed
-    const float* pj = psf + ((size_t)l * cs.ny + j) * cs.pz * cs.px;
-    for (int e = threadIdx.x; e < cs.px * cs.PL; e += 256) {
-      const int a = e / cs.PL, b = e - a * cs.PL - 15;
-      P[e] = (b >= 0 && b < cs.pz) ? pj[b * cs.px + a] : 0.0f;
-    }
-    if (kedge) {
-      // rows of output k = 0 / nz-1: suffix (b' >= b) / prefix (b' <= b) sums of the
-      // PSF row along b (nz = 1: the full row sum for every b)
-      const float* suf = psf_cum + ((size_t)l * cs.ny + j) * cs.pz * cs.px;
-      const float* pre = suf + (size_t)cs.nview_ny_pz_px;
-      for (int e = threadIdx.x; e < cs.px * cs.PL; e += 256) {
-        const int a = e / cs.PL, b = e - a * cs.PL - 15;
-        const float tot = suf[a];                                  // b = 0 suffix: whole row
-        float vs, vp;
-        if (cs.nz == 1) { vs = tot; vp = tot; }
-        else {
-          vs = (b < 0) ? tot : (b < cs.pz ? suf[b * cs.px + a] : 0.0f);
-          vp = (b < 0) ? 0.0f : pre[min(b, cs.pz - 1) * cs.px + a];
-        }
-        P[cs.px * cs.PL + e] = vs;
-        P[2 * cs.px * cs.PL + e] = vp;
+    if (prefetch) {
+      pf.store(cs, P, kedge);
+    } else {
+      BackPsf one;
+      for (int base = 0; base < cs.px * cs.PL; base += 256 * kStagePsf) {
+        one.load_range(cs, psf, psf_cum, l, j, kedge, base);
+        one.store_range(cs, P, kedge, base);
       }
     }
     __syncthreads();
-    floatx4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-    for (int a = 0; a < cs.px; ++a) {
-      const float* Ap = P + a * cs.PL + aoff;
-      const float* B0 = R + rowb + colb[0] + a;
-      const float* B1 = R + rowb + colb[1] + a;
-      float av[KS], b0[KS], b1[KS];
+    if (prefetch && j + 1 < j1) pf.load(cs, psf, psf_cum, l, j + 1, kedge);
+    floatx4 acc[4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f},
+                      {0.f, 0.f, 0.f, 0.f}};
+    const float* B0 = R + rowb + colb[0];
+    const float* B1 = R + rowb + colb[1];
+    Ops<KS> A, B;
+    const float* Pa = P + aoff;
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        av[s] = Ap[4 * s];
-        b0[s] = B0[4 * s * cs.RSI];
-        b1[s] = B1[4 * s * cs.RSI];
-      }
-#pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        acc0 = mfma(av[s], b0[s], acc0);
-        acc1 = mfma(av[s], b1[s], acc1);
-      }
+    for (int s = 0; s < kPrefetch; ++s) A.load_back(s, Pa, B0, B1, 0, cs.PL, cs.RSI);
+    for (int a = 0; a < cs.px; a += 2) {
+      const int a1 = min(a + 1, cs.px - 1), a2 = min(a + 2, cs.px - 1);
+      tap_block<KS>(A, B, acc,
+                    [&](Ops<KS>& o, int t) { o.load_back(t, Pa, B0, B1, a, cs.PL, cs.RSI); },
+                    [&](Ops<KS>& o, int t) { o.load_back(t, Pa, B0, B1, a1, cs.PL, cs.RSI); });
+      if (a + 1 < cs.px)
+        tap_block<KS>(B, A, acc,
+                      [&](Ops<KS>& o, int t) { o.load_back(t, Pa, B0, B1, a1, cs.PL, cs.RSI); },
+                      [&](Ops<KS>& o, int t) { o.load_back(t, Pa, B0, B1, a2, cs.PL, cs.RSI); });
     }
     float* out = U + (size_t)lb * cs.nz * cs.ny * cs.nx + (size_t)j * cs.nx;
 #pragma unroll
@@ -239,8 +431,8 @@ __global__ __launch_bounds__(256, 2) void conv_back_mfma(const float* __restrict
       const int i = i0 + wi * 32 + n;
       if (k < cs.nz) {
         float* row = out + (size_t)k * cs.ny * cs.nx;
-        if (i < cs.nx) row[i] = acc0[vv];
-        if (i + 16 < cs.nx) row[i + 16] = acc1[vv];
+        if (i < cs.nx) row[i] = acc[0][vv] + acc[2][vv];
+        if (i + 16 < cs.nx) row[i + 16] = acc[1][vv] + acc[3][vv];
       }
     }
   }
@@ -253,7 +445,7 @@ hipError_t launch_fwd_ks(const ConvShape& cs, const float* W, const float* psf, 
   hipError_t e = hipFuncSetAttribute((const void*)conv_fwd_mfma<KS>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
   if (e != hipSuccess) return e;
-  dim3 grid(cs.tiles_k * cs.tiles_i, cs.nchunk, nvb);
+  dim3 grid(cs.tiles_k * cs.tiles_i * cs.nchunk * nvb);
   hipLaunchKernelGGL(conv_fwd_mfma<KS>, grid, dim3(256), sm, s, W, psf, partial, cs, view0, nvb);
   return hipGetLastError();
 }
@@ -265,7 +457,7 @@ hipError_t launch_back_ks(const ConvShape& cs, const float* v, const float* psf,
   hipError_t e = hipFuncSetAttribute((const void*)conv_back_mfma<KS>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
   if (e != hipSuccess) return e;
-  dim3 grid(cs.tiles_k * cs.tiles_i, cs.nchunk, nvb);
+  dim3 grid(cs.tiles_k * cs.tiles_i * cs.nchunk * nvb);
   hipLaunchKernelGGL(conv_back_mfma<KS>, grid, dim3(256), sm, s, v, psf, psf_cum, U, cs, view0,
                      nvb);
   return hipGetLastError();
@@ -342,6 +534,33 @@ ConvShape make_conv_shape(const spect_geom& g, int jc_fwd, int jc_back) {
   return cs;
 }
 
+// Workgroups of one launch resident per CU (HIP occupancy query).
+template <int KS>
+int wgs_per_cu_ks(const ConvShape& cs, bool back) {
+  int nb = 0;
+  const size_t sm = conv_mfma_lds_bytes(cs, back);
+  hipError_t e = back ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                            &nb, (const void*)conv_back_mfma<KS>, 256, sm)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                            &nb, (const void*)conv_fwd_mfma<KS>, 256, sm);
+  if (e != hipSuccess || nb < 1) nb = (int)(kLdsBytes / (sm ? sm : 1));
+  return nb < 1 ? 1 : nb;
+}
+
+// Depth chunks per (tile, view): minimise rounds * planes-per-workgroup, the
+// length of the schedule when the resident slots are refilled in waves.
+static int pick_chunks(int ny, long long tiles_views, long long slots) {
+  int best = 1;
+  long long best_cost = -1;
+  for (int n = 1; n <= kMaxChunks && n <= ny; ++n) {
+    const long long wgs = tiles_views * n;
+    const long long rounds = (wgs + slots - 1) / slots;
+    const long long cost = rounds * ((ny + n - 1) / n);
+    if (best_cost < 0 || cost < best_cost) { best_cost = cost; best = n; }
+  }
+  return best;
+}
+
 #define SPECT_KS_CASES(X) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20)
 
 hipError_t launch_conv_fwd_mfma(const Plan& p, const float* W, float* partial, int view0, int nvb,
@@ -369,4 +588,26 @@ hipError_t launch_conv_back_mfma(const Plan& p, const float* v, float* U, int vi
   }
 }
 
+}  // namespace spect
+
+namespace spect {
+void tune_conv_chunks(ConvShape& cs, int views) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    return;
+  int fw = 1, bw = 1;
+  switch (cs.KS) {
+#define CASE(K) case K: fw = wgs_per_cu_ks<K>(cs, false); bw = wgs_per_cu_ks<K>(cs, true); break;
+    SPECT_KS_CASES(CASE)
+#undef CASE
+    default: return;
+  }
+  const long long tv = (long long)cs.tiles_k * cs.tiles_i * views;
+  cs.nchunk = pick_chunks(cs.ny, tv, (long long)cus * fw);
+  cs.nchunk_back = pick_chunks(cs.ny, tv, (long long)cus * bw);
+  cs.jc = (cs.ny + cs.nchunk - 1) / cs.nchunk;
+  cs.jc_back = (cs.ny + cs.nchunk_back - 1) / cs.nchunk_back;
+}
 }  // namespace spect

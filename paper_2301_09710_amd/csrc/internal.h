@@ -6,7 +6,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
-#include "../../include/spect.h"
+#include "spect.h"
 
 namespace spect {
 
@@ -25,6 +25,8 @@ constexpr int kBackGroups = 16;
 constexpr int kRotViewsPerGroup = 8;
 // Largest number of 4-deep k-steps of the MFMA convolution (pz <= 65).
 constexpr int kMaxMfmaKSteps = 20;
+// Largest number of depth chunks (forward partial sums) per tile and view.
+constexpr int kMaxChunks = 16;
 // LDS of one gfx950 compute unit.
 constexpr size_t kLdsBytes = 163840;
 
@@ -121,6 +123,9 @@ spect_status compute_layout(const spect_geom& g, Layout* lay, int* view_batch, i
 
 bool conv_mfma_supported(const spect_geom& g);
 ConvShape make_conv_shape(const spect_geom& g, int jc_fwd, int jc_back);
+// Choose the depth chunking of the MFMA convolution for `views` views per
+// launch from the device's CU count and the kernels' occupancy.
+void tune_conv_chunks(ConvShape& cs, int views);
 size_t conv_mfma_lds_bytes(const ConvShape& cs, bool back);
 
 // ---- kernel launchers (return hipGetLastError() of the launch) ----

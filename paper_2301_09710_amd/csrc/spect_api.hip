@@ -44,7 +44,8 @@ spect_status compute_layout(const spect_geom& g, Layout* lay, int* view_batch, i
   lay->tables_off = take((size_t)g.nview * 2 * n * sizeof(int32_t));
   lay->tables_w = take((size_t)g.nview * 2 * n * sizeof(float2));
   lay->vol_batch = take((size_t)vb * N * sizeof(float));
-  lay->fwd_partial = take((size_t)nc * vb * g.nz * g.nx * sizeof(float));
+  const int maxc = nc > kMaxChunks ? nc : kMaxChunks;
+  lay->fwd_partial = take((size_t)maxc * vb * g.nz * g.nx * sizeof(float));
   lay->back_partial = take((size_t)kBackGroups * N * sizeof(float));
   const bool cache = (g.flags & SPECT_CACHE_MUBAR) != 0;
   lay->mubar_cache = cache ? take((size_t)g.nview * N * sizeof(float)) : 0;
@@ -191,6 +192,10 @@ spect_status spect_plan_create(spect_plan* out, const spect_geom* g, const float
   p->mubar_batch = nullptr;
   p->use_mfma = conv_mfma_supported(*g);
   p->conv = make_conv_shape(*g, kFwdJChunk, kBackJChunk);
+  if (p->use_mfma) {
+    tune_conv_chunks(p->conv, g->nview);   // independent of view_batch: same sums
+    p->nchunk = p->conv.nchunk;          // forward partial sums per view
+  }
   float* cum = reinterpret_cast<float*>(p->ws + lay.psf_cum);
   p->psf_cum = cum;
   if (e == hipSuccess) e = timed(*p, K_MUBAR, stream, [&] { return launch_psf_cum(*p, cum, stream); });
