@@ -10,9 +10,9 @@
 
 namespace spect {
 
-// Largest in-plane size for which one z-slice (two padded n x (n+1) float
-// buffers) fits in the 160 KiB LDS of a gfx950 compute unit.
-constexpr int kMaxLdsN = 140;
+// Largest in-plane size for which two z-slices (n rows of stride n + 8 (mod
+// 16) floats) and the per-view tables fit in the 160 KiB LDS of a gfx950 CU.
+constexpr int kMaxLdsN = 136;
 // Threads per workgroup of the rotation kernels.
 constexpr int kRotThreads = 1024;
 // Depth planes per workgroup (one partial sum each) of the forward convolution.

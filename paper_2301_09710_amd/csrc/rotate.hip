@@ -4,12 +4,16 @@
 // transpose of those steps accumulated over views (Alg. 2).
 //
 // Design: one workgroup owns one z-slice (n x n, n = nx = ny) held in LDS as
-// rows j of stride S = n + 1 floats and loops over several views.  The three
+// rows j of stride S floats and loops over several views.  The three
 // passes are evaluated as one fused gather per output pixel: pass 3 needs two
 // pass-2 values, each needing two pass-1 values, each needing two pixels of
 // the quarter-turned slice -- at most 8 LDS reads and 14 two-tap blends,
 // with the pass semantics kept exactly (every intermediate sample outside
-// [0, n) is zero, as in a pass over the whole slice).  The quarter turn is an
+// [0, n) is zero, as in a pass over the whole slice).  A wave owns 8 x 8 pixel
+// tiles and the LDS row stride S is 8 (mod 16) floats: the gathers of a
+// rotated tile then spread over the 64 LDS banks for every angle (a wave
+// covering one row would read along a sheared line, which some angle maps
+// onto one bank).  The quarter turn is an
 // affine remapping of the LDS address, so the slice is staged once per
 // workgroup, unrotated, whatever the view.  The transpose uses the same
 // tables with the taps mirrored (out[q] = w.x in[q - o] + w.y in[q - o - 1]),
@@ -20,7 +24,23 @@ namespace spect {
 namespace {
 
 constexpr int NT = kRotThreads;
-constexpr int RMAX = (kMaxLdsN * kMaxLdsN + NT - 1) / NT;
+constexpr int NWAVE = NT / 64;
+constexpr int TPR_MAX = (kMaxLdsN + 7) / 8;                 // 8x8 tiles per row
+constexpr int RMAX = (TPR_MAX * TPR_MAX + NWAVE - 1) / NWAVE; // tiles (pixels) per lane
+
+// LDS row stride of a slice: >= n and = 8 (mod 16).
+__host__ __device__ __forceinline__ int slice_stride(int n) { return n + ((8 - n % 16) + 16) % 16; }
+
+// Pixel of lane `lane`, iteration r: 8x8 tile (w + NWAVE r) of the slice.
+__device__ __forceinline__ bool tile_pixel(int n, int r, int& i, int& j) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tpr = (n + 7) >> 3;
+  const int tile = w + NWAVE * r;
+  const int tj = tile / tpr, ti = tile - tj * tpr;
+  i = 8 * ti + (lane & 7);
+  j = 8 * tj + (lane >> 3);
+  return tj < tpr && i < n && j < n;
+}
 
 // Position (di, dj) that pixel (i, j) takes under P_m, the gather
 // out(p) = in(R(m*90deg)^-1 (p - c) + c) with R acting on (i, j).
@@ -146,7 +166,7 @@ __global__ __launch_bounds__(NT) void mubar_kernel(const float* __restrict__ mu,
                                                    int view0, int nviews, int VG, int out_view0,
                                                    Tables tab, double dy) {
   extern __shared__ float smem[];
-  const int S = n + 1;
+  const int S = slice_stride(n);
   float* X = smem;
   float* Y = smem + n * S;
   ViewTab t = carve_tab(Y + n * S, n);
@@ -160,9 +180,10 @@ __global__ __launch_bounds__(NT) void mubar_kernel(const float* __restrict__ mu,
     load_tab(tab, l, n, t);
     __syncthreads();
     const QAddr qa = quarter_addr(tab.quarter[l], n, S);
-    for (int p = threadIdx.x; p < n * n; p += NT) {
-      const int j = p / n, i = p - j * n;
-      Y[j * S + i] = rotated_pixel(X, n, qa, t, i, j);
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+      int i, j;
+      if (tile_pixel(n, r, i, j)) Y[j * S + i] = rotated_pixel(X, n, qa, t, i, j);
     }
     __syncthreads();
     // suffix scan along j for every column i (detector beyond j = n-1), FP64
@@ -192,7 +213,7 @@ __global__ __launch_bounds__(NT) void rot_fwd_kernel(const float* __restrict__ x
                                                      float* __restrict__ W, int n, int nz,
                                                      int view0, int nvb, int VG, Tables tab) {
   extern __shared__ float smem[];
-  const int S = n + 1;
+  const int S = slice_stride(n);
   float* X = smem;
   ViewTab t = carve_tab(X + n * S, n);
   const int k = blockIdx.x;
@@ -201,15 +222,22 @@ __global__ __launch_bounds__(NT) void rot_fwd_kernel(const float* __restrict__ x
   const int lb0 = blockIdx.y * VG, lb1 = min(nvb, lb0 + VG);
   for (int lb = lb0; lb < lb1; ++lb) {
     const int l = view0 + lb;
+    const float* mbs = mb + (size_t)(lb + mb_off) * N + (size_t)k * nn;
+    float att[RMAX];                       // attenuation factors, loaded ahead of the gathers
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+      int i, j;
+      att[r] = tile_pixel(n, r, i, j) ? mbs[j * n + i] : 0.0f;
+    }
     __syncthreads();
     load_tab(tab, l, n, t);
     __syncthreads();
     const QAddr qa = quarter_addr(tab.quarter[l], n, S);
-    const float* mbs = mb + (size_t)(lb + mb_off) * N + (size_t)k * nn;
     float* dst = W + (size_t)lb * N + (size_t)k * nn;
-    for (int p = threadIdx.x; p < n * n; p += NT) {
-      const int j = p / n, i = p - j * n;
-      dst[p] = rotated_pixel(X, n, qa, t, i, j) * mbs[p];
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+      int i, j;
+      if (tile_pixel(n, r, i, j)) dst[j * n + i] = rotated_pixel(X, n, qa, t, i, j) * att[r];
     }
   }
 }
@@ -223,7 +251,7 @@ __global__ __launch_bounds__(NT) void rot_back_kernel(const float* __restrict__ 
                                                       int view0, int nvb, int G, int accumulate,
                                                       Tables tab) {
   extern __shared__ float smem[];
-  const int S = n + 1;
+  const int S = slice_stride(n);
   float* Gs = smem;
   ViewTab t = carve_tab(Gs + n * S, n);
   const int k = blockIdx.x, g = blockIdx.y;
@@ -245,9 +273,8 @@ __global__ __launch_bounds__(NT) void rot_back_kernel(const float* __restrict__ 
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < RMAX; ++r) {
-      const int p = threadIdx.x + r * NT;
-      if (p < n * n) {
-        const int j = p / n, i = p - j * n;
+      int i, j;
+      if (tile_pixel(n, r, i, j)) {
         int di, dj;
         quarter_dst(m, n, i, j, di, dj);                 // P_m^T: x(i, j) = h(P_m position)
         acc[r] += rotated_T_pixel(Gs, n, S, t, di, dj);
@@ -257,8 +284,8 @@ __global__ __launch_bounds__(NT) void rot_back_kernel(const float* __restrict__ 
   float* dst = partial + (size_t)g * N + (size_t)k * nn;
 #pragma unroll
   for (int r = 0; r < RMAX; ++r) {
-    const int p = threadIdx.x + r * NT;
-    if (p < n * n) dst[p] = accumulate ? dst[p] + acc[r] : acc[r];
+    int i, j;
+    if (tile_pixel(n, r, i, j)) dst[j * n + i] = accumulate ? dst[j * n + i] + acc[r] : acc[r];
   }
 }
 
@@ -272,7 +299,7 @@ __global__ void back_reduce_kernel(const float* __restrict__ partial, float* __r
 }
 
 size_t tab_bytes(int n) { return (size_t)2 * n * 4 + (size_t)2 * n * 8; }
-size_t slice_bytes(int n) { return (size_t)n * (n + 1) * 4; }
+size_t slice_bytes(int n) { return (size_t)n * slice_stride(n) * 4; }
 
 hipError_t set_smem(const void* fn, size_t bytes) {
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
