@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--cpu-views", type=int, default=24,
                     help="views in the bounded oracle sample (0 disables the CPU baseline)")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB device-to-device: a plain "
+                         "copy kernel of known size that calibrates HBM byte counters")
     return ap.parse_args()
 
 
@@ -201,6 +204,15 @@ def main():
             lat.append(a.elapsed_time(b))
         em = {"iters": args.em_iters, "recons": args.em_recons, "p50_ms": pct(lat, 50),
               "p99_ms": pct(lat, 99)}
+
+    if args.copy_mb > 0:
+        nbytes = args.copy_mb << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dstb = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dstb.copy_(src)
+        torch.cuda.synchronize()
+        del src, dstb
 
     cpu = None
     if args.cpu_views > 0:

@@ -26,13 +26,12 @@
 // short.  Partial sums per chunk are reduced in a fixed order afterwards.
 //
 // Adjoint (per depth plane): the same tiles read the projection of one view,
-// staged once with zero padding; replicate padding's adjoint is the fold of
-// the border onto the edge rows and columns, which is handled by
-//   * output rows at k = 0 / nz-1: suffix / prefix sums of the PSF row
-//     along b replace the PSF row (per-lane choice of the A source);
-//   * output columns at i = 0 / nx-1: prefix / suffix sums of the projection
-//     along x replace the shifted projection (extra LDS columns, per-lane
-//     choice of the B source).
+// staged once with zero padding, and compute the zero-padded correlation,
+// which is the exact adjoint at every bin off the edge rows (k = 0, nz-1)
+// and columns (i = 0, nx-1).  Replicate padding's adjoint folds the border
+// onto those edges; conv_back_edges recomputes the edge bins exactly as a
+// small dense MFMA product over cumulative sums of the projection (planes as
+// rows), so the main kernel stays uniform across lanes.
 #include "internal.h"
 
 namespace spect {
@@ -61,12 +60,12 @@ struct Ops {
     b0[s] = Rb[4 * s * RSI - a];
     b1[s] = Rb[4 * s * RSI - a + 16];
   }
-  // adjoint: A = P[var][a][aoff + 4s], B = R[row + colb + a + 4s RSI]
-  __device__ __forceinline__ void load_back(int s, const float* Pa, const float* B0,
-                                            const float* B1, int a, int PL, int RSI) {
+  // adjoint: A = P[a][aoff + 4s], B = R[boff + a + 4s RSI (+16)]
+  __device__ __forceinline__ void load_back(int s, const float* Pa, const float* Rb, int a, int PL,
+                                            int RSI) {
     av[s] = Pa[a * PL + 4 * s];
-    b0[s] = B0[a + 4 * s * RSI];
-    b1[s] = B1[a + 4 * s * RSI];
+    b0[s] = Rb[4 * s * RSI + a];
+    b1[s] = Rb[4 * s * RSI + a + 16];
   }
   // even and odd k-steps feed separate accumulators: four independent MFMA
   // dependency chains per wave
@@ -259,69 +258,46 @@ __global__ __launch_bounds__(256, 2) void conv_fwd_mfma(const float* __restrict_
   }
 }
 
-// Per-thread staging of one adjoint plane's PSF rows: P[0] the rows
-// themselves (offset 15: index b + 15), on z-edge tiles also P[1] the suffix
-// sums (b' >= b) and P[2] the prefix sums (b' <= b) along b; nz = 1 uses the
-// full row sum for both.
+// Per-thread staging of one adjoint plane's PSF rows: P[a][b + 15].
 struct BackPsf {
-  float v0[kStagePsf], v1[kStagePsf], v2[kStagePsf];
+  float v0[kStagePsf];
   __device__ __forceinline__ void load_range(const ConvShape& cs, const float* __restrict__ psf,
-                                             const float* __restrict__ psf_cum, int l, int j,
-                                             bool kedge, int base) {
-    const size_t off = ((size_t)l * cs.ny + j) * cs.pz * cs.px;
-    const float* pj = psf + off;
-    const float* suf = psf_cum + off;
-    const float* pre = suf + (size_t)cs.nview_ny_pz_px;
+                                             int l, int j, int base) {
+    const float* pj = psf + ((size_t)l * cs.ny + j) * cs.pz * cs.px;
 #pragma unroll
     for (int t = 0; t < kStagePsf; ++t) {
       const int e = base + threadIdx.x + 256 * t;
-      float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
+      float x0 = 0.0f;
       if (e < cs.px * cs.PL) {
         const int a = e / cs.PL, b = e - a * cs.PL - 15;
         if (b >= 0 && b < cs.pz) x0 = pj[b * cs.px + a];
-        if (kedge) {
-          const float tot = suf[a];
-          if (cs.nz == 1) { x1 = tot; x2 = tot; }
-          else {
-            x1 = (b < 0) ? tot : (b < cs.pz ? suf[b * cs.px + a] : 0.0f);
-            x2 = (b < 0) ? 0.0f : pre[min(b, cs.pz - 1) * cs.px + a];
-          }
-        }
       }
-      v0[t] = x0; v1[t] = x1; v2[t] = x2;
+      v0[t] = x0;
     }
   }
-  __device__ __forceinline__ void store_range(const ConvShape& cs, float* P, bool kedge,
-                                              int base) const {
-    const int m = cs.px * cs.PL;
+  __device__ __forceinline__ void store_range(const ConvShape& cs, float* P, int base) const {
 #pragma unroll
     for (int t = 0; t < kStagePsf; ++t) {
       const int e = base + threadIdx.x + 256 * t;
-      if (e < m) {
-        P[e] = v0[t];
-        if (kedge) { P[m + e] = v1[t]; P[2 * m + e] = v2[t]; }
-      }
+      if (e < cs.px * cs.PL) P[e] = v0[t];
     }
-  }
-  __device__ __forceinline__ void load(const ConvShape& cs, const float* psf, const float* psf_cum,
-                                       int l, int j, bool kedge) {
-    load_range(cs, psf, psf_cum, l, j, kedge, 0);
-  }
-  __device__ __forceinline__ void store(const ConvShape& cs, float* P, bool kedge) const {
-    store_range(cs, P, kedge, 0);
   }
 };
 
 // ---------------------------------------------------------------- adjoint
+// Interior formula for every output bin of a tile:
+//   u[k][i] = sum_{a,b} p[a,b] v[k + b - hb][i + a - ha]   (v zero outside)
+// which is the exact adjoint everywhere except on the edge rows k = 0, nz-1
+// and edge columns i = 0, nx-1, where replicate padding folds the border;
+// conv_back_edges overwrites those afterwards.
 template <int KS>
 __global__ __launch_bounds__(256, 2) void conv_back_mfma(const float* __restrict__ v,
                                                          const float* __restrict__ psf,
-                                                         const float* __restrict__ psf_cum,
                                                          float* __restrict__ U, ConvShape cs,
                                                          int view0, int nvb) {
   extern __shared__ float sm[];
-  float* R = sm;                               // RK x RSI: projection region + edge columns
-  float* P = sm + cs.RK * cs.RSI;              // 3 x px x PL: PSF rows, suffix sums, prefix sums
+  float* R = sm;                               // RK x RSI: zero-padded projection region
+  float* P = sm + cs.RK * cs.RSI;              // px x PL: PSF rows
   const int ntile = cs.tiles_k * cs.tiles_i;
   const int logical = xcd_remap(blockIdx.x, gridDim.x);
   const int tile = logical % ntile, rest = logical / ntile;
@@ -333,96 +309,50 @@ __global__ __launch_bounds__(256, 2) void conv_back_mfma(const float* __restrict
   int j0, j1;
   chunk_range(c, cs.nchunk, cs.ny, j0, j1);
   const float* vl = v + (size_t)l * cs.nz * cs.nx;
-  const int ELO = cs.RI, EHI = cs.RI + cs.px;  // edge column blocks
-  const bool kedge = (k0 == 0) || (k0 + 16 * cs.WK >= cs.nz);
 
-  // Stage the projection region once: row rk <-> input k = k0 - hb + rk (zero outside),
-  // col ri <-> input i = i0 - ha + ri (zero outside); col ELO + a holds the sum of
-  // v[k][i] over i <= a - ha, col EHI + a the sum over i >= nx-1 + a - ha (nx = 1: all i).
+  // region row rk <-> input k = k0 - hb + rk, column ri <-> input i = i0 - ha + ri
   for (int e = threadIdx.x; e < cs.RK * cs.RI; e += 256) {
     const int rk = e / cs.RI, ri = e - rk * cs.RI;
     const int kk = k0 - cs.hb + rk, ii = i0 - cs.ha + ri;
     R[rk * cs.RSI + ri] =
         (kk >= 0 && kk < cs.nz && ii >= 0 && ii < cs.nx) ? vl[(size_t)kk * cs.nx + ii] : 0.0f;
   }
-  for (int e = threadIdx.x; e < cs.RK * 2; e += 256) {
-    const int rk = e >> 1, hi = e & 1;
-    const int kk = k0 - cs.hb + rk;
-    float* dst = R + rk * cs.RSI + (hi ? EHI : ELO);
-    if (kk < 0 || kk >= cs.nz) {
-      for (int a = 0; a < cs.px; ++a) dst[a] = 0.0f;
-      continue;
-    }
-    const float* row = vl + (size_t)kk * cs.nx;
-    if (!hi) {
-      float run = 0.0f;
-      int upto = -1;                                   // sum of row[0..upto]
-      for (int a = 0; a < cs.px; ++a) {
-        const int t = (cs.nx == 1) ? 0 : min(a - cs.ha, cs.nx - 1);
-        while (upto < t) run += row[++upto];
-        dst[a] = (t < 0) ? 0.0f : run;
-      }
-    } else {
-      for (int a = 0; a < cs.px; ++a) {
-        const int t = (cs.nx == 1) ? 0 : max(cs.nx - 1 + a - cs.ha, 0);
-        float run = 0.0f;
-        for (int i = t; i < cs.nx; ++i) run += row[i];
-        dst[a] = run;
-      }
-    }
-  }
-
-  // per-lane sources
-  const int kout = k0 + wk * 16 + n;                               // this lane's A row (output k)
-  int var = 0;
-  if (cs.nz == 1 || kout == 0) var = 1;
-  else if (kout == cs.nz - 1) var = 2;
-  const int aoff = var * cs.px * cs.PL + g - n + 15;               // A: P[var][a][aoff + 4s]
-  int colb[2];
-#pragma unroll
-  for (int nb = 0; nb < 2; ++nb) {
-    const int iout = i0 + wi * 32 + nb * 16 + n;                   // this lane's B column
-    if (cs.nx == 1 || iout == 0) colb[nb] = ELO;
-    else if (iout == cs.nx - 1) colb[nb] = EHI;
-    else colb[nb] = wi * 32 + nb * 16 + n;                         // + a: input i = iout + a - ha
-  }
-  const int rowb = (wk * 16 + g) * cs.RSI;
-
-  // PSF rows of the next plane are prefetched into registers during the
-  // current plane (with their suffix / prefix sums on z-edge tiles)
+  // A[m][r] = p[a][b = r - m] (row offset 15), B = R[(16 wk + g + 4s) RSI + 32 wi + n + a (+16)]
+  const int aoff = g - n + 15;
+  const int boff = (wk * 16 + g) * cs.RSI + wi * 32 + n;
+  // PSF rows of the next plane are prefetched into registers during the current one
   const bool prefetch = cs.px * cs.PL <= 256 * kStagePsf;
   BackPsf pf;
-  if (prefetch && j0 < j1) pf.load(cs, psf, psf_cum, l, j0, kedge);
+  if (prefetch && j0 < j1) pf.load_range(cs, psf, l, j0, 0);
   for (int j = j0; j < j1; ++j) {
     __syncthreads();                                               // region staged / plane consumed
     if (prefetch) {
-      pf.store(cs, P, kedge);
+      pf.store_range(cs, P, 0);
     } else {
       BackPsf one;
       for (int base = 0; base < cs.px * cs.PL; base += 256 * kStagePsf) {
-        one.load_range(cs, psf, psf_cum, l, j, kedge, base);
-        one.store_range(cs, P, kedge, base);
+        one.load_range(cs, psf, l, j, base);
+        one.store_range(cs, P, base);
       }
     }
     __syncthreads();
-    if (prefetch && j + 1 < j1) pf.load(cs, psf, psf_cum, l, j + 1, kedge);
+    if (prefetch && j + 1 < j1) pf.load_range(cs, psf, l, j + 1, 0);
     floatx4 acc[4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f},
                       {0.f, 0.f, 0.f, 0.f}};
-    const float* B0 = R + rowb + colb[0];
-    const float* B1 = R + rowb + colb[1];
     Ops<KS> A, B;
     const float* Pa = P + aoff;
+    const float* Rb = R + boff;
 #pragma unroll
-    for (int s = 0; s < kPrefetch; ++s) A.load_back(s, Pa, B0, B1, 0, cs.PL, cs.RSI);
+    for (int s = 0; s < kPrefetch; ++s) A.load_back(s, Pa, Rb, 0, cs.PL, cs.RSI);
     for (int a = 0; a < cs.px; a += 2) {
       const int a1 = min(a + 1, cs.px - 1), a2 = min(a + 2, cs.px - 1);
       tap_block<KS>(A, B, acc,
-                    [&](Ops<KS>& o, int t) { o.load_back(t, Pa, B0, B1, a, cs.PL, cs.RSI); },
-                    [&](Ops<KS>& o, int t) { o.load_back(t, Pa, B0, B1, a1, cs.PL, cs.RSI); });
+                    [&](Ops<KS>& o, int t) { o.load_back(t, Pa, Rb, a, cs.PL, cs.RSI); },
+                    [&](Ops<KS>& o, int t) { o.load_back(t, Pa, Rb, a1, cs.PL, cs.RSI); });
       if (a + 1 < cs.px)
         tap_block<KS>(B, A, acc,
-                      [&](Ops<KS>& o, int t) { o.load_back(t, Pa, B0, B1, a1, cs.PL, cs.RSI); },
-                      [&](Ops<KS>& o, int t) { o.load_back(t, Pa, B0, B1, a2, cs.PL, cs.RSI); });
+                      [&](Ops<KS>& o, int t) { o.load_back(t, Pa, Rb, a1, cs.PL, cs.RSI); },
+                      [&](Ops<KS>& o, int t) { o.load_back(t, Pa, Rb, a2, cs.PL, cs.RSI); });
     }
     float* out = U + (size_t)lb * cs.nz * cs.ny * cs.nx + (size_t)j * cs.nx;
 #pragma unroll
@@ -433,6 +363,211 @@ __global__ __launch_bounds__(256, 2) void conv_back_mfma(const float* __restrict
         float* row = out + (size_t)k * cs.ny * cs.nx;
         if (i < cs.nx) row[i] = acc[0][vv] + acc[2][vv];
         if (i + 16 < cs.nx) row[i + 16] = acc[1][vv] + acc[3][vv];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- adjoint, edges
+// Exact adjoint on the edge rows and columns of every depth plane of a view,
+// overwriting what conv_back_mfma wrote there.  For an output bin (k', i')
+//   u = sum_{a,b} p[a,b] * sum { v[k][i] : clamp(k - b + hb) = k',
+//                                          clamp(i - a + ha) = i' }.
+// On an edge row k' (0 or nz-1) the k-sum depends only on (b, i), so with
+// Tk[b][i] = sum_{k in K(b)} v[k][i] the plane's row is
+//   u[k'][i'] = sum_a sum_b p[a,b,j] Tk[b][i' + a - ha]   (Tk zero outside),
+// a dense product over b with the depth planes j as rows (M), the bins i' as
+// columns (N), looped over a: no band waste.  Corner bins (i' = 0, nx-1)
+// also fold along i: their B value is sum_{i in I(a)} Tk[b][i].  Edge columns
+// are the same with the roles of (a, i) and (b, k) swapped, rows excluded.
+// grid: (nvb, 4 edge kinds, ceil(ny / 64)); each wave owns 16 planes.
+constexpr int kEdgeNB = 9;   // N-blocks per pass of a wave (8 bins + the corner block)
+
+// Sizes of the edge problem: q = taps contracted in K (along the folded
+// axis), t = taps looped outside, o = output bins along the edge line.
+struct EdgeDims {
+  int nq, hq, nt, ht, nout, nfold, ksteps, nqp, TWp;
+};
+__host__ __device__ inline EdgeDims edge_dims(const ConvShape& cs, bool krow) {
+  EdgeDims d;
+  d.nq = krow ? cs.pz : cs.px;
+  d.hq = krow ? cs.hb : cs.ha;
+  d.nt = krow ? cs.px : cs.pz;
+  d.ht = krow ? cs.ha : cs.hb;
+  d.nout = krow ? cs.nx : cs.nz;
+  d.nfold = krow ? cs.nz : cs.nx;
+  d.ksteps = (d.nq + 3) / 4;
+  d.nqp = 4 * d.ksteps;                                         // K padded with zero rows
+  d.TWp = 16 * ((d.nout + 15) / 16) + 2 * d.ht;                 // columns read by the N-blocks
+  return d;
+}
+
+__global__ __launch_bounds__(256) void conv_back_edges(const float* __restrict__ v,
+                                                       const float* __restrict__ psf,
+                                                       float* __restrict__ U, ConvShape cs,
+                                                       int view0) {
+  extern __shared__ float sm[];
+  const int lb = blockIdx.x, kind = blockIdx.y, l = view0 + lb;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
+  const int jblk = blockIdx.z * 64 + w * 16;                     // this wave's 16 planes
+  const bool krow = kind < 2;                                    // edge row (k) or column (i)
+  // skip duplicates of a size-1 axis (both edges are the same line)
+  if ((kind == 1 && cs.nz == 1) || (kind == 3 && cs.nx == 1)) return;
+  if (!krow && cs.nz <= 2) return;                               // no interior rows to fix
+  const float* vl = v + (size_t)l * cs.nz * cs.nx;
+  EdgeDims d = edge_dims(cs, krow);
+  const int eout = (kind & 1) ? d.nfold - 1 : 0;  // the edge position on the folded axis
+  float* T = sm;                                  // nqp x TWp: folded sums, zero-padded
+  float* Cx = T + d.nqp * d.TWp;                  // nqp x nt x 2: corner sums, then one zero
+  float* As = Cx + (krow ? d.nqp * d.nt * 2 + 1 : 1);  // 256 x nt: per-lane A scratch
+  // The fold sets of an edge lie within hq + 1 lines of it: stage that band of the
+  // projection (lines along the folded axis, bins along the edge) in the A scratch.
+  const int bw = min(d.hq + 1, d.nfold);
+  const int fbase = (eout == 0) ? 0 : d.nfold - bw;              // first folded line staged
+  float* Vb = As;                                                // bw x nout
+  for (int e = threadIdx.x; e < bw * d.nout; e += 256) {
+    const int f = e / d.nout, o = e - f * d.nout;
+    Vb[e] = krow ? vl[(size_t)(fbase + f) * cs.nx + o] : vl[(size_t)o * cs.nx + fbase + f];
+  }
+  if (threadIdx.x == 0) Cx[krow ? d.nqp * d.nt * 2 : 0] = 0.0f;   // zero slot of empty N-blocks
+  __syncthreads();
+
+  // T[q][c] = sum over f in F(q) of v at (fold f, other c - ht), with
+  // F(q) = {f : clamp(f - q + hq) = eout}.  The sets grow monotonically in q
+  // (ascending for eout = 0, descending for eout = nfold-1), so one running
+  // sum per column fills all q with additions only.
+  const bool up = (eout == 0);
+  for (int cc = threadIdx.x; cc < d.TWp; cc += 256) {
+    const int o = cc - d.ht;
+    const bool live = o >= 0 && o < d.nout;
+    float sum = 0.0f;
+    int clo = 0, chi = -1;                                        // current set [clo, chi]
+    for (int step = 0; step < d.nqp; ++step) {
+      const int q = up ? step : d.nqp - 1 - step;
+      int flo = (eout == 0) ? 0 : eout + q - d.hq;
+      int fhi = (eout == d.nfold - 1) ? d.nfold - 1 : eout + q - d.hq;
+      flo = max(flo, 0);
+      fhi = min(fhi, d.nfold - 1);
+      const bool ok = live && q < d.nq && flo <= fhi;
+      if (ok) {
+        if (chi < clo) { clo = fhi + 1; chi = fhi; }            // start empty at the fixed end
+        for (int f = clo - 1; f >= flo; --f) sum += Vb[(f - fbase) * d.nout + o];
+        for (int f = chi + 1; f <= fhi; ++f) sum += Vb[(f - fbase) * d.nout + o];
+        clo = min(clo, flo);
+        chi = max(chi, fhi);
+      }
+      T[q * d.TWp + cc] = ok ? sum : 0.0f;
+    }
+  }
+  __syncthreads();
+  // corners (edge rows only): Cx[q][t][side] = sum over o in O_side(t) of T[q][o + ht];
+  // Cx[nqp nt 2] is a zero read by the other lanes of the corner N-block
+  if (krow) {
+    for (int e = threadIdx.x; e < d.nqp * d.nt * 2 + 1; e += 256) Cx[e] = 0.0f;
+    __syncthreads();
+    for (int e = threadIdx.x; e < 2 * d.nq; e += 256) {
+      const int side = e / d.nq, q = e - side * d.nq;
+      const int oe = side ? d.nout - 1 : 0;
+      const bool oup = (oe == 0);
+      float sum = 0.0f;
+      int clo = 0, chi = -1;
+      for (int step = 0; step < d.nt; ++step) {
+        const int t = oup ? step : d.nt - 1 - step;
+        int olo = (oe == 0) ? 0 : oe + t - d.ht;
+        int ohi = (oe == d.nout - 1) ? d.nout - 1 : oe + t - d.ht;
+        olo = max(olo, 0);
+        ohi = min(ohi, d.nout - 1);
+        if (olo <= ohi) {
+          if (chi < clo) { clo = ohi + 1; chi = ohi; }
+          for (int o = clo - 1; o >= olo; --o) sum += T[q * d.TWp + o + d.ht];
+          for (int o = chi + 1; o <= ohi; ++o) sum += T[q * d.TWp + o + d.ht];
+          clo = min(clo, olo);
+          chi = max(chi, ohi);
+        }
+        if (!(side == 1 && d.nout == 1)) Cx[(q * d.nt + t) * 2 + side] = (olo <= ohi) ? sum : 0.0f;
+      }
+    }
+    __syncthreads();
+  }
+  if (jblk >= cs.ny) return;
+  const int jm = min(jblk + n, cs.ny - 1);                       // A row (plane); clamped rows unused
+  const float* pj = psf + ((size_t)l * cs.ny + jm) * cs.pz * cs.px;
+  float* Al = As + ((size_t)w * 64 + lane) * d.nt;
+  // N-blocks: the bins 0 .. nout-1 (edge bins of rows excluded: corners), then for rows one
+  // block whose lanes 0 and 1 are the two corners
+  const int nblocks = (d.nout + 15) / 16;
+  const int nall = nblocks + (krow ? 1 : 0);
+  for (int nb0 = 0; nb0 < nall; nb0 += kEdgeNB) {
+    floatx4 acc[kEdgeNB];
+#pragma unroll
+    for (int u = 0; u < kEdgeNB; ++u) acc[u] = {0.f, 0.f, 0.f, 0.f};
+    for (int s = 0; s < d.ksteps; ++s) {
+      const int q = 4 * s + g;                                   // K index of this lane
+      // A[m = plane][K = q] = p[a][b]: krow -> (a = t, b = q), else (a = q, b = t)
+      for (int t0 = 0; t0 < d.nt; t0 += 16) {                   // 16 independent loads at a time
+        float r16[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int t = t0 + u;
+          r16[u] = (q < d.nq && t < d.nt) ? (krow ? pj[q * cs.px + t] : pj[t * cs.px + q]) : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (t0 + u < d.nt) Al[t0 + u] = r16[u];
+      }
+      // B source of each N-block for this lane: a pointer advanced by `step` per tap t
+      const float* zero = Cx + (krow ? d.nqp * d.nt * 2 : 0);   // a zero slot
+      const float* bp[kEdgeNB];
+      int bst[kEdgeNB];
+#pragma unroll
+      for (int u = 0; u < kEdgeNB; ++u) {
+        const int blk = nb0 + u;
+        if (blk < nblocks) { bp[u] = T + q * d.TWp + 16 * blk + n; bst[u] = 1; }
+        else if (blk == nblocks && krow && n < 2) { bp[u] = Cx + q * d.nt * 2 + n; bst[u] = 2; }
+        else { bp[u] = zero; bst[u] = 0; }
+      }
+      // pipelined over taps: the operands of t+1 are read while t's MFMAs run
+      float avA, avB, bvA[kEdgeNB], bvB[kEdgeNB];
+      auto load = [&](float& av, float (&bv)[kEdgeNB], int t) {
+        av = Al[t];
+#pragma unroll
+        for (int u = 0; u < kEdgeNB; ++u) bv[u] = bp[u][t * bst[u]];
+      };
+      auto run = [&](float av, const float (&bv)[kEdgeNB]) {
+#pragma unroll
+        for (int u = 0; u < kEdgeNB; ++u) acc[u] = mfma(av, bv[u], acc[u]);
+      };
+      load(avA, bvA, 0);
+      for (int t = 0; t < d.nt; t += 2) {
+        load(avB, bvB, min(t + 1, d.nt - 1));
+        __builtin_amdgcn_sched_barrier(0);
+        run(avA, bvA);
+        __builtin_amdgcn_sched_barrier(0);
+        load(avA, bvA, min(t + 2, d.nt - 1));
+        __builtin_amdgcn_sched_barrier(0);
+        if (t + 1 < d.nt) run(avB, bvB);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    // D[4g + r][n]: plane jblk + 4g + r, output position of (block, lane)
+#pragma unroll
+    for (int u = 0; u < kEdgeNB; ++u) {
+      const int blk = nb0 + u;
+      int o;
+      if (blk < nblocks) {
+        o = 16 * blk + n;
+        if (o >= d.nout || o == 0 || o == d.nout - 1) continue;  // edge bins: corner block / rows
+      } else if (blk == nblocks && krow && n < 2 && !(n == 1 && d.nout == 1)) {
+        o = n ? d.nout - 1 : 0;
+      } else {
+        continue;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = jblk + 4 * g + r;
+        if (j >= cs.ny) continue;
+        const int k = krow ? eout : o, i = krow ? o : eout;
+        U[(((size_t)lb * cs.nz + k) * cs.ny + j) * cs.nx + i] = acc[u][r];
       }
     }
   }
@@ -451,45 +586,18 @@ hipError_t launch_fwd_ks(const ConvShape& cs, const float* W, const float* psf, 
 }
 
 template <int KS>
-hipError_t launch_back_ks(const ConvShape& cs, const float* v, const float* psf,
-                          const float* psf_cum, float* U, int view0, int nvb, hipStream_t s) {
+hipError_t launch_back_ks(const ConvShape& cs, const float* v, const float* psf, float* U,
+                          int view0, int nvb, hipStream_t s) {
   const size_t sm = conv_mfma_lds_bytes(cs, true);
   hipError_t e = hipFuncSetAttribute((const void*)conv_back_mfma<KS>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
   if (e != hipSuccess) return e;
   dim3 grid(cs.tiles_k * cs.tiles_i * cs.nchunk * nvb);
-  hipLaunchKernelGGL(conv_back_mfma<KS>, grid, dim3(256), sm, s, v, psf, psf_cum, U, cs, view0,
-                     nvb);
+  hipLaunchKernelGGL(conv_back_mfma<KS>, grid, dim3(256), sm, s, v, psf, U, cs, view0, nvb);
   return hipGetLastError();
-}
-
-// grid (ceil(px/64), ny, nview): suffix and prefix sums of every PSF row along b.
-__global__ void psf_cum_kernel(const float* __restrict__ psf, float* __restrict__ out, int ny,
-                               int pz, int px, long long total) {
-  const int a = blockIdx.x * 64 + threadIdx.x;
-  if (a >= px) return;
-  const size_t base = ((size_t)blockIdx.z * ny + blockIdx.y) * pz * px + a;
-  float run = 0.0f;
-  for (int b = pz - 1; b >= 0; --b) {
-    run += psf[base + (size_t)b * px];
-    out[base + (size_t)b * px] = run;
-  }
-  run = 0.0f;
-  for (int b = 0; b < pz; ++b) {
-    run += psf[base + (size_t)b * px];
-    out[total + base + (size_t)b * px] = run;
-  }
 }
 
 }  // namespace
-
-hipError_t launch_psf_cum(const Plan& p, float* out, hipStream_t s) {
-  const spect_geom& g = p.g;
-  dim3 grid((g.px + 63) / 64, g.ny, g.nview);
-  hipLaunchKernelGGL(psf_cum_kernel, grid, dim3(64), 0, s, p.psf, out, g.ny, g.pz, g.px,
-                     (long long)g.nview * g.ny * g.pz * g.px);
-  return hipGetLastError();
-}
 
 // Row stride of a staged region: >= cols, and = 16 or 48 (mod 64) so that the
 // four 16-lane row groups of a B read fall in distinct LDS banks.
@@ -500,7 +608,7 @@ static int region_stride(int cols) {
 }
 
 size_t conv_mfma_lds_bytes(const ConvShape& cs, bool back) {
-  return back ? (size_t)(cs.RK * cs.RSI_back + 3 * cs.px * cs.PL) * sizeof(float)
+  return back ? (size_t)(cs.RK * cs.RSI_back + cs.px * cs.PL) * sizeof(float)
               : (size_t)(cs.RK * cs.RSI + cs.px * cs.PL) * sizeof(float);
 }
 
@@ -508,7 +616,8 @@ bool conv_mfma_supported(const spect_geom& g) {
   const int ks = (15 + g.pz + 3) / 4;
   if (ks < 4 || ks > kMaxMfmaKSteps) return false;
   ConvShape cs = make_conv_shape(g, kFwdJChunk, kBackJChunk);
-  return conv_mfma_lds_bytes(cs, false) <= kLdsBytes && conv_mfma_lds_bytes(cs, true) <= kLdsBytes;
+  return conv_mfma_lds_bytes(cs, false) <= kLdsBytes && conv_mfma_lds_bytes(cs, true) <= kLdsBytes &&
+         conv_edges_lds_bytes(cs) <= kLdsBytes;
 }
 
 ConvShape make_conv_shape(const spect_geom& g, int jc_fwd, int jc_back) {
@@ -523,14 +632,13 @@ ConvShape make_conv_shape(const spect_geom& g, int jc_fwd, int jc_back) {
   cs.RK = 16 * (cs.WK - 1) + 4 * cs.KS;        // rows read by the last k-step of the last wave
   cs.RI = 32 * cs.WI + g.px - 1;
   cs.RSI = region_stride(cs.RI);
-  cs.RSI_back = region_stride(cs.RI + 2 * g.px);
+  cs.RSI_back = region_stride(cs.RI);
   cs.PL = 4 * cs.KS + 15;
   cs.Z = 4 * cs.KS - 1 - 2 * cs.hb;
   cs.jc = jc_fwd;
   cs.nchunk = (g.ny + jc_fwd - 1) / jc_fwd;
   cs.jc_back = jc_back;
   cs.nchunk_back = (g.ny + jc_back - 1) / jc_back;
-  cs.nview_ny_pz_px = (long long)g.nview * g.ny * g.pz * g.px;
   return cs;
 }
 
@@ -581,7 +689,7 @@ hipError_t launch_conv_back_mfma(const Plan& p, const float* v, float* U, int vi
   cs.jc = cs.jc_back;
   cs.nchunk = cs.nchunk_back;
   switch (cs.KS) {
-#define CASE(K) case K: return launch_back_ks<K>(cs, v, p.psf, p.psf_cum, U, view0, nvb, s);
+#define CASE(K) case K: return launch_back_ks<K>(cs, v, p.psf, U, view0, nvb, s);
     SPECT_KS_CASES(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;
@@ -591,6 +699,30 @@ hipError_t launch_conv_back_mfma(const Plan& p, const float* v, float* U, int vi
 }  // namespace spect
 
 namespace spect {
+size_t conv_edges_lds_bytes(const ConvShape& cs) {
+  const EdgeDims r = edge_dims(cs, true), c = edge_dims(cs, false);
+  auto scratch = [](const EdgeDims& e) {
+    const size_t band = (size_t)(e.hq + 1 < e.nfold ? e.hq + 1 : e.nfold) * e.nout;
+    const size_t lanes = 256 * (size_t)e.nt;
+    return band > lanes ? band : lanes;
+  };
+  const size_t rows = (size_t)r.nqp * r.TWp + (size_t)r.nqp * r.nt * 2 + 1 + scratch(r);
+  const size_t cols = (size_t)c.nqp * c.TWp + 1 + scratch(c);
+  return (rows > cols ? rows : cols) * sizeof(float);
+}
+
+hipError_t launch_conv_back_edges(const Plan& p, const float* v, float* U, int view0, int nvb,
+                                  hipStream_t s) {
+  const ConvShape& cs = p.conv;
+  const size_t sm = conv_edges_lds_bytes(cs);
+  hipError_t e = hipFuncSetAttribute((const void*)conv_back_edges,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+  if (e != hipSuccess) return e;
+  dim3 grid(nvb, 4, (cs.ny + 63) / 64);
+  hipLaunchKernelGGL(conv_back_edges, grid, dim3(256), sm, s, v, p.psf, U, cs, view0);
+  return hipGetLastError();
+}
+
 void tune_conv_chunks(ConvShape& cs, int views) {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||

@@ -41,7 +41,6 @@ struct ConvShape {
   int PL, Z;            // PSF row length in LDS and its zero offset (forward)
   int jc, nchunk;       // forward depth chunk
   int jc_back, nchunk_back;
-  long long nview_ny_pz_px;  // size of one PSF array (offset of the prefix sums)
 };
 
 // Per-view geometry tables, on the device (inside the workspace).
@@ -64,7 +63,6 @@ struct Layout {
   size_t back_partial;  // kBackGroups * N floats
   size_t mubar_cache;   // nview * N floats (only with SPECT_CACHE_MUBAR)
   size_t mubar_batch;   // view_batch * N floats (only without SPECT_CACHE_MUBAR)
-  size_t psf_cum;       // 2 * nview * ny * pz * px floats: suffix, prefix sums along b
   size_t em_proj;       // nview * nz * nx floats
   size_t em_vol;        // N floats
   size_t total;
@@ -73,7 +71,7 @@ struct Layout {
 // Kernel identities for the optional per-launch timing.
 enum KernelId {
   K_MUBAR = 0, K_ROT_FWD, K_CONV_FWD, K_FWD_REDUCE, K_CONV_BACK, K_ROT_BACK,
-  K_BACK_REDUCE, K_EM_RATIO, K_EM_UPDATE, K_COUNT
+  K_BACK_REDUCE, K_EM_RATIO, K_EM_UPDATE, K_CONV_BACK_EDGES, K_COUNT
 };
 extern const char* const kKernelNames[K_COUNT];
 
@@ -94,7 +92,6 @@ struct Plan {
   Tables tab;
   const float* mubar;   // cache or nullptr
   float* mubar_batch;   // per-batch attenuation factors when not cached
-  const float* psf_cum; // suffix / prefix sums of the PSF along b
   bool use_mfma;        // MFMA convolution path (else the direct kernels)
   ConvShape conv;
   Profiler* prof;       // non-null while spect_profile_start is active
@@ -127,17 +124,19 @@ ConvShape make_conv_shape(const spect_geom& g, int jc_fwd, int jc_back);
 // launch from the device's CU count and the kernels' occupancy.
 void tune_conv_chunks(ConvShape& cs, int views);
 size_t conv_mfma_lds_bytes(const ConvShape& cs, bool back);
+size_t conv_edges_lds_bytes(const ConvShape& cs);
 
 // ---- kernel launchers (return hipGetLastError() of the launch) ----
 hipError_t launch_mubar(const Plan& p, float* out, int view0, int nviews, int out_view0,
                         hipStream_t s);
-hipError_t launch_psf_cum(const Plan& p, float* out, hipStream_t s);
 hipError_t launch_rot_fwd(const Plan& p, const float* x, const float* mb, int mb_off, float* W,
                           int view0, int nvb, hipStream_t s);
 hipError_t launch_conv_fwd_mfma(const Plan& p, const float* W, float* partial, int view0, int nvb,
                                 hipStream_t s);
 hipError_t launch_conv_back_mfma(const Plan& p, const float* v, float* U, int view0, int nvb,
                                  hipStream_t s);
+hipError_t launch_conv_back_edges(const Plan& p, const float* v, float* U, int view0, int nvb,
+                                  hipStream_t s);
 hipError_t launch_conv_fwd(const Plan& p, const float* W, float* partial, int view0, int nvb,
                            hipStream_t s);
 hipError_t launch_fwd_reduce(const Plan& p, const float* partial, float* v, int view0, int nvb,

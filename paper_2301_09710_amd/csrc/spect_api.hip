@@ -50,7 +50,7 @@ spect_status compute_layout(const spect_geom& g, Layout* lay, int* view_batch, i
   const bool cache = (g.flags & SPECT_CACHE_MUBAR) != 0;
   lay->mubar_cache = cache ? take((size_t)g.nview * N * sizeof(float)) : 0;
   lay->mubar_batch = cache ? 0 : take((size_t)vb * N * sizeof(float));
-  lay->psf_cum = take((size_t)2 * g.nview * g.ny * g.pz * g.px * sizeof(float));
+
   lay->em_proj = take(M * sizeof(float));
   lay->em_vol = take(N * sizeof(float));
   lay->total = off;
@@ -101,7 +101,8 @@ static void fill_tables(const spect_geom& g, int32_t* q, int32_t* off, float2* w
 namespace spect {
 const char* const kKernelNames[K_COUNT] = {"mubar", "rot_fwd",  "conv_fwd",
                                            "fwd_reduce",  "conv_back", "rot_back",
-                                           "back_reduce", "em_ratio", "em_update"};
+                                           "back_reduce", "em_ratio", "em_update",
+                                           "conv_back_edges"};
 
 static void profiler_free(Profiler* pr) {
   if (!pr) return;
@@ -196,9 +197,6 @@ spect_status spect_plan_create(spect_plan* out, const spect_geom* g, const float
     tune_conv_chunks(p->conv, g->nview);   // independent of view_batch: same sums
     p->nchunk = p->conv.nchunk;          // forward partial sums per view
   }
-  float* cum = reinterpret_cast<float*>(p->ws + lay.psf_cum);
-  p->psf_cum = cum;
-  if (e == hipSuccess) e = timed(*p, K_MUBAR, stream, [&] { return launch_psf_cum(*p, cum, stream); });
   if (g->flags & SPECT_CACHE_MUBAR) {
     float* cache = reinterpret_cast<float*>(p->ws + lay.mubar_cache);
     if (e == hipSuccess)
@@ -276,6 +274,10 @@ static spect_status back_impl(const Plan& p, const float* v, float* x, hipStream
           return p.use_mfma ? launch_conv_back_mfma(p, v, U, v0, nvb, s)
                             : launch_conv_back(p, v, U, v0, nvb, s);
         }) != hipSuccess)
+      return SPECT_ERR_HIP;
+    if (p.use_mfma &&
+        timed(p, K_CONV_BACK_EDGES, s,
+              [&] { return launch_conv_back_edges(p, v, U, v0, nvb, s); }) != hipSuccess)
       return SPECT_ERR_HIP;
     const float* mb;
     int mb_off;
