@@ -10,8 +10,9 @@
 
 namespace spect {
 
-// Largest in-plane size for which two z-slices (n rows of stride n + 8 (mod
-// 16) floats) and the per-view tables fit in the 160 KiB LDS of a gfx950 CU.
+// Largest in-plane size for which two z-slices (n rows of stride n + 1
+// floats), the scan segments and the per-view tables fit in the 160 KiB LDS
+// of a gfx950 CU.
 constexpr int kMaxLdsN = 136;
 // Threads per workgroup of the rotation kernels.
 constexpr int kRotThreads = 1024;
@@ -125,6 +126,7 @@ ConvShape make_conv_shape(const spect_geom& g, int jc_fwd, int jc_back);
 void tune_conv_chunks(ConvShape& cs, int views);
 size_t conv_mfma_lds_bytes(const ConvShape& cs, bool back);
 size_t conv_edges_lds_bytes(const ConvShape& cs);
+size_t rotation_lds_bytes(int n);
 
 // ---- kernel launchers (return hipGetLastError() of the launch) ----
 hipError_t launch_mubar(const Plan& p, float* out, int view0, int nviews, int out_view0,

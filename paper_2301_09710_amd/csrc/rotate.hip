@@ -3,44 +3,32 @@
 // shears, form the attenuation factor of Eq. (1), weight; and the exact
 // transpose of those steps accumulated over views (Alg. 2).
 //
-// Design: one workgroup owns one z-slice (n x n, n = nx = ny) held in LDS as
-// rows j of stride S floats and loops over several views.  The three
-// passes are evaluated as one fused gather per output pixel: pass 3 needs two
-// pass-2 values, each needing two pass-1 values, each needing two pixels of
-// the quarter-turned slice -- at most 8 LDS reads and 14 two-tap blends,
-// with the pass semantics kept exactly (every intermediate sample outside
-// [0, n) is zero, as in a pass over the whole slice).  A wave owns 8 x 8 pixel
-// tiles and the LDS row stride S is 8 (mod 16) floats: the gathers of a
-// rotated tile then spread over the 64 LDS banks for every angle (a wave
-// covering one row would read along a sheared line, which some angle maps
-// onto one bank).  The quarter turn is an
-// affine remapping of the LDS address, so the slice is staged once per
-// workgroup, unrotated, whatever the view.  The transpose uses the same
-// tables with the taps mirrored (out[q] = w.x in[q - o] + w.y in[q - o - 1]),
-// applies the passes in reverse order and the inverse quarter turn last.
+// One workgroup owns one z-slice (n x n, n = nx = ny) and loops over several
+// views.  Each pass is a two-tap gather along rows or columns with per-line
+// offset and weights from the host tables:
+//   forward   out[q] = w.x in[q + o] + w.y in[q + o + 1]
+//   transpose out[q] = w.x in[q - o] + w.y in[q - o - 1]
+// with every sample outside [0, n) equal to zero.  The quarter turn P_m is
+// an affine remapping of the LDS address of the staged, unrotated slice, so
+// the forward kernels stage their input once per workgroup whatever the view;
+// the transpose applies P_m^T last, on the way into the accumulators.
+//
+// The attenuation and transpose kernels run the passes one after another in
+// LDS, on slices of odd row stride n + 1 (row passes, column passes and
+// quarter-turned reads are then free of bank conflicts), with each wave
+// owning whole lines.  The forward rotation fuses the three passes into one
+// gather per pixel from a single staged slice (see rot_fwd_kernel).
+#include <type_traits>
+
 #include "internal.h"
 
 namespace spect {
 namespace {
 
 constexpr int NT = kRotThreads;
-constexpr int NWAVE = NT / 64;
-constexpr int TPR_MAX = (kMaxLdsN + 7) / 8;                 // 8x8 tiles per row
-constexpr int RMAX = (TPR_MAX * TPR_MAX + NWAVE - 1) / NWAVE; // tiles (pixels) per lane
+constexpr int NW = NT / 64;                                   // waves per workgroup
 
-// LDS row stride of a slice: >= n and = 8 (mod 16).
-__host__ __device__ __forceinline__ int slice_stride(int n) { return n + ((8 - n % 16) + 16) % 16; }
-
-// Pixel of lane `lane`, iteration r: 8x8 tile (w + NWAVE r) of the slice.
-__device__ __forceinline__ bool tile_pixel(int n, int r, int& i, int& j) {
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int tpr = (n + 7) >> 3;
-  const int tile = w + NWAVE * r;
-  const int tj = tile / tpr, ti = tile - tj * tpr;
-  i = 8 * ti + (lane & 7);
-  j = 8 * tj + (lane >> 3);
-  return tj < tpr && i < n && j < n;
-}
+__host__ __device__ __forceinline__ int slice_stride(int n) { return n + 1; }
 
 // Position (di, dj) that pixel (i, j) takes under P_m, the gather
 // out(p) = in(R(m*90deg)^-1 (p - c) + c) with R acting on (i, j).
@@ -69,70 +57,6 @@ struct ViewTab {          // per-view tables in LDS
 
 __device__ __forceinline__ bool inside(int q, int n) { return (unsigned)q < (unsigned)n; }
 
-// Forward: value of (S3 S2 S1 P_m x)(i, j) from the unrotated slice X.
-__device__ __forceinline__ float rotated_pixel(const float* X, int n, const QAddr& qa,
-                                               const ViewTab& t, int i, int j) {
-  float f3 = 0.0f;
-  const int o3 = t.o13[j];
-  const float2 w3 = t.w13[j];
-#pragma unroll
-  for (int t3 = 0; t3 < 2; ++t3) {
-    const int i2 = i + o3 + t3;
-    if (!inside(i2, n)) continue;
-    const int o2 = t.o2[i2];
-    const float2 w2 = t.w2[i2];
-    float f2 = 0.0f;
-#pragma unroll
-    for (int t2 = 0; t2 < 2; ++t2) {
-      const int j1 = j + o2 + t2;
-      if (!inside(j1, n)) continue;
-      const int o1 = t.o13[j1];
-      const float2 w1 = t.w13[j1];
-      const int ia = i2 + o1, ib = i2 + o1 + 1;
-      const float a = inside(ia, n) ? X[qa.base + qa.ci * ia + qa.cj * j1] : 0.0f;
-      const float b = inside(ib, n) ? X[qa.base + qa.ci * ib + qa.cj * j1] : 0.0f;
-      const float f1 = w1.x * a + w1.y * b;
-      f2 += (t2 == 0 ? w2.x : w2.y) * f1;
-    }
-    f3 += (t3 == 0 ? w3.x : w3.y) * f2;
-  }
-  return f3;
-}
-
-// Transpose: value of (S1^T S2^T S3^T g)(q, r) from g stored as G[r][q].
-__device__ __forceinline__ float rotated_T_pixel(const float* G, int n, int S, const ViewTab& t,
-                                                 int q, int r) {
-  // pass-1 transpose along i for row r
-  const int o1 = t.o13[r];
-  const float2 w1 = t.w13[r];
-  float h1 = 0.0f;
-#pragma unroll
-  for (int t1 = 0; t1 < 2; ++t1) {
-    const int q2 = q - o1 - t1;
-    if (!inside(q2, n)) continue;
-    // pass-2 transpose along j for column q2
-    const int o2 = t.o2[q2];
-    const float2 w2 = t.w2[q2];
-    float h2 = 0.0f;
-#pragma unroll
-    for (int t2 = 0; t2 < 2; ++t2) {
-      const int r3 = r - o2 - t2;
-      if (!inside(r3, n)) continue;
-      // pass-3 transpose along i for row r3
-      const int o3 = t.o13[r3];
-      const float2 w3 = t.w13[r3];
-      const int qa = q2 - o3, qb = q2 - o3 - 1;
-      const float a = inside(qa, n) ? G[r3 * S + qa] : 0.0f;
-      const float b = inside(qb, n) ? G[r3 * S + qb] : 0.0f;
-      const float h3 = w3.x * a + w3.y * b;
-      h2 += (t2 == 0 ? w2.x : w2.y) * h3;
-    }
-    h1 += (t1 == 0 ? w1.x : w1.y) * h2;
-  }
-  return h1;
-}
-
-// LDS carve-up: slice buffers of n*S floats, then the tables of one view.
 __device__ __forceinline__ ViewTab carve_tab(float* after, int n) {
   ViewTab t;
   t.o13 = reinterpret_cast<int*>(after);
@@ -158,9 +82,120 @@ __device__ __forceinline__ void stage_slice(float* X, const float* __restrict__ 
   }
 }
 
+// Line ownership: wave w owns lines w, w + NW, ...; lane l covers positions
+// l, l + 64, ... (EPL = elements per lane) of a line.
+__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// pass 1 (forward) read from the unrotated slice X through the quarter turn
+__device__ __forceinline__ float pass1_px(const float* X, int n, const QAddr& qa,
+                                          const ViewTab& t, int i, int j) {
+  const int o = t.o13[j];
+  const float2 w = t.w13[j];
+  const int ia = i + o, ib = ia + 1;
+  const float a = inside(ia, n) ? X[qa.base + qa.ci * ia + qa.cj * j] : 0.0f;
+  const float b = inside(ib, n) ? X[qa.base + qa.ci * ib + qa.cj * j] : 0.0f;
+  return w.x * a + w.y * b;
+}
+
+// row pass (along i) on Y: forward (kSgn = +1) or transpose (kSgn = -1)
+template <int kSgn>
+__device__ __forceinline__ float row_px(const float* Y, int n, int S, const ViewTab& t, int i,
+                                        int j) {
+  const int o = t.o13[j];
+  const float2 w = t.w13[j];
+  const int ia = i + kSgn * o, ib = ia + kSgn;
+  const float a = inside(ia, n) ? Y[j * S + ia] : 0.0f;
+  const float b = inside(ib, n) ? Y[j * S + ib] : 0.0f;
+  return w.x * a + w.y * b;
+}
+
+// column pass (along j) on Y: forward or transpose
+template <int kSgn>
+__device__ __forceinline__ float col_px(const float* Y, int n, int S, const ViewTab& t, int i,
+                                        int j) {
+  const int o = t.o2[i];
+  const float2 w = t.w2[i];
+  const int ja = j + kSgn * o, jb = ja + kSgn;
+  const float a = inside(ja, n) ? Y[ja * S + i] : 0.0f;
+  const float b = inside(jb, n) ? Y[jb * S + i] : 0.0f;
+  return w.x * a + w.y * b;
+}
+
+// In-place pass over the lines a wave owns: each line is read completely
+// (every lane's taps) before any lane writes it, so no workgroup barrier is
+// needed inside the pass; EPL values per lane are held in registers.
+template <int kSgn, bool kRows, int EPL>
+__device__ __forceinline__ void line_pass(float* Y, int n, int S, const ViewTab& t) {
+  const int lane = lane_id();
+  for (int line = wave_id(); line < n; line += NW) {
+    float v[EPL];
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      const int q = lane + 64 * e;
+      v[e] = (q < n) ? (kRows ? row_px<kSgn>(Y, n, S, t, q, line) : col_px<kSgn>(Y, n, S, t, line, q))
+                     : 0.0f;
+    }
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      const int q = lane + 64 * e;
+      if (q < n) Y[kRows ? line * S + q : q * S + line] = v[e];
+    }
+  }
+}
+
+// Passes 1 and 2 of R_l X into Y (and pass 3 when kAllThree; otherwise the
+// caller fuses pass 3 with its output).  Ends with Y complete (barrier).
+template <bool kAllThree, int EPL>
+__device__ __forceinline__ void rotate_into(float* Y, const float* X, int n, int S, int m,
+                                            const ViewTab& t) {
+  const QAddr qa = quarter_addr(m, n, S);
+  const int lane = lane_id();
+  for (int j = wave_id(); j < n; j += NW)
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      const int i = lane + 64 * e;
+      if (i < n) Y[j * S + i] = pass1_px(X, n, qa, t, i, j);
+    }
+  __syncthreads();
+  line_pass<1, false, EPL>(Y, n, S, t);
+  __syncthreads();
+  if (kAllThree) {
+    line_pass<1, true, EPL>(Y, n, S, t);
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- Eq. (1)
-// grid (nz, ceil(nviews / VG)): for slice k and views [v0 + g*VG, ...):
-// out[(l - out_view0)][k] = mubar of view l.  LDS: mu slice, rotated buffer, tables.
+// Column suffix scan of a rotated attenuation slice in Y (detector beyond
+// j = n-1): kScanSeg threads per column each own a run of rows; run sums in
+// FP64 are combined through LDS, then every thread writes its run.
+constexpr int kScanSeg = 8;
+
+__device__ void mubar_scan(float* Y, double* seg, int n, int S, double dy) {
+  const int per = (n + kScanSeg - 1) / kScanSeg;
+  const int sgi = threadIdx.x % kScanSeg;
+  const int j0 = sgi * per, j1 = min(n, j0 + per);
+  for (int col = threadIdx.x / kScanSeg; col < n; col += NT / kScanSeg) {
+    double own = 0.0;
+    for (int j = j0; j < j1; ++j) own += (double)Y[j * S + col];
+    seg[col * kScanSeg + sgi] = own;
+  }
+  __syncthreads();
+  for (int col = threadIdx.x / kScanSeg; col < n; col += NT / kScanSeg) {
+    double run = 0.0;                                   // everything beyond this run
+    for (int s2 = sgi + 1; s2 < kScanSeg; ++s2) run += seg[col * kScanSeg + s2];
+    for (int j = j1 - 1; j >= j0; --j) {
+      const float mu = Y[j * S + col];
+      Y[j * S + col] = (float)exp(-dy * (0.5 * (double)mu + run));
+      run += (double)mu;
+    }
+  }
+  __syncthreads();
+}
+
+// grid (nz, ceil(nviews / VG)): out[(l - out_view0)][k] = mubar of view l.
+template <int EPL>
 __global__ __launch_bounds__(NT) void mubar_kernel(const float* __restrict__ mu,
                                                    float* __restrict__ out, int n, int nz,
                                                    int view0, int nviews, int VG, int out_view0,
@@ -168,35 +203,20 @@ __global__ __launch_bounds__(NT) void mubar_kernel(const float* __restrict__ mu,
   extern __shared__ float smem[];
   const int S = slice_stride(n);
   float* X = smem;
-  float* Y = smem + n * S;
-  ViewTab t = carve_tab(Y + n * S, n);
+  float* Y = X + n * S;
+  double* seg = reinterpret_cast<double*>(Y + n * S);   // offset 2 n (n+1) floats: 8-byte aligned
+  ViewTab t = carve_tab(reinterpret_cast<float*>(seg + kScanSeg * n), n);
   const int k = blockIdx.x;
   const size_t nn = (size_t)n * n;
   stage_slice(X, mu + (size_t)k * nn, n, S);
   const int lb0 = blockIdx.y * VG, lb1 = min(nviews, lb0 + VG);
   for (int lb = lb0; lb < lb1; ++lb) {
     const int l = view0 + lb;
-    __syncthreads();                                   // X staged / previous view done
+    __syncthreads();                                   // X staged / previous view written out
     load_tab(tab, l, n, t);
     __syncthreads();
-    const QAddr qa = quarter_addr(tab.quarter[l], n, S);
-#pragma unroll
-    for (int r = 0; r < RMAX; ++r) {
-      int i, j;
-      if (tile_pixel(n, r, i, j)) Y[j * S + i] = rotated_pixel(X, n, qa, t, i, j);
-    }
-    __syncthreads();
-    // suffix scan along j for every column i (detector beyond j = n-1), FP64
-    if (threadIdx.x < n) {
-      const int i = threadIdx.x;
-      double run = 0.0;
-      for (int j = n - 1; j >= 0; --j) {
-        const float m = Y[j * S + i];
-        Y[j * S + i] = (float)exp(-dy * (0.5 * (double)m + run));
-        run += (double)m;
-      }
-    }
-    __syncthreads();
+    rotate_into<true, EPL>(Y, X, n, S, tab.quarter[l], t);
+    mubar_scan(Y, seg, n, S, dy);
     float* dst = out + ((size_t)(l - out_view0) * nz + k) * nn;
     for (int p = threadIdx.x; p < n * n; p += NT) {
       const int j = p / n, i = p - j * n;
@@ -206,14 +226,66 @@ __global__ __launch_bounds__(NT) void mubar_kernel(const float* __restrict__ mu,
 }
 
 // ---------------------------------------------------------------- forward
+// The forward kernel keeps a single staged slice and evaluates the three
+// passes as one fused gather per output pixel: pass 3 needs two pass-2
+// values, each needing two pass-1 values, each needing two quarter-turned
+// pixels (at most 8 LDS reads and 14 two-tap blends), with every intermediate
+// sample outside [0, n) equal to zero exactly as in a pass over the whole
+// slice.  One slice in LDS lets two workgroups share a CU.  A wave owns 8 x 8
+// pixel tiles and the slice row stride is 8 (mod 16) floats, so the gathers of
+// a rotated tile spread over the LDS banks for every angle.
+__host__ __device__ __forceinline__ int gather_stride(int n) { return n + ((8 - n % 16) + 16) % 16; }
+
+// Pixel of this lane in iteration r: 8x8 tile (w + NW r) of the slice.
+__device__ __forceinline__ bool tile_pixel(int n, int r, int& i, int& j) {
+  const int tpr = (n + 7) >> 3;
+  const int tile = wave_id() + NW * r;
+  const int tj = tile / tpr, ti = tile - tj * tpr;
+  i = 8 * ti + (lane_id() & 7);
+  j = 8 * tj + (lane_id() >> 3);
+  return tj < tpr && i < n && j < n;
+}
+
+// (S3 S2 S1 P_m x)(i, j) from the unrotated slice X.
+__device__ __forceinline__ float rotated_pixel(const float* X, int n, const QAddr& qa,
+                                               const ViewTab& t, int i, int j) {
+  float f3 = 0.0f;
+  const int o3 = t.o13[j];
+  const float2 w3 = t.w13[j];
+#pragma unroll
+  for (int t3 = 0; t3 < 2; ++t3) {
+    const int i2 = i + o3 + t3;
+    if (!inside(i2, n)) continue;
+    const int o2 = t.o2[i2];
+    const float2 w2 = t.w2[i2];
+    float f2 = 0.0f;
+#pragma unroll
+    for (int t2 = 0; t2 < 2; ++t2) {
+      const int j1 = j + o2 + t2;
+      if (!inside(j1, n)) continue;
+      const int o1 = t.o13[j1];
+      const float2 w1 = t.w13[j1];
+      const int ia = i2 + o1, ib = ia + 1;
+      const float a = inside(ia, n) ? X[qa.base + qa.ci * ia + qa.cj * j1] : 0.0f;
+      const float b = inside(ib, n) ? X[qa.base + qa.ci * ib + qa.cj * j1] : 0.0f;
+      f2 += (t2 == 0 ? w2.x : w2.y) * (w1.x * a + w1.y * b);
+    }
+    f3 += (t3 == 0 ? w3.x : w3.y) * f2;
+  }
+  return f3;
+}
+
 // grid (nz, ceil(nvb / VG)): W[lb][k] = (R_l x)[k] * mubar_l[k] for the views
-// lb of this group; mubar of view lb is at mb + (lb + mb_off) * N.
+// lb of this group; mubar of view lb is at mb + (lb + mb_off) * N.  RM = 8x8
+// tiles per wave, visited kCh at a time.
+constexpr int kCh = 4;
+template <int RM>
 __global__ __launch_bounds__(NT) void rot_fwd_kernel(const float* __restrict__ x,
                                                      const float* __restrict__ mb, int mb_off,
                                                      float* __restrict__ W, int n, int nz,
                                                      int view0, int nvb, int VG, Tables tab) {
   extern __shared__ float smem[];
-  const int S = slice_stride(n);
+  const int S = gather_stride(n);
   float* X = smem;
   ViewTab t = carve_tab(X + n * S, n);
   const int k = blockIdx.x;
@@ -223,21 +295,35 @@ __global__ __launch_bounds__(NT) void rot_fwd_kernel(const float* __restrict__ x
   for (int lb = lb0; lb < lb1; ++lb) {
     const int l = view0 + lb;
     const float* mbs = mb + (size_t)(lb + mb_off) * N + (size_t)k * nn;
-    float att[RMAX];                       // attenuation factors, loaded ahead of the gathers
+    float* dst = W + (size_t)lb * N + (size_t)k * nn;
+    // attenuation factors of the next kCh tiles are loaded while the current
+    // ones are gathered
+    float att[kCh];
 #pragma unroll
-    for (int r = 0; r < RMAX; ++r) {
+    for (int c = 0; c < kCh; ++c) {
       int i, j;
-      att[r] = tile_pixel(n, r, i, j) ? mbs[j * n + i] : 0.0f;
+      att[c] = tile_pixel(n, c, i, j) ? mbs[j * n + i] : 0.0f;
     }
-    __syncthreads();
+    __syncthreads();                       // X staged / previous view's readers done
     load_tab(tab, l, n, t);
     __syncthreads();
     const QAddr qa = quarter_addr(tab.quarter[l], n, S);
-    float* dst = W + (size_t)lb * N + (size_t)k * nn;
+#pragma unroll 1
+    for (int r0 = 0; r0 < RM; r0 += kCh) {
+      float nxt[kCh];
 #pragma unroll
-    for (int r = 0; r < RMAX; ++r) {
-      int i, j;
-      if (tile_pixel(n, r, i, j)) dst[j * n + i] = rotated_pixel(X, n, qa, t, i, j) * att[r];
+      for (int c = 0; c < kCh; ++c) {
+        int i, j;
+        nxt[c] = (r0 + kCh + c < RM && tile_pixel(n, r0 + kCh + c, i, j)) ? mbs[j * n + i] : 0.0f;
+      }
+#pragma unroll
+      for (int c = 0; c < kCh; ++c) {
+        int i, j;
+        if (r0 + c < RM && tile_pixel(n, r0 + c, i, j))
+          dst[j * n + i] = rotated_pixel(X, n, qa, t, i, j) * att[c];
+      }
+#pragma unroll
+      for (int c = 0; c < kCh; ++c) att[c] = nxt[c];
     }
   }
 }
@@ -245,6 +331,8 @@ __global__ __launch_bounds__(NT) void rot_fwd_kernel(const float* __restrict__ x
 // ---------------------------------------------------------------- back
 // grid (nz, G): partial[g][k] (+)= sum over views lb = g, g+G, ... of
 //   P_m^T S1^T S2^T S3^T (U[lb][k] * mubar_l[k]).
+// Output pixel (i, j) accumulates in wave j mod NW, lane i mod 64.
+template <int EPL, int LPW>
 __global__ __launch_bounds__(NT) void rot_back_kernel(const float* __restrict__ U,
                                                       const float* __restrict__ mb, int mb_off,
                                                       float* __restrict__ partial, int n, int nz,
@@ -252,13 +340,15 @@ __global__ __launch_bounds__(NT) void rot_back_kernel(const float* __restrict__ 
                                                       Tables tab) {
   extern __shared__ float smem[];
   const int S = slice_stride(n);
-  float* Gs = smem;
-  ViewTab t = carve_tab(Gs + n * S, n);
-  const int k = blockIdx.x, g = blockIdx.y;
+  float* Y = smem;
+  ViewTab t = carve_tab(Y + n * S, n);
+  const int k = blockIdx.x, g = blockIdx.y, lane = lane_id(), w = wave_id();
   const size_t nn = (size_t)n * n, N = nn * nz;
-  float acc[RMAX];
+  float acc[LPW][EPL];
 #pragma unroll
-  for (int r = 0; r < RMAX; ++r) acc[r] = 0.0f;
+  for (int r = 0; r < LPW; ++r)
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) acc[r][e] = 0.0f;
   for (int lb = g; lb < nvb; lb += G) {
     const int l = view0 + lb;
     const int m = tab.quarter[l];
@@ -268,24 +358,36 @@ __global__ __launch_bounds__(NT) void rot_back_kernel(const float* __restrict__ 
     const float* mbs = mb + (size_t)(lb + mb_off) * N + (size_t)k * nn;
     for (int p = threadIdx.x; p < n * n; p += NT) {
       const int j = p / n, i = p - j * n;
-      Gs[j * S + i] = src[p] * mbs[p];
+      Y[j * S + i] = src[p] * mbs[p];
     }
     __syncthreads();
+    line_pass<-1, true, EPL>(Y, n, S, t);              // pass 3 transpose
+    __syncthreads();
+    line_pass<-1, false, EPL>(Y, n, S, t);             // pass 2 transpose
+    __syncthreads();
 #pragma unroll
-    for (int r = 0; r < RMAX; ++r) {
-      int i, j;
-      if (tile_pixel(n, r, i, j)) {
-        int di, dj;
-        quarter_dst(m, n, i, j, di, dj);                 // P_m^T: x(i, j) = h(P_m position)
-        acc[r] += rotated_T_pixel(Gs, n, S, t, di, dj);
+    for (int r = 0; r < LPW; ++r) {                    // pass 1 transpose, then P_m^T
+      const int j = w + NW * r;
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        const int i = lane + 64 * e;
+        if (j < n && i < n) {
+          int di, dj;
+          quarter_dst(m, n, i, j, di, dj);             // x(i, j) = h(P_m position)
+          acc[r][e] += row_px<-1>(Y, n, S, t, di, dj);
+        }
       }
     }
   }
   float* dst = partial + (size_t)g * N + (size_t)k * nn;
 #pragma unroll
-  for (int r = 0; r < RMAX; ++r) {
-    int i, j;
-    if (tile_pixel(n, r, i, j)) dst[j * n + i] = accumulate ? dst[j * n + i] + acc[r] : acc[r];
+  for (int r = 0; r < LPW; ++r) {
+    const int j = w + NW * r;
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      const int i = lane + 64 * e;
+      if (j < n && i < n) dst[j * n + i] = accumulate ? dst[j * n + i] + acc[r][e] : acc[r][e];
+    }
   }
 }
 
@@ -307,41 +409,67 @@ hipError_t set_smem(const void* fn, size_t bytes) {
 
 }  // namespace
 
+size_t rotation_lds_bytes(int n) {
+  // mubar kernel: two slices, the FP64 scan segments, tables
+  return 2 * slice_bytes(n) + (size_t)kScanSeg * n * 8 + tab_bytes(n);
+}
+
+// Instantiation by slice size: EPL = elements of a line per lane,
+// LPW = lines per wave.
+template <class F>
+hipError_t with_shape(int n, F&& f) {
+  if (n <= 64) return f(std::integral_constant<int, 1>(), std::integral_constant<int, 4>());
+  if (n <= 128) return f(std::integral_constant<int, 2>(), std::integral_constant<int, 8>());
+  return f(std::integral_constant<int, 3>(), std::integral_constant<int, (kMaxLdsN + NW - 1) / NW>());
+}
+
 hipError_t launch_mubar(const Plan& p, float* out, int view0, int nviews, int out_view0,
                         hipStream_t s) {
   const int n = p.g.nx;
-  const size_t sm = 2 * slice_bytes(n) + tab_bytes(n);
-  hipError_t e = set_smem((const void*)mubar_kernel, sm);
-  if (e != hipSuccess) return e;
+  const size_t sm = rotation_lds_bytes(n);
   const int VG = kRotViewsPerGroup;
   dim3 grid(p.g.nz, (nviews + VG - 1) / VG);
-  hipLaunchKernelGGL(mubar_kernel, grid, dim3(NT), sm, s, p.mu, out, n, p.g.nz, view0, nviews, VG,
-                     out_view0, p.tab, p.g.dy);
-  return hipGetLastError();
+  return with_shape(n, [&](auto E, auto) {
+    hipError_t e = set_smem((const void*)mubar_kernel<E.value>, sm);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(mubar_kernel<E.value>, grid, dim3(NT), sm, s, p.mu, out, n, p.g.nz, view0,
+                       nviews, VG, out_view0, p.tab, p.g.dy);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_rot_fwd(const Plan& p, const float* x, const float* mb, int mb_off, float* W,
                           int view0, int nvb, hipStream_t s) {
   const int n = p.g.nx;
-  const size_t sm = slice_bytes(n) + tab_bytes(n);
-  hipError_t e = set_smem((const void*)rot_fwd_kernel, sm);
-  if (e != hipSuccess) return e;
+  const size_t sm = (size_t)n * gather_stride(n) * 4 + tab_bytes(n);
   const int VG = kRotViewsPerGroup;
   dim3 grid(p.g.nz, (nvb + VG - 1) / VG);
-  hipLaunchKernelGGL(rot_fwd_kernel, grid, dim3(NT), sm, s, x, mb, mb_off, W, n, p.g.nz, view0,
-                     nvb, VG, p.tab);
-  return hipGetLastError();
+  auto go = [&](auto RM) {
+    hipError_t e = set_smem((const void*)rot_fwd_kernel<RM.value>, sm);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(rot_fwd_kernel<RM.value>, grid, dim3(NT), sm, s, x, mb, mb_off, W, n,
+                       p.g.nz, view0, nvb, VG, p.tab);
+    return hipGetLastError();
+  };
+  // 8x8 tiles per wave: ceil(ceil(n/8)^2 / NW)
+  if (n <= 64) return go(std::integral_constant<int, 4>());
+  if (n <= 128) return go(std::integral_constant<int, 16>());
+  constexpr int tpr = (kMaxLdsN + 7) / 8;
+  return go(std::integral_constant<int, (tpr * tpr + NW - 1) / NW>());
 }
 
 hipError_t launch_rot_back(const Plan& p, const float* U, const float* mb, int mb_off,
                            float* partial, int view0, int nvb, bool accumulate, hipStream_t s) {
   const int n = p.g.nx;
   const size_t sm = slice_bytes(n) + tab_bytes(n);
-  hipError_t e = set_smem((const void*)rot_back_kernel, sm);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(rot_back_kernel, dim3(p.g.nz, kBackGroups), dim3(NT), sm, s, U, mb, mb_off,
-                     partial, n, p.g.nz, view0, nvb, kBackGroups, accumulate ? 1 : 0, p.tab);
-  return hipGetLastError();
+  return with_shape(n, [&](auto E, auto L) {
+    hipError_t e = set_smem((const void*)rot_back_kernel<E.value, L.value>, sm);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((rot_back_kernel<E.value, L.value>), dim3(p.g.nz, kBackGroups), dim3(NT), sm,
+                       s, U, mb, mb_off, partial, n, p.g.nz, view0, nvb, kBackGroups,
+                       accumulate ? 1 : 0, p.tab);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_back_reduce(const Plan& p, const float* partial, float* x, hipStream_t s) {
