@@ -65,14 +65,18 @@ def test_nonfinite_angle_rejected():
 
 
 def test_workspace_grows_with_cache_and_shrinks_with_batch():
-    g0, _ = spect.make_geom(128, 128, 80, 128, 37, 37, 4.8)
-    g1, _ = spect.make_geom(128, 128, 80, 128, 37, 37, 4.8, flags=spect.SPECT_CACHE_MUBAR)
-    g2, _ = spect.make_geom(128, 128, 80, 128, 37, 37, 4.8, view_batch=16)
-    b0, b1, b2 = (spect.spect_workspace_bytes(g) for g in (g0, g1, g2))
+    """The attenuation cache holds every view; without it a buffer for one view
+    batch is kept instead.  Smaller view batches shrink the per-batch buffers."""
     N = 128 * 128 * 80 * 4
-    assert b1 - b0 >= 128 * N
-    assert b2 < b0 - 100 * N
-    assert b0 % 256 == 0
+    ws = lambda **kw: spect.spect_workspace_bytes(spect.make_geom(128, 128, 80, 128, 37, 37, 4.8, **kw)[0])
+    b_all = ws()
+    b_all_cache = ws(flags=spect.SPECT_CACHE_MUBAR)
+    b16 = ws(view_batch=16)
+    b16_cache = ws(view_batch=16, flags=spect.SPECT_CACHE_MUBAR)
+    assert b_all_cache == b_all                    # batch = all views: same size either way
+    assert b16_cache - b16 == (128 - 16) * N       # cache of 128 views replaces a 16-view batch
+    assert b16 < b_all - 200 * N                   # W and mubar batch buffers both shrink
+    assert all(b % 256 == 0 for b in (b_all, b_all_cache, b16, b16_cache))
 
 
 def test_plan_create_rejects_before_any_gpu_call():
