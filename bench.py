@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--em-iters", type=int, default=8, help="EM iterations per reconstruction")
     ap.add_argument("--cpu-views", type=int, default=24,
                     help="views in the bounded oracle sample (0 disables the CPU baseline)")
+    ap.add_argument("--grad-iters", type=int, default=10,
+                    help="unrolled EM iterations differentiated end to end (0 disables)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB device-to-device: a plain "
@@ -205,6 +207,36 @@ def main():
         em = {"iters": args.em_iters, "recons": args.em_recons, "p50_ms": pct(lat, 50),
               "p99_ms": pct(lat, 99)}
 
+    # Differentiation through unrolled EM (not part of `value`): MSE against the
+    # phantom backpropagated to x0 and y through `grad_iters` EM updates.
+    grad = None
+    if args.grad_iters > 0:
+        from paper_2301_09710_amd import autograd as sag
+        ones = torch.ones(plan.proj_shape, dtype=torch.float32, device=dev)
+        sens = plan.back(ones)
+        yc = plan.forward(xd)
+        rg = torch.full_like(yc, 0.05 * float(yc.mean()))
+        yg = torch.poisson(yc + rg)
+        x0 = torch.full_like(xd, float(xd.mean()))
+        torch.cuda.synchronize()
+        base_mem = torch.cuda.memory_allocated(dev)
+        torch.cuda.reset_peak_memory_stats(dev)
+        a, m, b = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        x0g = x0.clone().requires_grad_(True)
+        ygg = yg.clone().requires_grad_(True)
+        a.record()
+        xk = sag.unrolled_mlem(plan, x0g, ygg, sens, rg, iters=args.grad_iters)
+        loss = ((xk - xd) ** 2).mean()
+        m.record()
+        loss.backward()
+        b.record()
+        torch.cuda.synchronize()
+        grad = {"iters": args.grad_iters, "forward_ms": a.elapsed_time(m),
+                "backward_ms": m.elapsed_time(b), "total_ms": a.elapsed_time(b),
+                "projector_directions": 6 * args.grad_iters,
+                "peak_extra_mb": (torch.cuda.max_memory_allocated(dev) - base_mem) / 2 ** 20}
+        del x0g, ygg, xk, loss
+
     if args.copy_mb > 0:
         nbytes = args.copy_mb << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
@@ -239,6 +271,7 @@ def main():
                             "p10": pct(step_ms, 10), "p90": pct(step_ms, 90)},
         "wall_s_timed": wall,
         "em_recon_latency": em,
+        "unrolled_em_grad": grad,
         "kernels_ms_per_launch": avg_ms,
         "roofline": roof,
         "cpu_baseline": cpu,

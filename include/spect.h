@@ -113,6 +113,23 @@ spect_status spect_em_step(spect_plan plan, float* d_x, const float* d_y,
                            const float* d_r, const float* d_sens,
                            hipStream_t stream);
 
+/* Vector-Jacobian product of one spect_em_step (Sec. II-B: the unrolled EM
+ * iterations are trained by backpropagation, and the projector's adjoint is
+ * what makes that exact).  For x+ = em_step(x, y) and an upstream gradient
+ * g = dL/dx+ ([nz][ny][nx]) it writes
+ *   d_gx = dL/dx  = g * b / sens + A'(gq)          [nz][ny][nx]
+ *   d_gy = dL/dy  = t / ybar  (NULL to skip)       [nview][nz][nx]
+ * with ybar = A x + r, rho = y / ybar, b = A' rho, t = A(g * x / sens) and
+ * gq = -(t / ybar) * (y / ybar); the guarded branches (sens <= 0, ybar <= 0)
+ * are constant and contribute zero.  The step's forward is recomputed from
+ * d_x, so a caller that keeps only the iterates x_k gets gradients through
+ * unrolled EM (four projector directions per step).  d_x, d_y, d_r
+ * (nullable), d_sens as for spect_em_step; d_g must not overlap d_x, d_y,
+ * d_r, d_sens or d_gy; d_gx may equal d_g and overlaps no other buffer. */
+spect_status spect_em_step_vjp(spect_plan plan, const float* d_x, const float* d_y,
+                               const float* d_r, const float* d_sens, const float* d_g,
+                               float* d_gx, float* d_gy, hipStream_t stream);
+
 /* Release the host plan object (does not free borrowed device memory). */
 spect_status spect_plan_destroy(spect_plan plan);
 

@@ -53,3 +53,52 @@ def reg_em_update(x, e, sens, u, beta):
     disc = np.sqrt(d * d + 4.0 * beta * x * e)
     return np.where(d > 0, 2.0 * x * e / np.where(d > 0, d + disc, 1.0),
                     (-d + disc) / (2.0 * beta))
+
+
+def mlem_step_vjp(x, y, r, sens, g, A, At):
+    """Reverse-mode derivative of ``mlem_step`` (the unrolled EM iterations of
+    Sec. II-B are trained by backpropagation).  For x+ = x * b / s with
+    b = At(rho), rho = y / ybar, ybar = A x + r and upstream g = dL/dx+, the
+    chain rule gives, away from the guarded branches (which are constant):
+
+      dL/db   = g x / s                 dL/dx (direct) = g b / s
+      dL/drho = A(dL/db)                (b = At rho, and At's adjoint is A)
+      dL/dy   = dL/drho / ybar
+      dL/dybar = -dL/drho * y / ybar^2
+      dL/dx  += At(dL/dybar)            (ybar = A x + r)
+
+    Returns (dL/dx, dL/dy).  A and At are callables; FP64 throughout."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    sens = np.asarray(sens, dtype=np.float64)
+    ybar = A(x) + (0.0 if r is None else np.asarray(r, dtype=np.float64))
+    b = At(ratio(y, ybar))
+    okx = sens > 0
+    g_b = np.zeros_like(x)
+    g_b[okx] = g[okx] * x[okx] / sens[okx]
+    gx = np.zeros_like(x)
+    gx[okx] = g[okx] * b[okx] / sens[okx]
+    g_rho = A(g_b)
+    oky = ybar > 0
+    gy = np.zeros_like(ybar)
+    gy[oky] = g_rho[oky] / ybar[oky]
+    g_ybar = np.zeros_like(ybar)
+    g_ybar[oky] = -g_rho[oky] * y[oky] / ybar[oky] ** 2
+    gx = gx + At(g_ybar)
+    return gx, gy
+
+
+def unrolled_mlem_grad(x0, y, r, sens, A, At, iters, loss_grad):
+    """x_K after ``iters`` ML-EM updates from x0, and the gradients of a loss
+    L(x_K) with respect to x0 and y.  ``loss_grad(x_K)`` returns
+    (L, dL/dx_K).  Plain reverse accumulation over the stored iterates."""
+    xs = [np.asarray(x0, dtype=np.float64)]
+    for _ in range(iters):
+        xs.append(mlem_step(xs[-1], y, r, sens, A, At))
+    loss, g = loss_grad(xs[-1])
+    gy = np.zeros_like(np.asarray(y, dtype=np.float64))
+    for k in range(iters - 1, -1, -1):
+        g, gyk = mlem_step_vjp(xs[k], y, r, sens, g, A, At)
+        gy = gy + gyk
+    return xs[-1], loss, g, gy

@@ -23,6 +23,48 @@ __global__ void em_update_kernel(float* __restrict__ x, const float* __restrict_
   x[q] = s > 0.0f ? x[q] * e[q] / s : 0.0f;
 }
 
+// Vector-Jacobian product of one EM update x+ = x * A'(y / (A x + r)) / s
+// (Eq. (7)-(8), beta -> 0), with g = dL/dx+ and b = A'rho:
+//   dL/dx = g b / s + A'(gq),   gq = -(t / q)(y / q),   t = A (g x / s),
+//   dL/dy = t / q,              q = A x + r,
+// where the guarded branches (s <= 0, q <= 0) are constants and pass no
+// gradient.  The projections t and A'(gq) run on the projector kernels; the
+// steps below are the element-wise parts.
+
+// gb = g x / s and gx = g b / s (0 where s <= 0).
+__global__ void em_vjp_prep_kernel(const float* __restrict__ g, const float* __restrict__ x,
+                                   const float* __restrict__ b, const float* __restrict__ sens,
+                                   float* __restrict__ gb, float* __restrict__ gx, size_t n) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const float s = sens[q];
+  const float gq = g[q];
+  const bool ok = s > 0.0f;
+  gb[q] = ok ? gq * x[q] / s : 0.0f;
+  gx[q] = ok ? gq * b[q] / s : 0.0f;
+}
+
+// From t = A gb and the mean q = v + r: gy = t / q and gq = -(t / q)(y / q),
+// both 0 where q <= 0; gq overwrites t.
+__global__ void em_vjp_ratio_kernel(float* __restrict__ t, const float* __restrict__ v,
+                                    const float* __restrict__ y, const float* __restrict__ r,
+                                    float* __restrict__ gy, size_t m) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  const float ybar = v[q] + (r ? r[q] : 0.0f);
+  const bool ok = ybar > 0.0f;
+  const float tq = ok ? t[q] / ybar : 0.0f;
+  if (gy) gy[q] = tq;
+  t[q] = ok ? -tq * (y[q] / ybar) : 0.0f;
+}
+
+// a += b
+__global__ void add_kernel(float* __restrict__ a, const float* __restrict__ b, size_t n) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  a[q] += b[q];
+}
+
 constexpr int kDotThreads = 1024;
 
 // Single workgroup, fixed order: thread t sums elements t, t+T, ... in FP64,
@@ -54,6 +96,25 @@ hipError_t launch_em_ratio(const float* v, const float* y, const float* r, float
 hipError_t launch_em_update(float* x, const float* e, const float* sens, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(em_update_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, e,
                      sens, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_em_vjp_prep(const float* g, const float* x, const float* b, const float* sens,
+                              float* gb, float* gx, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(em_vjp_prep_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, x, b,
+                     sens, gb, gx, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_em_vjp_ratio(float* t, const float* v, const float* y, const float* r, float* gy,
+                               size_t m, hipStream_t s) {
+  hipLaunchKernelGGL(em_vjp_ratio_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, t, v,
+                     y, r, gy, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_add(float* a, const float* b, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(add_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, b, n);
   return hipGetLastError();
 }
 

@@ -66,13 +66,15 @@ struct Layout {
   size_t mubar_batch;   // view_batch * N floats (only without SPECT_CACHE_MUBAR)
   size_t em_proj;       // nview * nz * nx floats
   size_t em_vol;        // N floats
+  size_t em_proj2;      // nview * nz * nx floats (EM vector-Jacobian product)
+  size_t em_vol2;       // N floats (EM vector-Jacobian product)
   size_t total;
 };
 
 // Kernel identities for the optional per-launch timing.
 enum KernelId {
   K_MUBAR = 0, K_ROT_FWD, K_CONV_FWD, K_FWD_REDUCE, K_CONV_BACK, K_ROT_BACK,
-  K_BACK_REDUCE, K_EM_RATIO, K_EM_UPDATE, K_CONV_BACK_EDGES, K_COUNT
+  K_BACK_REDUCE, K_EM_RATIO, K_EM_UPDATE, K_CONV_BACK_EDGES, K_EM_VJP, K_COUNT
 };
 extern const char* const kKernelNames[K_COUNT];
 
@@ -151,6 +153,11 @@ hipError_t launch_back_reduce(const Plan& p, const float* partial, float* x, hip
 hipError_t launch_em_ratio(const float* v, const float* y, const float* r, float* rho, size_t m,
                            hipStream_t s);
 hipError_t launch_em_update(float* x, const float* e, const float* sens, size_t n, hipStream_t s);
+hipError_t launch_em_vjp_prep(const float* g, const float* x, const float* b, const float* sens,
+                              float* gb, float* gx, size_t n, hipStream_t s);
+hipError_t launch_em_vjp_ratio(float* t, const float* v, const float* y, const float* r, float* gy,
+                               size_t m, hipStream_t s);
+hipError_t launch_add(float* a, const float* b, size_t n, hipStream_t s);
 hipError_t launch_dot_f64(const float* a, const float* b, size_t n, double* out, hipStream_t s);
 
 }  // namespace spect

@@ -53,6 +53,8 @@ spect_status compute_layout(const spect_geom& g, Layout* lay, int* view_batch, i
 
   lay->em_proj = take(M * sizeof(float));
   lay->em_vol = take(N * sizeof(float));
+  lay->em_proj2 = take(M * sizeof(float));
+  lay->em_vol2 = take(N * sizeof(float));
   lay->total = off;
   *view_batch = vb;
   *nchunk = nc;
@@ -102,7 +104,7 @@ namespace spect {
 const char* const kKernelNames[K_COUNT] = {"mubar", "rot_fwd",  "conv_fwd",
                                            "fwd_reduce",  "conv_back", "rot_back",
                                            "back_reduce", "em_ratio", "em_update",
-                                           "conv_back_edges"};
+                                           "conv_back_edges", "em_vjp"};
 
 static void profiler_free(Profiler* pr) {
   if (!pr) return;
@@ -323,6 +325,42 @@ spect_status spect_em_step(spect_plan plan, float* d_x, const float* d_y, const 
   if (st != SPECT_OK) return st;
   if (timed(p, K_EM_UPDATE, stream, [&] { return launch_em_update(d_x, e, d_sens, N, stream); }) !=
       hipSuccess)
+    return SPECT_ERR_HIP;
+  return SPECT_OK;
+}
+
+spect_status spect_em_step_vjp(spect_plan plan, const float* d_x, const float* d_y,
+                               const float* d_r, const float* d_sens, const float* d_g,
+                               float* d_gx, float* d_gy, hipStream_t stream) {
+  if (!plan || !d_x || !d_y || !d_sens || !d_g || !d_gx) return SPECT_ERR_NULL;
+  if (!aligned(d_x, 4) || !aligned(d_y, 4) || !aligned(d_sens, 4) || !aligned(d_g, 4) ||
+      !aligned(d_gx, 4) || (d_r && !aligned(d_r, 4)) || (d_gy && !aligned(d_gy, 4)))
+    return SPECT_ERR_ALIGN;
+  const Plan& p = *reinterpret_cast<Plan*>(plan);
+  const size_t N = (size_t)p.g.nx * p.g.ny * p.g.nz;
+  const size_t M = (size_t)p.g.nview * p.g.nz * p.g.nx;
+  float* v = reinterpret_cast<float*>(p.ws + p.lay.em_proj);     // A x
+  float* t = reinterpret_cast<float*>(p.ws + p.lay.em_proj2);    // rho, then A gb, then gq
+  float* b = reinterpret_cast<float*>(p.ws + p.lay.em_vol);      // A' rho
+  float* w = reinterpret_cast<float*>(p.ws + p.lay.em_vol2);     // gb, then A' gq
+  // recompute the forward of the step (nothing is kept between calls)
+  spect_status st = forward_impl(p, d_x, v, stream);
+  if (st != SPECT_OK) return st;
+  if (timed(p, K_EM_RATIO, stream, [&] { return launch_em_ratio(v, d_y, d_r, t, M, stream); }) !=
+      hipSuccess)
+    return SPECT_ERR_HIP;
+  if ((st = back_impl(p, t, b, stream)) != SPECT_OK) return st;
+  if (timed(p, K_EM_VJP, stream, [&] {
+        return launch_em_vjp_prep(d_g, d_x, b, d_sens, w, d_gx, N, stream);
+      }) != hipSuccess)
+    return SPECT_ERR_HIP;
+  if ((st = forward_impl(p, w, t, stream)) != SPECT_OK) return st;
+  if (timed(p, K_EM_VJP, stream, [&] {
+        return launch_em_vjp_ratio(t, v, d_y, d_r, d_gy, M, stream);
+      }) != hipSuccess)
+    return SPECT_ERR_HIP;
+  if ((st = back_impl(p, t, w, stream)) != SPECT_OK) return st;
+  if (timed(p, K_EM_VJP, stream, [&] { return launch_add(d_gx, w, N, stream); }) != hipSuccess)
     return SPECT_ERR_HIP;
   return SPECT_OK;
 }

@@ -24,7 +24,7 @@ STATUS_NAMES = {
     4: "SPECT_ERR_WORKSPACE", 5: "SPECT_ERR_UNSUPPORTED", 6: "SPECT_ERR_HIP", 7: "SPECT_ERR_ALIGN",
 }
 EXPORTED = ("spect_workspace_bytes", "spect_plan_create", "spect_forward", "spect_back",
-            "spect_em_step", "spect_plan_destroy", "spect_status_string", "spect_dot_f64",
+            "spect_em_step", "spect_em_step_vjp", "spect_plan_destroy", "spect_status_string", "spect_dot_f64",
             "spect_profile_start", "spect_profile_stop", "spect_version")
 
 
@@ -62,13 +62,14 @@ def _lib():
         lib.spect_forward.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
         lib.spect_back.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
         lib.spect_em_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+        lib.spect_em_step_vjp.argtypes = [c_void_p] * 9
         lib.spect_plan_destroy.argtypes = [c_void_p]
         lib.spect_dot_f64.argtypes = [c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]
         lib.spect_profile_start.argtypes = [c_void_p, c_int32]
         lib.spect_profile_stop.argtypes = [c_void_p, POINTER(spect_kernel_time), c_int32,
                                            POINTER(c_int32)]
         for name in ("spect_workspace_bytes", "spect_plan_create", "spect_forward", "spect_back",
-                     "spect_em_step", "spect_plan_destroy", "spect_dot_f64",
+                     "spect_em_step", "spect_em_step_vjp", "spect_plan_destroy", "spect_dot_f64",
                      "spect_profile_start", "spect_profile_stop"):
             getattr(lib, name).restype = c_int
         lib.spect_status_string.argtypes = [c_int]
@@ -130,6 +131,13 @@ def spect_em_step(plan: int, d_x: int, d_y: int, d_r, d_sens: int, stream: int) 
     st = _lib().spect_em_step(plan, d_x, d_y, d_r, d_sens, stream)
     if st != SPECT_OK:
         raise SpectError(st, "spect_em_step")
+
+
+def spect_em_step_vjp(plan: int, d_x: int, d_y: int, d_r, d_sens: int, d_g: int, d_gx: int,
+                      d_gy, stream: int) -> None:
+    st = _lib().spect_em_step_vjp(plan, d_x, d_y, d_r, d_sens, d_g, d_gx, d_gy, stream)
+    if st != SPECT_OK:
+        raise SpectError(st, "spect_em_step_vjp")
 
 
 def spect_plan_destroy(plan: int) -> None:
@@ -246,6 +254,23 @@ class Plan:
         spect_em_step(self._plan, x.data_ptr(), y.data_ptr(), None if r is None else r.data_ptr(),
                       sens.data_ptr(), _stream(torch, self.device))
         return x
+
+    def em_step_vjp(self, x, y, sens, g, r=None, need_gy=True):
+        """(dL/dx, dL/dy or None) of one em_step at input x for dL/dx+ = g."""
+        import torch
+        _check(x, self.vol_shape, "x", self.device)
+        _check(y, self.proj_shape, "y", self.device)
+        _check(sens, self.vol_shape, "sens", self.device)
+        _check(g, self.vol_shape, "g", self.device)
+        if r is not None:
+            _check(r, self.proj_shape, "r", self.device)
+        gx = torch.empty(self.vol_shape, dtype=torch.float32, device=self.device)
+        gy = torch.empty(self.proj_shape, dtype=torch.float32, device=self.device) if need_gy else None
+        spect_em_step_vjp(self._plan, x.data_ptr(), y.data_ptr(),
+                          None if r is None else r.data_ptr(), sens.data_ptr(), g.data_ptr(),
+                          gx.data_ptr(), None if gy is None else gy.data_ptr(),
+                          _stream(torch, self.device))
+        return gx, gy
 
     def profile_start(self, max_launches=4096):
         spect_profile_start(self._plan, max_launches)
