@@ -61,6 +61,15 @@ typedef enum {
   SPECT_ERR_ALIGN = 7        /* device pointer not aligned as documented */
 } spect_status;
 
+/* convolution precision (spect_geom.conv_precision) */
+#define SPECT_CONV_FP32 0  /* FP32 throughout (the reference-accuracy path) */
+#define SPECT_CONV_BF16 1  /* PSF convolution and its adjoint as BF16 matrix-core
+                              products with FP32 accumulation; rotation, attenuation,
+                              depth sum, edge fold and EM stay FP32 */
+#define SPECT_CONV_FP16 2  /* the same with FP16 operands: values of the weighted
+                              volume and of projections handed to spect_back must
+                              stay below 65504 in magnitude */
+
 /* flags */
 #define SPECT_CACHE_MUBAR 0x1u  /* keep the attenuation factor of Eq. (1) for all
                                    views in the workspace (nview*nx*ny*nz floats),
@@ -78,6 +87,8 @@ typedef struct {
   uint32_t flags;         /* SPECT_CACHE_MUBAR or 0 */
   int32_t view_batch;     /* views processed per internal batch; 0 = all.
                              Smaller batches need less workspace. */
+  int32_t conv_precision; /* SPECT_CONV_FP32 (0), SPECT_CONV_BF16 or SPECT_CONV_FP16;
+                             other values give SPECT_ERR_VALUE */
 } spect_geom;
 
 /* Workspace bytes a plan with geometry g needs (host only, no GPU call).
@@ -112,6 +123,19 @@ spect_status spect_back(spect_plan plan, const float* d_v, float* d_x,
 spect_status spect_em_step(spect_plan plan, float* d_x, const float* d_y,
                            const float* d_r, const float* d_sens,
                            hipStream_t stream);
+
+/* One regularised EM update in place (Sec. II-B, Eq. (7)-(8)): with
+ *   e = A'(y / (A x + r))  (the ratio 0 where A x + r <= 0),
+ *   d = sens - beta * u,
+ * x becomes the nonnegative root of beta x^2 + d x - x_old e = 0,
+ *   x = (-d + sqrt(d^2 + 4 beta x_old e)) / (2 beta),
+ * evaluated without cancellation when d > 0.  d_u: the regularisation
+ * target [nz][ny][nx] (the paper's CNN output u_k); beta >= 0 and finite
+ * (beta = 0 gives x_old e / sens, 0 where sens <= 0); otherwise
+ * SPECT_ERR_VALUE.  Other arguments as for spect_em_step. */
+spect_status spect_reg_em_step(spect_plan plan, float* d_x, const float* d_y,
+                               const float* d_r, const float* d_sens, const float* d_u,
+                               float beta, hipStream_t stream);
 
 /* Vector-Jacobian product of one spect_em_step (Sec. II-B: the unrolled EM
  * iterations are trained by backpropagation, and the projector's adjoint is

@@ -17,7 +17,9 @@ Modules
   attenuation accumulated attenuation factor, Eq. (1)
   convolution replicate-padded 2-D convolution, its transpose, FFT form
   projector   forward projector (Alg. 1), back projector (Alg. 2 / Eq. (2))
-  em          Poisson model and EM updates, Eq. (3)-(4), (7)-(8)
+  em          Poisson model and EM updates, Eq. (3)-(4), (7)-(8), and their
+              reverse-mode derivatives (unrolled EM, Sec. II-B)
+  precision   rounding to BF16 / FP16 for the reduced-precision convolution
   dense       explicit system matrices for tiny problems (Sec. III-A-3)
 
 Index conventions: arrays come in the C-ABI storage layout
@@ -33,5 +35,5 @@ M = floor(theta/(pi/2) + 1/2), phi in [-pi/4, pi/4); quarter turn first, then
 the shears X(tan(phi/2)) Y(-sin phi) X(tan(phi/2)); zero outside the grid for
 interpolation; replicate padding of width (p-1)/2 for odd kernels.
 """
-from . import geometry, rotation, attenuation, convolution, projector, em, dense  # noqa: F401
+from . import geometry, rotation, attenuation, convolution, projector, em, dense, precision  # noqa: F401
 from .projector import forward, back, Geometry  # noqa: F401

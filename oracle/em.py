@@ -102,3 +102,28 @@ def unrolled_mlem_grad(x0, y, r, sens, A, At, iters, loss_grad):
         g, gyk = mlem_step_vjp(xs[k], y, r, sens, g, A, At)
         gy = gy + gyk
     return xs[-1], loss, g, gy
+
+
+def osem_subsets(nview, nsub):
+    """Ordered subsets of the views (Sec. III-A compares OSEM reconstructions):
+    subset s holds the views l with l mod nsub = s, visited for s = 0..nsub-1.
+    The paper does not say how its subsets are formed; interleaved subsets
+    are the usual choice."""
+    return [list(range(s, nview, nsub)) for s in range(nsub)]
+
+
+def osem(x0, y, r, A_sub, At_sub, nview, nsub, iters):
+    """OSEM: each iteration runs one ML-EM update per subset, with the
+    subset's own projector A_s, back projector At_s and sensitivity At_s 1.
+    A_sub(s, x) returns the projections of subset s ([len(s)][nz][nx]);
+    At_sub(s, v) back-projects them.  y, r: full sinograms [nview][nz][nx]."""
+    subs = osem_subsets(nview, nsub)
+    y = np.asarray(y, dtype=np.float64)
+    r = None if r is None else np.asarray(r, dtype=np.float64)
+    sens = [At_sub(s, np.ones((len(v),) + y.shape[1:])) for s, v in enumerate(subs)]
+    x = np.asarray(x0, dtype=np.float64)
+    for _ in range(iters):
+        for s, views in enumerate(subs):
+            x = mlem_step(x, y[views], None if r is None else r[views], sens[s],
+                          lambda z, s=s: A_sub(s, z), lambda v, s=s: At_sub(s, v))
+    return x

@@ -1,0 +1,458 @@
+// PSF convolution as BF16 / FP16 matrix-core contractions with FP32
+// accumulation (v_mfma_f32_16x16x32_{bf16,f16}): the reduced-precision form of
+// the replicate-padded convolution and its adjoint (Sec. II-A, Alg. 1 and 2).
+// Rotation, attenuation, the depth-sum reduction and the edge fold of the
+// adjoint stay FP32; the inputs of the contraction (the weighted planes or
+// the projection, and the PSF) are rounded to nearest-even at staging.
+//
+// Mapping (one M-block of 16 output z positions per wave, NN N-blocks of 16
+// output x positions per wave, the whole x range of a tile in one wave):
+//   C[m][n] += sum_r A[m][r] B[r][n]   for every x-tap a, with
+//   forward  A[m][r] = p[a][m - r + 2hb],  B[r][n] = R[16 w + r][16 u + n - a + 2ha]
+//   adjoint  A[m][r] = p[a][r - m],        B[r][n] = R[16 w + r][16 u + n + a]
+// where r runs over the 16 + pz - 1 region rows of the M-block's band.  The
+// K dimension of one MFMA (32) is four lanes groups of 8 consecutive rows;
+// each group takes its own (tap, 8-row chunk) pair from the flattened list of
+// px * C7 chunks (C7 = ceil((15 + pz) / 8)), so k-steps do not end at tap
+// boundaries and only the 8-row rounding of the band is wasted
+// (8 C7 / pz = 1.51x for pz = 37, against 64 / 37 for whole-tap k-steps).
+//
+// Operands come from LDS:
+//   B: the region is staged transposed (z contiguous, column stride RS =
+//      8 (mod 16) elements), so a lane's 8 rows are one aligned 16-byte read
+//      and eight consecutive columns cover all banks;
+//   A: each PSF row is stored reversed (forward) or shifted (adjoint) as
+//      overlapping element pairs, one 32-bit word per position, so the 8
+//      values a lane needs from an arbitrary start are four word reads.
+// A is shared by the NN N-blocks of a k-step.
+#include <type_traits>
+
+#include "internal.h"
+
+namespace spect {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <class T> struct Lp;
+template <> struct Lp<__bf16> {
+  typedef bf16x8 vec;
+  static __device__ __forceinline__ floatx4 mfma(u32x4 a, u32x4 b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(vec, a),
+                                                  __builtin_bit_cast(vec, b), c, 0, 0, 0);
+  }
+};
+template <> struct Lp<_Float16> {
+  typedef halfx8 vec;
+  static __device__ __forceinline__ floatx4 mfma(u32x4 a, u32x4 b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(vec, a),
+                                                 __builtin_bit_cast(vec, b), c, 0, 0, 0);
+  }
+};
+
+// Two values rounded to T (nearest even) packed low-first in a 32-bit word.
+template <class T>
+__device__ __forceinline__ unsigned pack2(float lo, float hi) {
+  typedef T t2 __attribute__((ext_vector_type(2)));
+  t2 v;
+  v[0] = (T)lo;
+  v[1] = (T)hi;
+  return __builtin_bit_cast(unsigned, v);
+}
+
+__device__ __forceinline__ int clampi(int q, int lo, int hi) { return q < lo ? lo : (q > hi ? hi : q); }
+
+// PSF pair table of one plane: QP[a][q] = (Q[a][q], Q[a][q + 1]) with
+//   forward  Q[a][q] = p[a][2hb + 15 - q]
+//   adjoint  Q[a][q] = p[a][q - 15]
+// (0 outside the PSF); row px is all zero (the chunks past the last tap).
+// Staging issues the global loads of kStageIt items per thread before any
+// conversion or LDS write, so that their latencies overlap.
+constexpr int kStageIt = 4;
+
+template <class T, bool kBack>
+__device__ __forceinline__ void stage_psf(unsigned* QP, const float* __restrict__ pj,
+                                          const LpShape& s) {
+  const int rows = s.px + 1, total = rows * s.QL;
+  for (int base = 0; base < total; base += kStageIt * (int)blockDim.x) {
+    float v[kStageIt][2];
+#pragma unroll
+    for (int it = 0; it < kStageIt; ++it) {
+      const int e = base + threadIdx.x + it * blockDim.x;
+      const int q = e / rows, a = e - q * rows;         // a fastest: PSF rows are contiguous in a
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int b = kBack ? q + h - 15 : 2 * s.hb + 15 - q - h;
+        v[it][h] = (e < total && a < s.px && b >= 0 && b < s.pz) ? pj[b * s.px + a] : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < kStageIt; ++it) {
+      const int e = base + threadIdx.x + it * blockDim.x;
+      const int q = e / rows, a = e - q * rows;
+      if (e < total) QP[a * s.QL + q] = pack2<T>(v[it][0], v[it][1]);
+    }
+  }
+}
+
+// Transposed region Rt[cc][rr] (column stride RS elements) of a plane
+// src[z * zstride + x]: rr <-> z = k0 - hb + rr, cc <-> x = i0 - ha + cc,
+// clamped (forward, replicate padding) or zero outside (adjoint).  Each item
+// is 8 consecutive rows of one column: 8 loads (consecutive threads take
+// consecutive columns, so loads coalesce along x) and one 16-byte LDS write.
+template <class T, bool kClamp>
+__device__ __forceinline__ void stage_region(unsigned* Rt, const float* __restrict__ src,
+                                             size_t zstride, const LpShape& s, int k0, int i0) {
+  const int total = (s.RR / 8) * s.RC;
+  u32x4* R4 = reinterpret_cast<u32x4*>(Rt);
+  for (int base = 0; base < total; base += kStageIt * (int)blockDim.x) {
+    float v[kStageIt][8];
+#pragma unroll
+    for (int it = 0; it < kStageIt; ++it) {
+      const int e = base + threadIdx.x + it * blockDim.x;
+      const int rq = e / s.RC, cc = e - rq * s.RC;
+      const int x = i0 - s.ha + cc;
+#pragma unroll
+      for (int h = 0; h < 8; ++h) {
+        const int z = k0 - s.hb + 8 * rq + h;
+        if (kClamp) {
+          v[it][h] = e < total
+                         ? src[(size_t)clampi(z, 0, s.nz - 1) * zstride + clampi(x, 0, s.nx - 1)]
+                         : 0.0f;
+        } else {
+          v[it][h] = (e < total && z >= 0 && z < s.nz && x >= 0 && x < s.nx)
+                         ? src[(size_t)z * zstride + x]
+                         : 0.0f;
+        }
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < kStageIt; ++it) {
+      const int e = base + threadIdx.x + it * blockDim.x;
+      const int rq = e / s.RC, cc = e - rq * s.RC;
+      if (e < total)
+        R4[(cc * s.RS) / 8 + rq] = u32x4{pack2<T>(v[it][0], v[it][1]), pack2<T>(v[it][2], v[it][3]),
+                                         pack2<T>(v[it][4], v[it][5]), pack2<T>(v[it][6], v[it][7])};
+    }
+  }
+}
+
+// Operands of one k-step: A (4 words) and the B of the NN N-blocks.
+template <int NN>
+struct Step {
+  u32x4 a;
+  u32x4 b[NN];
+};
+
+// The (tap, 8-row chunk) pair of this lane group advances by four chunks per
+// k-step: c7 += 4, carried into the tap.  C7 >= 2, so two carries suffice.
+__device__ __forceinline__ void advance(int& t, int& c7, int C7) {
+  c7 += 4;
+  if (c7 >= C7) { c7 -= C7; ++t; }
+  if (c7 >= C7) { c7 -= C7; ++t; }
+}
+
+// Operands of the k-step whose lane-group chunk is (t, c7); taps t >= px
+// (the k-steps past the last chunk) read the zero row of the PSF table and
+// an in-range B.
+template <int NN, bool kBack>
+__device__ __forceinline__ void load_step(Step<NN>& st, const unsigned* QP, const u32x4* R4,
+                                          const LpShape& s, int t, int c7, int m, int n, int w) {
+  const bool in = t < s.px;
+  const int ta = in ? t : s.px, tb = in ? t : 0;
+  const unsigned* q = QP + ta * s.QL + 8 * c7 - m + 15;
+  st.a = u32x4{q[0], q[2], q[4], q[6]};
+  const int col0 = kBack ? n + tb : n - tb + 2 * s.ha;
+  const u32x4* b = R4 + (col0 * s.RS + 16 * w + 8 * c7) / 8;   // 16-byte aligned
+  const int ustride = 2 * s.RS;                                 // 16 columns, in 16-byte units
+#pragma unroll
+  for (int u = 0; u < NN; ++u) st.b[u] = b[u * ustride];
+}
+
+// All k-steps of one plane (KSt is even), the operands of the next k-step
+// read while the MFMAs of the current one run.  m: A row of this lane
+// (lane mod 16); n: B column (the same lane mod 16); g: lane group.
+template <class T, int NN, bool kBack>
+__device__ __forceinline__ void plane_mma(floatx4 (&acc)[NN], const unsigned* QP,
+                                          const unsigned* Rt, const LpShape& s, int g, int m,
+                                          int n, int w) {
+  const u32x4* R4 = reinterpret_cast<const u32x4*>(Rt);
+  int t = 0, c7 = g;
+  if (c7 >= s.C7) { c7 -= s.C7; ++t; }
+  if (c7 >= s.C7) { c7 -= s.C7; ++t; }
+  Step<NN> x, y;
+  load_step<NN, kBack>(x, QP, R4, s, t, c7, m, n, w);
+  advance(t, c7, s.C7);
+  // The scheduling barriers keep each k-step's loads ahead of the previous
+  // k-step's MFMAs (left alone, the scheduler pairs every load with its MFMA
+  // and exposes the LDS latency).
+  for (int ks = 0; ks < s.KSt; ks += 2) {
+    load_step<NN, kBack>(y, QP, R4, s, t, c7, m, n, w);
+    advance(t, c7, s.C7);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < NN; ++u) acc[u] = Lp<T>::mfma(x.a, x.b[u], acc[u]);
+    __builtin_amdgcn_sched_barrier(0);
+    load_step<NN, kBack>(x, QP, R4, s, t, c7, m, n, w);
+    advance(t, c7, s.C7);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < NN; ++u) acc[u] = Lp<T>::mfma(y.a, y.b[u], acc[u]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Workgroup -> (tile, chunk, view).
+__device__ __forceinline__ void decode(const LpShape& s, int& tk, int& ti, int& c, int& lb,
+                                       int nchunk) {
+  const int ntile = s.tiles_k * s.tiles_i;
+  const int b = blockIdx.x;
+  const int tile = b % ntile, rest = b / ntile;
+  tk = tile / s.tiles_i;
+  ti = tile - tk * s.tiles_i;
+  c = rest % nchunk;
+  lb = rest / nchunk;
+}
+
+__device__ __forceinline__ void plane_range(int c, int nchunk, int ny, int& j0, int& j1) {
+  j0 = (int)(((long long)c * ny) / nchunk);
+  j1 = (int)(((long long)(c + 1) * ny) / nchunk);
+}
+
+// ---------------------------------------------------------------- forward
+// partial[c][lb][k][i] = sum over the planes j of chunk c of (p_{j,l} * W_j)[k][i]
+template <class T, int NN>
+__global__ __launch_bounds__(64 * kLpMaxWaves) void conv_fwd_lp(const float* __restrict__ W,
+                                                                const float* __restrict__ psf,
+                                                                float* __restrict__ partial,
+                                                                LpShape s, int view0, int nvb) {
+  extern __shared__ unsigned lds[];
+  unsigned* Rt = lds;                                  // RC * RS / 2 words
+  unsigned* QP = lds + s.RC * s.RS / 2;                // (px + 1) * QL words
+  int tk, ti, c, lb;
+  decode(s, tk, ti, c, lb, s.nchunk);
+  const int l = view0 + lb;
+  const int k0 = tk * 16 * s.WKm, i0 = ti * 16 * NN;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
+  int j0, j1;
+  plane_range(c, s.nchunk, s.ny, j0, j1);
+  const size_t zstride = (size_t)s.ny * s.nx;
+  const float* Wl = W + (size_t)lb * s.nz * zstride;
+  floatx4 acc[NN];
+#pragma unroll
+  for (int u = 0; u < NN; ++u) acc[u] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int j = j0; j < j1; ++j) {
+    __syncthreads();                                   // previous plane consumed
+    stage_region<T, true>(Rt, Wl + (size_t)j * s.nx, zstride, s, k0, i0);
+    stage_psf<T, false>(QP, psf + ((size_t)l * s.ny + j) * s.pz * s.px, s);
+    __syncthreads();
+    plane_mma<T, NN, false>(acc, QP, Rt, s, g, n, n, w);
+  }
+  float* out = partial + ((size_t)c * nvb + lb) * s.nz * s.nx;
+#pragma unroll
+  for (int u = 0; u < NN; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int k = k0 + 16 * w + 4 * g + v, i = i0 + 16 * u + n;
+      if (k < s.nz && i < s.nx) out[(size_t)k * s.nx + i] = acc[u][v];
+    }
+}
+
+// ---------------------------------------------------------------- adjoint
+// U[lb][k][j][i] = zero-padded correlation of the projection of view l with
+// p_{j,l}; exact off the edge rows and columns, which the FP32 edge kernel
+// rewrites afterwards.
+template <class T, int NN>
+__global__ __launch_bounds__(64 * kLpMaxWaves) void conv_back_lp(const float* __restrict__ v,
+                                                                 const float* __restrict__ psf,
+                                                                 float* __restrict__ U, LpShape s,
+                                                                 int view0, int nvb) {
+  extern __shared__ unsigned lds[];
+  unsigned* Rt = lds;
+  unsigned* QP = lds + s.RC * s.RS / 2;
+  int tk, ti, c, lb;
+  decode(s, tk, ti, c, lb, s.nchunk_back);
+  const int l = view0 + lb;
+  const int k0 = tk * 16 * s.WKm, i0 = ti * 16 * NN;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
+  int j0, j1;
+  plane_range(c, s.nchunk_back, s.ny, j0, j1);
+  stage_region<T, false>(Rt, v + (size_t)l * s.nz * s.nx, (size_t)s.nx, s, k0, i0);
+  for (int j = j0; j < j1; ++j) {
+    __syncthreads();                                   // region staged / previous plane consumed
+    stage_psf<T, true>(QP, psf + ((size_t)l * s.ny + j) * s.pz * s.px, s);
+    __syncthreads();
+    floatx4 acc[NN];
+#pragma unroll
+    for (int u = 0; u < NN; ++u) acc[u] = floatx4{0.f, 0.f, 0.f, 0.f};
+    plane_mma<T, NN, true>(acc, QP, Rt, s, g, n, n, w);
+    float* out = U + (size_t)lb * s.nz * s.ny * s.nx + (size_t)j * s.nx;
+#pragma unroll
+    for (int u = 0; u < NN; ++u)
+#pragma unroll
+      for (int vv = 0; vv < 4; ++vv) {
+        const int k = k0 + 16 * w + 4 * g + vv, i = i0 + 16 * u + n;
+        if (k < s.nz && i < s.nx) out[(size_t)k * s.ny * s.nx + i] = acc[u][vv];
+      }
+  }
+}
+
+hipError_t set_lds(const void* fn, size_t bytes) {
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// Instantiations: NN in {1, 2, 4, 8} (N-blocks per wave), T in {bf16, f16}.
+template <class T, bool kBack, class F>
+hipError_t with_nn(int NN, F&& f) {
+  switch (NN) {
+    case 1: return f(std::integral_constant<int, 1>());
+    case 2: return f(std::integral_constant<int, 2>());
+    case 4: return f(std::integral_constant<int, 4>());
+    case 8: return f(std::integral_constant<int, 8>());
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <class T>
+const void* fwd_fn(int NN) {
+  switch (NN) {
+    case 1: return (const void*)conv_fwd_lp<T, 1>;
+    case 2: return (const void*)conv_fwd_lp<T, 2>;
+    case 4: return (const void*)conv_fwd_lp<T, 4>;
+    default: return (const void*)conv_fwd_lp<T, 8>;
+  }
+}
+
+template <class T>
+const void* back_fn(int NN) {
+  switch (NN) {
+    case 1: return (const void*)conv_back_lp<T, 1>;
+    case 2: return (const void*)conv_back_lp<T, 2>;
+    case 4: return (const void*)conv_back_lp<T, 4>;
+    default: return (const void*)conv_back_lp<T, 8>;
+  }
+}
+
+template <class T>
+hipError_t launch_fwd_t(const LpShape& s, const float* W, const float* psf, float* partial,
+                        int view0, int nvb, hipStream_t st) {
+  const size_t sm = lp_lds_bytes(s);
+  hipError_t e = set_lds(fwd_fn<T>(s.NN), sm);
+  if (e != hipSuccess) return e;
+  const dim3 grid((unsigned)(s.tiles_k * s.tiles_i * s.nchunk * nvb)), block(64 * s.WKm);
+  return with_nn<T, false>(s.NN, [&](auto NN) {
+    hipLaunchKernelGGL((conv_fwd_lp<T, NN.value>), grid, block, sm, st, W, psf, partial, s, view0,
+                       nvb);
+    return hipGetLastError();
+  });
+}
+
+template <class T>
+hipError_t launch_back_t(const LpShape& s, const float* v, const float* psf, float* U, int view0,
+                         int nvb, hipStream_t st) {
+  const size_t sm = lp_lds_bytes(s);
+  hipError_t e = set_lds(back_fn<T>(s.NN), sm);
+  if (e != hipSuccess) return e;
+  const dim3 grid((unsigned)(s.tiles_k * s.tiles_i * s.nchunk_back * nvb)), block(64 * s.WKm);
+  return with_nn<T, true>(s.NN, [&](auto NN) {
+    hipLaunchKernelGGL((conv_back_lp<T, NN.value>), grid, block, sm, st, v, psf, U, s, view0, nvb);
+    return hipGetLastError();
+  });
+}
+
+template <class T>
+int lp_wgs_per_cu(const LpShape& s, bool back) {
+  int nb = 0;
+  const void* fn = back ? back_fn<T>(s.NN) : fwd_fn<T>(s.NN);
+  const size_t sm = lp_lds_bytes(s);
+  if (set_lds(fn, sm) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 64 * s.WKm, sm) != hipSuccess || nb < 1)
+    nb = (int)(kLdsBytes / (sm ? sm : 1));
+  return nb < 1 ? 1 : nb;
+}
+
+// Depth chunks per (tile, view): minimise rounds * planes per workgroup.
+int lp_pick_chunks(int ny, long long tiles_views, long long slots) {
+  int best = 1;
+  long long best_cost = -1;
+  for (int c = 1; c <= kMaxChunks && c <= ny; ++c) {
+    const long long rounds = (tiles_views * c + slots - 1) / slots;
+    const long long cost = rounds * ((ny + c - 1) / c);
+    if (best_cost < 0 || cost < best_cost) { best_cost = cost; best = c; }
+  }
+  return best;
+}
+
+}  // namespace
+
+static int odd8_stride(int rows) {      // >= rows, multiple of 8, odd multiple of 8
+  int s = (rows + 7) / 8;
+  if (s % 2 == 0) ++s;
+  return 8 * s;
+}
+
+LpShape make_lp_shape(const spect_geom& g) {
+  LpShape s;
+  s.nx = g.nx; s.ny = g.ny; s.nz = g.nz; s.px = g.px; s.pz = g.pz;
+  s.ha = (g.px - 1) / 2; s.hb = (g.pz - 1) / 2;
+  const int nmb = (g.nz + 15) / 16;
+  s.tiles_k = (nmb + kLpMaxWaves - 1) / kLpMaxWaves;
+  s.WKm = (nmb + s.tiles_k - 1) / s.tiles_k;
+  const int nblk = (g.nx + 15) / 16;
+  s.NN = nblk >= 8 ? 8 : (nblk >= 4 ? 4 : (nblk >= 2 ? 2 : 1));
+  if (nblk > 4 && nblk < 8) s.NN = 8;
+  if (nblk == 3) s.NN = 4;
+  s.tiles_i = (nblk + s.NN - 1) / s.NN;
+  s.C7 = (15 + g.pz + 7) / 8;
+  s.nchunks = g.px * s.C7;
+  s.KSt = (s.nchunks + 3) / 4;
+  s.KSt += s.KSt & 1;                  // even: the k-step loop runs in pairs
+  s.RR = 16 * (s.WKm - 1) + 8 * s.C7;
+  s.RS = odd8_stride(s.RR);
+  s.RC = 16 * s.NN + g.px - 1;
+  s.QL = 8 * s.C7 + 15;
+  s.nchunk = 1;
+  s.nchunk_back = 1;
+  return s;
+}
+
+size_t lp_lds_bytes(const LpShape& s) {
+  return (size_t)s.RC * s.RS * 2 + (size_t)(s.px + 1) * s.QL * 4;
+}
+
+bool lp_supported(const spect_geom& g) {
+  return lp_lds_bytes(make_lp_shape(g)) <= kLdsBytes;
+}
+
+void tune_lp_chunks(LpShape& s, int views, int precision) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    return;
+  const bool f16 = precision == SPECT_CONV_FP16;
+  const int fw = f16 ? lp_wgs_per_cu<_Float16>(s, false) : lp_wgs_per_cu<__bf16>(s, false);
+  const int bw = f16 ? lp_wgs_per_cu<_Float16>(s, true) : lp_wgs_per_cu<__bf16>(s, true);
+  const long long tv = (long long)s.tiles_k * s.tiles_i * views;
+  s.nchunk = lp_pick_chunks(s.ny, tv, (long long)cus * fw);
+  s.nchunk_back = lp_pick_chunks(s.ny, tv, (long long)cus * bw);
+}
+
+hipError_t launch_conv_fwd_lp(const Plan& p, const float* W, float* partial, int view0, int nvb,
+                              hipStream_t st) {
+  return p.conv_precision == SPECT_CONV_FP16
+             ? launch_fwd_t<_Float16>(p.lp, W, p.psf, partial, view0, nvb, st)
+             : launch_fwd_t<__bf16>(p.lp, W, p.psf, partial, view0, nvb, st);
+}
+
+hipError_t launch_conv_back_lp(const Plan& p, const float* v, float* U, int view0, int nvb,
+                               hipStream_t st) {
+  return p.conv_precision == SPECT_CONV_FP16
+             ? launch_back_t<_Float16>(p.lp, v, p.psf, U, view0, nvb, st)
+             : launch_back_t<__bf16>(p.lp, v, p.psf, U, view0, nvb, st);
+}
+
+}  // namespace spect

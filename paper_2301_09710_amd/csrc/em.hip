@@ -23,6 +23,25 @@ __global__ void em_update_kernel(float* __restrict__ x, const float* __restrict_
   x[q] = s > 0.0f ? x[q] * e[q] / s : 0.0f;
 }
 
+// Regularised update of Eq. (7)-(8): the root of beta x^2 + d x - x_k e = 0
+// with d = sens - beta u, evaluated as 2 x_k e / (d + sqrt(d^2 + 4 beta x_k e))
+// when d > 0 (no cancellation) and as (-d + sqrt(...)) / (2 beta) otherwise;
+// beta = 0 is the ML-EM update (0 where sens <= 0).
+__global__ void em_reg_update_kernel(float* __restrict__ x, const float* __restrict__ e,
+                                     const float* __restrict__ sens, const float* __restrict__ u,
+                                     float beta, size_t n) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const float xe = x[q] * e[q];
+  const float d = sens[q] - beta * u[q];
+  if (beta == 0.0f) {
+    x[q] = d > 0.0f ? xe / d : 0.0f;
+    return;
+  }
+  const float root = sqrtf(fmaf(d, d, 4.0f * beta * xe));
+  x[q] = d > 0.0f ? 2.0f * xe / (d + root) : (root - d) / (2.0f * beta);
+}
+
 // Vector-Jacobian product of one EM update x+ = x * A'(y / (A x + r)) / s
 // (Eq. (7)-(8), beta -> 0), with g = dL/dx+ and b = A'rho:
 //   dL/dx = g b / s + A'(gq),   gq = -(t / q)(y / q),   t = A (g x / s),
@@ -115,6 +134,13 @@ hipError_t launch_em_vjp_ratio(float* t, const float* v, const float* y, const f
 
 hipError_t launch_add(float* a, const float* b, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(add_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, b, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_em_reg_update(float* x, const float* e, const float* sens, const float* u,
+                                float beta, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(em_reg_update_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, e,
+                     sens, u, beta, n);
   return hipGetLastError();
 }
 

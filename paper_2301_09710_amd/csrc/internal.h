@@ -44,6 +44,18 @@ struct ConvShape {
   int jc_back, nchunk_back;
 };
 
+// Tiling of the BF16 / FP16 convolution (see conv_lp.hip).
+constexpr int kLpMaxWaves = 8;   // M-blocks (waves) per workgroup at most
+struct LpShape {
+  int nx, ny, nz, px, pz, ha, hb;
+  int WKm, NN;            // waves (M-blocks of 16 z) per workgroup, N-blocks of 16 x per wave
+  int tiles_k, tiles_i;   // workgroup tiles of 16 WKm x 16 NN output bins
+  int C7, nchunks, KSt;   // 8-row chunks per tap band, px * C7, k-steps of 4 chunks
+  int RR, RS, RC;         // region rows used, column stride (elements), columns
+  int QL;                 // PSF pair-table row length (words)
+  int nchunk, nchunk_back;// depth chunks (forward, adjoint)
+};
+
 // Per-view geometry tables, on the device (inside the workspace).
 //   quarter[l]             : m, number of quarter turns (0..3)
 //   off[l][0][j], w[l][0][j]: passes 1 and 3 (along i, one entry per row j)
@@ -74,7 +86,8 @@ struct Layout {
 // Kernel identities for the optional per-launch timing.
 enum KernelId {
   K_MUBAR = 0, K_ROT_FWD, K_CONV_FWD, K_FWD_REDUCE, K_CONV_BACK, K_ROT_BACK,
-  K_BACK_REDUCE, K_EM_RATIO, K_EM_UPDATE, K_CONV_BACK_EDGES, K_EM_VJP, K_COUNT
+  K_BACK_REDUCE, K_EM_RATIO, K_EM_UPDATE, K_CONV_BACK_EDGES, K_EM_VJP, K_CONV_FWD_LP,
+  K_CONV_BACK_LP, K_EM_REG_UPDATE, K_COUNT
 };
 extern const char* const kKernelNames[K_COUNT];
 
@@ -97,6 +110,8 @@ struct Plan {
   float* mubar_batch;   // per-batch attenuation factors when not cached
   bool use_mfma;        // MFMA convolution path (else the direct kernels)
   ConvShape conv;
+  int conv_precision;   // SPECT_CONV_FP32 / _BF16 / _FP16
+  LpShape lp;           // tiling of the reduced-precision convolution
   Profiler* prof;       // non-null while spect_profile_start is active
   // host copies of the tables (kept alive for the asynchronous upload)
   int32_t* h_quarter;
@@ -128,6 +143,10 @@ ConvShape make_conv_shape(const spect_geom& g, int jc_fwd, int jc_back);
 void tune_conv_chunks(ConvShape& cs, int views);
 size_t conv_mfma_lds_bytes(const ConvShape& cs, bool back);
 size_t conv_edges_lds_bytes(const ConvShape& cs);
+LpShape make_lp_shape(const spect_geom& g);
+size_t lp_lds_bytes(const LpShape& s);
+bool lp_supported(const spect_geom& g);
+void tune_lp_chunks(LpShape& s, int views, int precision);
 size_t rotation_lds_bytes(int n);
 
 // ---- kernel launchers (return hipGetLastError() of the launch) ----
@@ -153,11 +172,17 @@ hipError_t launch_back_reduce(const Plan& p, const float* partial, float* x, hip
 hipError_t launch_em_ratio(const float* v, const float* y, const float* r, float* rho, size_t m,
                            hipStream_t s);
 hipError_t launch_em_update(float* x, const float* e, const float* sens, size_t n, hipStream_t s);
+hipError_t launch_conv_fwd_lp(const Plan& p, const float* W, float* partial, int view0, int nvb,
+                              hipStream_t s);
+hipError_t launch_conv_back_lp(const Plan& p, const float* v, float* U, int view0, int nvb,
+                               hipStream_t s);
 hipError_t launch_em_vjp_prep(const float* g, const float* x, const float* b, const float* sens,
                               float* gb, float* gx, size_t n, hipStream_t s);
 hipError_t launch_em_vjp_ratio(float* t, const float* v, const float* y, const float* r, float* gy,
                                size_t m, hipStream_t s);
 hipError_t launch_add(float* a, const float* b, size_t n, hipStream_t s);
+hipError_t launch_em_reg_update(float* x, const float* e, const float* sens, const float* u,
+                                float beta, size_t n, hipStream_t s);
 hipError_t launch_dot_f64(const float* a, const float* b, size_t n, double* out, hipStream_t s);
 
 }  // namespace spect

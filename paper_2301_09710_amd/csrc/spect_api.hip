@@ -20,12 +20,18 @@ static spect_status validate(const spect_geom* g) {
   if (!(std::isfinite(g->dy) && g->dy > 0.0)) return SPECT_ERR_VALUE;
   if (g->flags & ~SPECT_CACHE_MUBAR) return SPECT_ERR_VALUE;
   if (g->view_batch < 0) return SPECT_ERR_VALUE;
+  if (g->conv_precision != SPECT_CONV_FP32 && g->conv_precision != SPECT_CONV_BF16 &&
+      g->conv_precision != SPECT_CONV_FP16)
+    return SPECT_ERR_VALUE;
   if (g->angles)
     for (int l = 0; l < g->nview; ++l)
       if (!std::isfinite(g->angles[l])) return SPECT_ERR_VALUE;
   if (g->nx > kMaxLdsN) return SPECT_ERR_UNSUPPORTED;
   // index arithmetic inside a plane / slice uses 32-bit ints
   if ((int64_t)g->nx * g->nz > (1 << 30) || (int64_t)g->px * g->pz > (1 << 20))
+    return SPECT_ERR_UNSUPPORTED;
+  // the reduced-precision convolution needs its LDS tiles and the FP32 edge fold
+  if (g->conv_precision != SPECT_CONV_FP32 && !(lp_supported(*g) && conv_mfma_supported(*g)))
     return SPECT_ERR_UNSUPPORTED;
   return SPECT_OK;
 }
@@ -104,7 +110,8 @@ namespace spect {
 const char* const kKernelNames[K_COUNT] = {"mubar", "rot_fwd",  "conv_fwd",
                                            "fwd_reduce",  "conv_back", "rot_back",
                                            "back_reduce", "em_ratio", "em_update",
-                                           "conv_back_edges", "em_vjp"};
+                                           "conv_back_edges", "em_vjp", "conv_fwd_lp",
+                                           "conv_back_lp", "em_reg_update"};
 
 static void profiler_free(Profiler* pr) {
   if (!pr) return;
@@ -199,6 +206,12 @@ spect_status spect_plan_create(spect_plan* out, const spect_geom* g, const float
     tune_conv_chunks(p->conv, g->nview);   // independent of view_batch: same sums
     p->nchunk = p->conv.nchunk;          // forward partial sums per view
   }
+  p->conv_precision = g->conv_precision;
+  if (p->conv_precision != SPECT_CONV_FP32) {
+    p->lp = make_lp_shape(*g);
+    tune_lp_chunks(p->lp, g->nview, p->conv_precision);
+    p->nchunk = p->lp.nchunk;
+  }
   if (g->flags & SPECT_CACHE_MUBAR) {
     float* cache = reinterpret_cast<float*>(p->ws + lay.mubar_cache);
     if (e == hipSuccess)
@@ -255,11 +268,14 @@ static spect_status forward_impl(const Plan& p, const float* x, float* v, hipStr
     if (timed(p, K_ROT_FWD, s, [&] { return launch_rot_fwd(p, x, mb, mb_off, W, v0, nvb, s); }) !=
         hipSuccess)
       return SPECT_ERR_HIP;
-    if (timed(p, K_CONV_FWD, s, [&] {
-          return p.use_mfma ? launch_conv_fwd_mfma(p, W, part, v0, nvb, s)
-                            : launch_conv_fwd(p, W, part, v0, nvb, s);
-        }) != hipSuccess)
-      return SPECT_ERR_HIP;
+    const hipError_t ec =
+        p.conv_precision != SPECT_CONV_FP32
+            ? timed(p, K_CONV_FWD_LP, s, [&] { return launch_conv_fwd_lp(p, W, part, v0, nvb, s); })
+            : timed(p, K_CONV_FWD, s, [&] {
+                return p.use_mfma ? launch_conv_fwd_mfma(p, W, part, v0, nvb, s)
+                                  : launch_conv_fwd(p, W, part, v0, nvb, s);
+              });
+    if (ec != hipSuccess) return SPECT_ERR_HIP;
     if (timed(p, K_FWD_REDUCE, s, [&] { return launch_fwd_reduce(p, part, v, v0, nvb, s); }) !=
         hipSuccess)
       return SPECT_ERR_HIP;
@@ -272,11 +288,14 @@ static spect_status back_impl(const Plan& p, const float* v, float* x, hipStream
   float* part = reinterpret_cast<float*>(p.ws + p.lay.back_partial);
   for (int v0 = 0; v0 < p.g.nview; v0 += p.view_batch) {
     const int nvb = (p.g.nview - v0 < p.view_batch) ? p.g.nview - v0 : p.view_batch;
-    if (timed(p, K_CONV_BACK, s, [&] {
-          return p.use_mfma ? launch_conv_back_mfma(p, v, U, v0, nvb, s)
-                            : launch_conv_back(p, v, U, v0, nvb, s);
-        }) != hipSuccess)
-      return SPECT_ERR_HIP;
+    const hipError_t ec =
+        p.conv_precision != SPECT_CONV_FP32
+            ? timed(p, K_CONV_BACK_LP, s, [&] { return launch_conv_back_lp(p, v, U, v0, nvb, s); })
+            : timed(p, K_CONV_BACK, s, [&] {
+                return p.use_mfma ? launch_conv_back_mfma(p, v, U, v0, nvb, s)
+                                  : launch_conv_back(p, v, U, v0, nvb, s);
+              });
+    if (ec != hipSuccess) return SPECT_ERR_HIP;
     if (p.use_mfma &&
         timed(p, K_CONV_BACK_EDGES, s,
               [&] { return launch_conv_back_edges(p, v, U, v0, nvb, s); }) != hipSuccess)
@@ -325,6 +344,32 @@ spect_status spect_em_step(spect_plan plan, float* d_x, const float* d_y, const 
   if (st != SPECT_OK) return st;
   if (timed(p, K_EM_UPDATE, stream, [&] { return launch_em_update(d_x, e, d_sens, N, stream); }) !=
       hipSuccess)
+    return SPECT_ERR_HIP;
+  return SPECT_OK;
+}
+
+spect_status spect_reg_em_step(spect_plan plan, float* d_x, const float* d_y, const float* d_r,
+                               const float* d_sens, const float* d_u, float beta,
+                               hipStream_t stream) {
+  if (!plan || !d_x || !d_y || !d_sens || !d_u) return SPECT_ERR_NULL;
+  if (!(std::isfinite(beta) && beta >= 0.0f)) return SPECT_ERR_VALUE;
+  if (!aligned(d_x, 4) || !aligned(d_y, 4) || !aligned(d_sens, 4) || !aligned(d_u, 4) ||
+      (d_r && !aligned(d_r, 4)))
+    return SPECT_ERR_ALIGN;
+  const Plan& p = *reinterpret_cast<Plan*>(plan);
+  const size_t N = (size_t)p.g.nx * p.g.ny * p.g.nz;
+  const size_t M = (size_t)p.g.nview * p.g.nz * p.g.nx;
+  float* ybar = reinterpret_cast<float*>(p.ws + p.lay.em_proj);
+  float* e = reinterpret_cast<float*>(p.ws + p.lay.em_vol);
+  spect_status st = forward_impl(p, d_x, ybar, stream);
+  if (st != SPECT_OK) return st;
+  if (timed(p, K_EM_RATIO, stream, [&] { return launch_em_ratio(ybar, d_y, d_r, ybar, M, stream); }) !=
+      hipSuccess)
+    return SPECT_ERR_HIP;
+  if ((st = back_impl(p, ybar, e, stream)) != SPECT_OK) return st;
+  if (timed(p, K_EM_REG_UPDATE, stream, [&] {
+        return launch_em_reg_update(d_x, e, d_sens, d_u, beta, N, stream);
+      }) != hipSuccess)
     return SPECT_ERR_HIP;
   return SPECT_OK;
 }

@@ -19,12 +19,14 @@ LIB_PATH = os.path.join(_HERE, "libspect.so")
 
 SPECT_OK = 0
 SPECT_CACHE_MUBAR = 0x1
+SPECT_CONV_FP32, SPECT_CONV_BF16, SPECT_CONV_FP16 = 0, 1, 2
+PRECISIONS = {"fp32": SPECT_CONV_FP32, "bf16": SPECT_CONV_BF16, "fp16": SPECT_CONV_FP16}
 STATUS_NAMES = {
     0: "SPECT_OK", 1: "SPECT_ERR_NULL", 2: "SPECT_ERR_SHAPE", 3: "SPECT_ERR_VALUE",
     4: "SPECT_ERR_WORKSPACE", 5: "SPECT_ERR_UNSUPPORTED", 6: "SPECT_ERR_HIP", 7: "SPECT_ERR_ALIGN",
 }
 EXPORTED = ("spect_workspace_bytes", "spect_plan_create", "spect_forward", "spect_back",
-            "spect_em_step", "spect_em_step_vjp", "spect_plan_destroy", "spect_status_string", "spect_dot_f64",
+            "spect_em_step", "spect_reg_em_step", "spect_em_step_vjp", "spect_plan_destroy", "spect_status_string", "spect_dot_f64",
             "spect_profile_start", "spect_profile_stop", "spect_version")
 
 
@@ -38,7 +40,8 @@ class SpectError(RuntimeError):
 class spect_geom(ctypes.Structure):
     _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32), ("nview", c_int32),
                 ("px", c_int32), ("pz", c_int32), ("dy", c_double),
-                ("angles", POINTER(c_double)), ("flags", c_uint32), ("view_batch", c_int32)]
+                ("angles", POINTER(c_double)), ("flags", c_uint32), ("view_batch", c_int32),
+                ("conv_precision", c_int32)]
 
 
 class spect_kernel_time(ctypes.Structure):
@@ -63,13 +66,14 @@ def _lib():
         lib.spect_back.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
         lib.spect_em_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
         lib.spect_em_step_vjp.argtypes = [c_void_p] * 9
+        lib.spect_reg_em_step.argtypes = [c_void_p] * 6 + [ctypes.c_float, c_void_p]
         lib.spect_plan_destroy.argtypes = [c_void_p]
         lib.spect_dot_f64.argtypes = [c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]
         lib.spect_profile_start.argtypes = [c_void_p, c_int32]
         lib.spect_profile_stop.argtypes = [c_void_p, POINTER(spect_kernel_time), c_int32,
                                            POINTER(c_int32)]
         for name in ("spect_workspace_bytes", "spect_plan_create", "spect_forward", "spect_back",
-                     "spect_em_step", "spect_em_step_vjp", "spect_plan_destroy", "spect_dot_f64",
+                     "spect_em_step", "spect_reg_em_step", "spect_em_step_vjp", "spect_plan_destroy", "spect_dot_f64",
                      "spect_profile_start", "spect_profile_stop"):
             getattr(lib, name).restype = c_int
         lib.spect_status_string.argtypes = [c_int]
@@ -85,10 +89,11 @@ def load():
     return _lib()
 
 
-def make_geom(nx, ny, nz, nview, px, pz, dy, angles=None, flags=0, view_batch=0):
+def make_geom(nx, ny, nz, nview, px, pz, dy, angles=None, flags=0, view_batch=0,
+              conv_precision=SPECT_CONV_FP32):
     """Build a spect_geom; returns (geom, keepalive) -- keep the second item
     alive while the geom is in use (it owns the angles array)."""
-    g = spect_geom(nx, ny, nz, nview, px, pz, float(dy), None, flags, view_batch)
+    g = spect_geom(nx, ny, nz, nview, px, pz, float(dy), None, flags, view_batch, conv_precision)
     keep = None
     if angles is not None:
         keep = (c_double * nview)(*[float(a) for a in angles])
@@ -131,6 +136,13 @@ def spect_em_step(plan: int, d_x: int, d_y: int, d_r, d_sens: int, stream: int) 
     st = _lib().spect_em_step(plan, d_x, d_y, d_r, d_sens, stream)
     if st != SPECT_OK:
         raise SpectError(st, "spect_em_step")
+
+
+def spect_reg_em_step(plan: int, d_x: int, d_y: int, d_r, d_sens: int, d_u: int, beta: float,
+                      stream: int) -> None:
+    st = _lib().spect_reg_em_step(plan, d_x, d_y, d_r, d_sens, d_u, float(beta), stream)
+    if st != SPECT_OK:
+        raise SpectError(st, "spect_reg_em_step")
 
 
 def spect_em_step_vjp(plan: int, d_x: int, d_y: int, d_r, d_sens: int, d_g: int, d_gx: int,
@@ -196,7 +208,8 @@ class Plan:
     x: [nz][ny][nx], v: [nview][nz][nx], mu: [nz][ny][nx], psf: [nview][ny][pz][px].
     """
 
-    def __init__(self, mu, psf, dy, angles=None, cache_mubar=False, view_batch=0):
+    def __init__(self, mu, psf, dy, angles=None, cache_mubar=False, view_batch=0,
+                 precision="fp32"):
         import torch
         self.device = mu.device
         if self.device.type != "cuda":
@@ -210,7 +223,11 @@ class Plan:
         self.shape = (nx, ny, nz, nview, px, pz)
         self.nx, self.ny, self.nz, self.nview, self.px, self.pz = self.shape
         flags = SPECT_CACHE_MUBAR if cache_mubar else 0
-        self._geom, self._keep = make_geom(nx, ny, nz, nview, px, pz, dy, angles, flags, view_batch)
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        self.precision = precision
+        self._geom, self._keep = make_geom(nx, ny, nz, nview, px, pz, dy, angles, flags, view_batch,
+                                           PRECISIONS[precision])
         self.ws_bytes = spect_workspace_bytes(self._geom)
         self._mu, self._psf = mu, psf
         self._ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
@@ -253,6 +270,19 @@ class Plan:
             _check(r, self.proj_shape, "r", self.device)
         spect_em_step(self._plan, x.data_ptr(), y.data_ptr(), None if r is None else r.data_ptr(),
                       sens.data_ptr(), _stream(torch, self.device))
+        return x
+
+    def reg_em_step(self, x, y, sens, u, beta, r=None):
+        """Regularised EM update of Eq. (7)-(8) in place (target u, weight beta)."""
+        import torch
+        _check(x, self.vol_shape, "x", self.device)
+        _check(y, self.proj_shape, "y", self.device)
+        _check(sens, self.vol_shape, "sens", self.device)
+        _check(u, self.vol_shape, "u", self.device)
+        if r is not None:
+            _check(r, self.proj_shape, "r", self.device)
+        spect_reg_em_step(self._plan, x.data_ptr(), y.data_ptr(), None if r is None else r.data_ptr(),
+                          sens.data_ptr(), u.data_ptr(), beta, _stream(torch, self.device))
         return x
 
     def em_step_vjp(self, x, y, sens, g, r=None, need_gy=True):

@@ -109,6 +109,24 @@ def test_entry_points_reject_null():
     assert lib.spect_forward(None, fake, fake, None) == 1
     assert lib.spect_back(None, fake, fake, None) == 1
     assert lib.spect_em_step(None, fake, fake, None, fake, None) == 1
+    assert lib.spect_reg_em_step(None, fake, fake, None, fake, fake, 0.5, None) == 1
+    assert lib.spect_em_step_vjp(None, fake, fake, None, fake, fake, fake, None, None) == 1
+    # a non-null fake plan pointer is never dereferenced before argument checks
+    assert lib.spect_reg_em_step(fake, fake, fake, None, fake, None, 0.5, None) == 1
+    assert lib.spect_reg_em_step(fake, fake, fake, None, fake, fake, -1.0, None) == 3
+    assert lib.spect_reg_em_step(fake, fake, fake, None, fake, fake, float("nan"), None) == 3
+    assert lib.spect_em_step_vjp(fake, fake, fake, None, fake, fake, None, None, None) == 1
     assert lib.spect_plan_destroy(None) == 1
     assert lib.spect_dot_f64(None, fake, 4, fake, None) == 1
     assert lib.spect_dot_f64(fake, fake, 4, fake + 4, None) == 7
+
+
+def test_conv_precision_validation():
+    for prec in (0, 1, 2):
+        g, _ = spect.make_geom(32, 32, 20, 16, 7, 7, 1.0, conv_precision=prec)
+        assert spect.spect_workspace_bytes(g) > 0
+    for bad in (-1, 3, 99):
+        g, _ = spect.make_geom(32, 32, 20, 16, 7, 7, 1.0, conv_precision=bad)
+        with pytest.raises(spect.SpectError) as e:
+            spect.spect_workspace_bytes(g)
+        assert e.value.status == 3

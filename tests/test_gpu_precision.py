@@ -1,0 +1,166 @@
+"""Reduced-precision PSF convolution (BF16 / FP16 matrix-core operands, FP32
+accumulation) through the C ABI.
+
+Two kinds of check:
+
+1. Kernel exactness.  With every view at angle 0 and mu = 0 the rotation is
+   the identity and the attenuation factor is 1 in FP32, so the forward
+   projection is sum_j conv(round(x_j), round(p_j)) exactly up to FP32
+   accumulation: the GPU result must match the FP64 oracle fed the same
+   rounded inputs within 1e-5.  The adjoint's interior bins likewise; its
+   edge rows and columns are rewritten by the FP32 fold from the unrounded
+   projection and PSF, and match the oracle on unrounded inputs.
+
+2. Stated accuracy on the real workloads against the FP64 oracle on the
+   unrounded inputs.  Rounding the two operands of each product costs at
+   most 2u relative (u = 2^-8 for BF16, 2^-11 for FP16) and the products
+   are positive for forward projections of nonnegative data, so the
+   relative L2 error of forward and back is bounded by 2u (plus FP32
+   accumulation); the measured values are printed.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import em, precision
+from oracle.projector import Geometry
+from paper_2301_09710_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2301_09710_amd import spect  # noqa: E402
+
+DEV = torch.device("cuda:0")
+TOL = 1e-5
+PRECS = ["bf16", "fp16"]
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+EXACT_CASES = [
+    # nx, nz, nview, px, pz
+    (32, 20, 4, 7, 7),
+    (37, 13, 3, 9, 5),
+    (16, 1, 2, 41, 3),      # kernel wider than the plane, one slice
+    (48, 40, 3, 19, 19),
+    (9, 4, 1, 1, 1),
+    (128, 80, 2, 37, 37),   # the paper-scale plane and PSF
+]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("case", EXACT_CASES)
+def test_lp_kernels_exact_on_rounded_inputs(case, prec):
+    nx, nz, nview, px, pz = case
+    say(f"lp exact {prec} {case}")
+    seed = nx * 7 + nz
+    x = synth.random_volume(nx, nx, nz, seed=seed)
+    mu = np.zeros_like(x)
+    psf = synth.random_psf(px, pz, nx, nview, seed=seed + 1, symmetric=False)
+    angles = [0.0] * nview
+    g = Geometry(nx, nx, nz, nview, px, pz, 1.0, angles=angles)
+    rnd = precision.rounder(prec)
+    plan = spect.Plan(to_dev(mu), to_dev(psf), 1.0, angles=angles, precision=prec)
+    v = host(plan.forward(to_dev(x)))
+    v_ref = oracle.forward(rnd(x), mu, rnd(psf), g)
+    assert rel_l2(v, v_ref) <= TOL
+    y = synth.random_volume(nx, nz, nview, seed=seed + 2)          # [nview][nz][nx]
+    b = host(plan.back(to_dev(y)))
+    b_rnd = oracle.back(rnd(y), mu, rnd(psf), g)
+    b_fp = oracle.back(y, mu, psf, g)
+    interior = np.zeros(b.shape, dtype=bool)
+    interior[1:nz - 1, :, 1:nx - 1] = True
+    if interior.any():
+        assert rel_l2(b[interior], b_rnd[interior]) <= TOL
+    assert rel_l2(b[~interior], b_fp[~interior]) <= TOL
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    x, mu, psf, dy = synth.config_inputs("tiny", seed=0, view_wobble=0.1)
+    g = Geometry(32, 32, 20, 16, 7, 7, dy)
+    v_ref = oracle.forward(x, mu, psf, g)
+    y = np.random.default_rng(1).uniform(0.5, 1.5, size=v_ref.shape).astype(np.float32)
+    return dict(x=x, mu=mu, psf=psf, dy=dy, g=g, v_ref=v_ref, y=y, b_ref=oracle.back(y, mu, psf, g))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_lp_accuracy_tiny(tiny, prec):
+    u = precision.unit_roundoff(prec)
+    plan = spect.Plan(to_dev(tiny["mu"]), to_dev(tiny["psf"]), tiny["dy"], precision=prec)
+    ef = rel_l2(host(plan.forward(to_dev(tiny["x"]))), tiny["v_ref"])
+    eb = rel_l2(host(plan.back(to_dev(tiny["y"]))), tiny["b_ref"])
+    say(f"{prec} tiny: forward {ef:.2e}, back {eb:.2e} (2u = {2 * u:.2e})")
+    assert ef <= 2 * u and eb <= 2 * u
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_lp_em_ten_iterations_tiny(tiny, prec):
+    """10 ML-EM iterations with the reduced-precision projector against the
+    FP64 oracle's iterates (the precision study's reconstruction error)."""
+    A = lambda v: oracle.forward(np.asarray(v).reshape(20, 32, 32), tiny["mu"], tiny["psf"], tiny["g"])
+    At = lambda v: oracle.back(v, tiny["mu"], tiny["psf"], tiny["g"])
+    yc = tiny["v_ref"]
+    r = np.full(yc.shape, 0.05 * yc.mean())
+    y = synth.poisson_counts(yc * 50 + r, seed=5).astype(np.float32)
+    r = r.astype(np.float32)
+    sens = At(np.ones(yc.shape))
+    x = np.ones_like(tiny["x"], dtype=np.float64)
+    for _ in range(10):
+        x = em.mlem_step(x, y, r, sens, A, At)
+    plan = spect.Plan(to_dev(tiny["mu"]), to_dev(tiny["psf"]), tiny["dy"], precision=prec)
+    sd = plan.back(torch.ones(plan.proj_shape, device=DEV))
+    xd = torch.ones(plan.vol_shape, device=DEV)
+    yd, rd = to_dev(y), to_dev(r)
+    for _ in range(10):
+        plan.em_step(xd, yd, sd, rd)
+    e = rel_l2(host(xd), x)
+    u = precision.unit_roundoff(prec)
+    say(f"{prec} tiny EM x10: {e:.2e} (u = {u:.2e})")
+    assert e <= 10 * u
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_lp_accuracy_paper_sampled_views(prec):
+    """128x128x80, 128 views, 37x37 PSFs; forward on 4 sampled views and the
+    back projection of a projection that is nonzero on those views only."""
+    say(f"{prec} paper-size accuracy")
+    x, mu, psf, dy = synth.config_inputs("paper", seed=0)
+    g = Geometry(128, 128, 80, 128, 37, 37, dy)
+    views = [0, 21, 64, 107]
+    plan = spect.Plan(to_dev(mu), to_dev(psf), dy, cache_mubar=True, precision=prec)
+    v = host(plan.forward(to_dev(x)))
+    v_ref = oracle.forward(x, mu, psf, g, views=views, conv="fft")
+    ef = rel_l2(v[views], v_ref[views])
+    y = np.zeros((128, 80, 128), dtype=np.float32)
+    y[views] = np.random.default_rng(3).uniform(0.5, 1.5, size=(len(views), 80, 128))
+    b = host(plan.back(to_dev(y)))
+    b_ref = oracle.back(y, mu, psf, g, views=views, conv="fft")
+    eb = rel_l2(b, b_ref)
+    u = precision.unit_roundoff(prec)
+    say(f"{prec} paper: forward {ef:.2e}, back {eb:.2e} (2u = {2 * u:.2e})")
+    assert ef <= 2 * u and eb <= 2 * u

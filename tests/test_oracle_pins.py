@@ -410,3 +410,53 @@ def test_regularized_update_limit_and_quadratic():
         np.testing.assert_allclose(beta * xh ** 2 + d * xh - x * e, 0, atol=1e-12)
         assert (xh >= 0).all()
     np.testing.assert_allclose(em.reg_em_update(x, e, s, u, 1e-12), x * e / s, rtol=1e-9)
+
+
+# ------------------------------------------------------------ reduced-precision rounding
+
+def test_rounding_hand_values_and_library():
+    from oracle import precision
+    # ties go to the even neighbour; spacing at 1 is 2^-7 (bf16), 2^-10 (fp16)
+    bf = precision.round_bf16(np.float32([1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -7, -2.0, 0.0]))
+    np.testing.assert_array_equal(bf, [1.0, 1 + 2 ** -6, 1 + 2 ** -7, -2.0, 0.0])
+    hf = precision.round_fp16(np.float32([1 + 2 ** -11, 1 + 3 * 2 ** -11, 65504.0, 2 ** -24]))
+    np.testing.assert_array_equal(hf, [1.0, 1 + 2 ** -9, 65504.0, 2 ** -24])
+    assert np.isinf(precision.round_fp16(np.float32([65520.0]))[0])
+    # agreement with torch's own narrowing conversions on random values
+    torch = pytest.importorskip("torch")
+    x = np.random.default_rng(0).normal(size=4096).astype(np.float32) * 10.0 ** np.random.default_rng(1).uniform(-6, 4, size=4096).astype(np.float32)
+    tb = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    th = torch.from_numpy(x).to(torch.float16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(precision.round_bf16(x), tb)
+    np.testing.assert_array_equal(precision.round_fp16(x), th)
+    assert precision.unit_roundoff("bf16") == 2.0 ** -8
+
+
+def test_osem_one_subset_is_mlem_and_subsets_partition_views():
+    xt, A, At, g = _tiny_problem()
+    subs = em.osem_subsets(g.nview, 4)
+    assert sorted(sum(subs, [])) == list(range(g.nview)) and all(len(s) > 0 for s in subs)
+    y = A(xt) * 1.3 + 0.2
+    A1 = lambda s, z: A(z)
+    At1 = lambda s, v: At(v)
+    x_os = em.osem(np.ones_like(xt), y, None, A1, At1, g.nview, 1, 3)
+    sens = At(np.ones(y.shape))
+    x_ml = np.ones_like(xt)
+    for _ in range(3):
+        x_ml = em.mlem_step(x_ml, y, None, sens, A, At)
+    np.testing.assert_array_equal(x_os, x_ml)
+
+
+def test_osem_subset_projector_restricts_views():
+    """A subset's projector (the same oracle on the subset's angles and PSF
+    slices) reproduces the full projector's rows for those views."""
+    nx, nz, nview = 10, 4, 6
+    x, mu = synth.body_phantom(nx, nx, nz, seed=1)
+    psf = synth.random_psf(3, 3, nx, nview, seed=2, symmetric=False)
+    g = Geometry(nx, nx, nz, nview, 3, 3, 2.0)
+    full = oracle.forward(x, mu, psf, g)
+    for views in em.osem_subsets(nview, 3):
+        ang = [2 * math.pi * l / nview for l in views]
+        gs = Geometry(nx, nx, nz, len(views), 3, 3, 2.0, angles=ang)
+        np.testing.assert_allclose(oracle.forward(x, mu, psf[views], gs), full[views], rtol=1e-13,
+                                   atol=1e-13 * np.abs(full).max())
