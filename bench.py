@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_PEAK_TFLOPS = 157.3          # MI355X published FP32 matrix (MFMA) peak, dense
+LP_PEAK_TFLOPS = 2500.0           # MI355X published dense BF16 / FP16 matrix peak
 HBM_PEAK_GBS = 8000.0
 
 
@@ -42,6 +43,14 @@ def parse():
                     help="views in the bounded oracle sample (0 disables the CPU baseline)")
     ap.add_argument("--grad-iters", type=int, default=10,
                     help="unrolled EM iterations differentiated end to end (0 disables)")
+    ap.add_argument("--precision-steps", type=int, default=10,
+                    help="pairs timed for each reduced-precision (BF16, FP16) convolution plan (0 disables)")
+    ap.add_argument("--serve-requests", type=int, default=48,
+                    help="requests in the continuous-batching serving trace (0 disables)")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="mean arrivals per second")
+    ap.add_argument("--serve-slots", type=int, default=4, help="concurrent requests at most")
+    ap.add_argument("--serve-precision", default="bf16", choices=["fp32", "bf16", "fp16"],
+                    help="convolution precision of the served reconstructions")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB device-to-device: a plain "
@@ -207,6 +216,50 @@ def main():
         em = {"iters": args.em_iters, "recons": args.em_recons, "p50_ms": pct(lat, 50),
               "p99_ms": pct(lat, 99)}
 
+    # Reduced-precision convolution (not part of `value`): the same pair with
+    # BF16 / FP16 matrix-core operands, its speed and its distance from the
+    # FP32 path (itself within 1e-5 of the FP64 oracle).
+    lp = None
+    if args.precision_steps > 0:
+        lp = {}
+        ref_v = vd.double()
+        ref_b = bd.double()
+        for prec in ("bf16", "fp16"):
+            pl = spect.Plan(mud, psfd, dy, cache_mubar=bool(args.cache_mubar), precision=prec)
+            v2 = torch.empty_like(vd)
+            b2 = torch.empty_like(bd)
+            for _ in range(args.warmup):
+                pl.forward(xd, out=v2)
+                pl.back(vd, out=b2)
+            torch.cuda.synchronize()
+            pl.profile_start(max_launches=64 * args.precision_steps + 64)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(args.precision_steps):
+                pl.forward(xd, out=v2)
+                pl.back(v2, out=b2)
+            b.record()
+            torch.cuda.synchronize()
+            kt = pl.profile_stop()
+            ms = a.elapsed_time(b) / args.precision_steps
+            pl.back(vd, out=b2)          # adjoint of the same input as the FP32 reference
+            pl.forward(xd, out=v2)
+            torch.cuda.synchronize()
+            kav = {k: v["total_ms"] / v["launches"] for k, v in kt.items()}
+            fwd_ms = kav.get("conv_fwd_lp")
+            lp[prec] = {
+                "pairs_per_s": 1000.0 / ms, "ms_per_pair": ms,
+                "rel_l2_forward_vs_fp32": float((v2.double() - ref_v).norm() / ref_v.norm()),
+                "rel_l2_back_vs_fp32": float((b2.double() - ref_b).norm() / ref_b.norm()),
+                "kernels_ms_per_launch": kav,
+                "conv_fwd_roofline": None if not fwd_ms else {
+                    "bound": "mfma", "achieved": conv_flops / (fwd_ms * 1e-3) / 1e12,
+                    "peak": LP_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": conv_flops / (fwd_ms * 1e-3) / 1e12 / LP_PEAK_TFLOPS},
+            }
+            pl.close()
+            del pl, v2, b2
+
     # Differentiation through unrolled EM (not part of `value`): MSE against the
     # phantom backpropagated to x0 and y through `grad_iters` EM updates.
     grad = None
@@ -218,6 +271,10 @@ def main():
         rg = torch.full_like(yc, 0.05 * float(yc.mean()))
         yg = torch.poisson(yc + rg)
         x0 = torch.full_like(xd, float(xd.mean()))
+        # one untimed pass so that the timed one sees warm allocator pools
+        xw = x0.clone().requires_grad_(True)
+        ((sag.unrolled_mlem(plan, xw, yg, sens, rg, iters=1) - xd) ** 2).mean().backward()
+        del xw
         torch.cuda.synchronize()
         base_mem = torch.cuda.memory_allocated(dev)
         torch.cuda.reset_peak_memory_stats(dev)
@@ -236,6 +293,33 @@ def main():
                 "projector_directions": 6 * args.grad_iters,
                 "peak_extra_mb": (torch.cuda.max_memory_allocated(dev) - base_mem) / 2 ** 20}
         del x0g, ygg, xk, loss
+
+    # Continuous-batching EM service (not part of `value`): Poisson arrivals of
+    # reconstructions of three sizes, 8 EM iterations each.
+    serving = None
+    if args.serve_requests > 0:
+        from paper_2301_09710_amd import serve as sv
+        trace = sv.poisson_trace(args.serve_requests, args.serve_rate, seed=args.seed + 1,
+                                 precision=args.serve_precision)
+        t_gen = time.perf_counter()
+        data = {r.rid: sv.RequestData(r, dev) for r in trace}
+        t_gen = time.perf_counter() - t_gen
+        budget = int(0.5 * torch.cuda.get_device_properties(dev).total_memory)
+        sched = sv.Scheduler(budget, args.serve_slots,
+                             lambda r: sv.request_bytes(r.size, r.precision))
+        ex = sv.GpuExecutor(dev, data, max_slots=args.serve_slots, keep_results=False)
+        torch.cuda.synchronize()
+        t_s = time.perf_counter()
+        done = sv.serve(trace, sched, ex)
+        torch.cuda.synchronize()
+        wall_s = time.perf_counter() - t_s
+        serving = sv.summarize(done, wall_s)
+        serving.update({"rate_req_s": args.serve_rate, "slots": args.serve_slots,
+                        "precision": args.serve_precision, "iters": trace[0].iters,
+                        "budget_gb": budget / 1e9, "peak_admitted_gb": sched.peak / 1e9,
+                        "wall_s": wall_s, "trace_s": trace[-1].arrival,
+                        "data_generation_s (untimed)": t_gen})
+        del data, ex, sched
 
     if args.copy_mb > 0:
         nbytes = args.copy_mb << 20
@@ -272,6 +356,8 @@ def main():
         "wall_s_timed": wall,
         "em_recon_latency": em,
         "unrolled_em_grad": grad,
+        "reduced_precision": lp,
+        "serving": serving,
         "kernels_ms_per_launch": avg_ms,
         "roofline": roof,
         "cpu_baseline": cpu,
