@@ -140,68 +140,52 @@ __device__ __forceinline__ void stage_region(unsigned* Rt, const float* __restri
   }
 }
 
-// Operands of one k-step: A (4 words) and the B of the NN N-blocks.
-template <int NN>
-struct Step {
-  u32x4 a;
-  u32x4 b[NN];
-};
-
-// The (tap, 8-row chunk) pair of this lane group advances by four chunks per
-// k-step: c7 += 4, carried into the tap.  C7 >= 2, so two carries suffice.
-__device__ __forceinline__ void advance(int& t, int& c7, int C7) {
-  c7 += 4;
-  if (c7 >= C7) { c7 -= C7; ++t; }
-  if (c7 >= C7) { c7 -= C7; ++t; }
-}
-
-// Operands of the k-step whose lane-group chunk is (t, c7); taps t >= px
-// (the k-steps past the last chunk) read the zero row of the PSF table and
-// an in-range B.
-template <int NN, bool kBack>
-__device__ __forceinline__ void load_step(Step<NN>& st, const unsigned* QP, const u32x4* R4,
-                                          const LpShape& s, int t, int c7, int m, int n, int w) {
-  const bool in = t < s.px;
-  const int ta = in ? t : s.px, tb = in ? t : 0;
-  const unsigned* q = QP + ta * s.QL + 8 * c7 - m + 15;
-  st.a = u32x4{q[0], q[2], q[4], q[6]};
-  const int col0 = kBack ? n + tb : n - tb + 2 * s.ha;
-  const u32x4* b = R4 + (col0 * s.RS + 16 * w + 8 * c7) / 8;   // 16-byte aligned
-  const int ustride = 2 * s.RS;                                 // 16 columns, in 16-byte units
-#pragma unroll
-  for (int u = 0; u < NN; ++u) st.b[u] = b[u * ustride];
-}
-
-// All k-steps of one plane (KSt is even), the operands of the next k-step
-// read while the MFMAs of the current one run.  m: A row of this lane
-// (lane mod 16); n: B column (the same lane mod 16); g: lane group.
-template <class T, int NN, bool kBack>
-__device__ __forceinline__ void plane_mma(floatx4 (&acc)[NN], const unsigned* QP,
-                                          const unsigned* Rt, const LpShape& s, int g, int m,
-                                          int n, int w) {
+// All taps of one plane, in quads: lane group g takes tap 4 tq + g (taps past
+// px read the zero PSF row).  For each absolute 8-row chunk R of the region,
+// the B operands of the wave's two N-blocks are read once and feed every
+// M-block b whose band holds the chunk (relative chunk c = R - 2b in
+// [0, C7)), with the A operand of relative chunk c kept in registers for the
+// whole quad.  B of chunk R + 1 is read while the MFMAs of chunk R run.
+//   acc[b][u]: M-block b (z rows k0 + 16 b ..), N-block u of this wave.
+template <class T, int C7, bool kBack>
+__device__ __forceinline__ void plane_quads(floatx4 (&acc)[kLpMaxWaves][2], const unsigned* QP,
+                                            const unsigned* Rt, const LpShape& s, int g, int m,
+                                            int n, int w) {
+  constexpr int kNRMax = 2 * (kLpMaxWaves - 1) + C7;
   const u32x4* R4 = reinterpret_cast<const u32x4*>(Rt);
-  int t = 0, c7 = g;
-  if (c7 >= s.C7) { c7 -= s.C7; ++t; }
-  if (c7 >= s.C7) { c7 -= s.C7; ++t; }
-  Step<NN> x, y;
-  load_step<NN, kBack>(x, QP, R4, s, t, c7, m, n, w);
-  advance(t, c7, s.C7);
-  // The scheduling barriers keep each k-step's loads ahead of the previous
-  // k-step's MFMAs (left alone, the scheduler pairs every load with its MFMA
-  // and exposes the LDS latency).
-  for (int ks = 0; ks < s.KSt; ks += 2) {
-    load_step<NN, kBack>(y, QP, R4, s, t, c7, m, n, w);
-    advance(t, c7, s.C7);
-    __builtin_amdgcn_sched_barrier(0);
+  for (int tq = 0; tq < s.ntq; ++tq) {
+    const int t = 4 * tq + g;
+    const bool in = t < s.px;
+    const int ta = in ? t : s.px, tb = in ? t : 0;
+    const unsigned* q = QP + ta * s.QL - m + 15;
+    u32x4 A[C7];
 #pragma unroll
-    for (int u = 0; u < NN; ++u) acc[u] = Lp<T>::mfma(x.a, x.b[u], acc[u]);
-    __builtin_amdgcn_sched_barrier(0);
-    load_step<NN, kBack>(x, QP, R4, s, t, c7, m, n, w);
-    advance(t, c7, s.C7);
-    __builtin_amdgcn_sched_barrier(0);
+    for (int c = 0; c < C7; ++c) A[c] = u32x4{q[8 * c], q[8 * c + 2], q[8 * c + 4], q[8 * c + 6]};
+    const int col = kBack ? 32 * w + n + tb : 32 * w + n - tb + 2 * s.ha;
+    const u32x4* b0 = R4 + (col * s.RS) / 8;             // chunk R: b0[R] (16-byte units)
+    const u32x4* b1 = R4 + ((col + 16) * s.RS) / 8;
+    u32x4 x0 = b0[0], x1 = b1[0];
 #pragma unroll
-    for (int u = 0; u < NN; ++u) acc[u] = Lp<T>::mfma(y.a, y.b[u], acc[u]);
-    __builtin_amdgcn_sched_barrier(0);
+    for (int R = 0; R < kNRMax; ++R) {
+      if (R >= s.NR) break;
+      u32x4 y0 = x0, y1 = x1;
+      if (R + 1 < s.NR) {
+        y0 = b0[R + 1];
+        y1 = b1[R + 1];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int b = 0; b < kLpMaxWaves; ++b) {
+        const int c = R - 2 * b;
+        if (c >= 0 && c < C7 && b < s.WKm) {
+          acc[b][0] = Lp<T>::mfma(A[c], x0, acc[b][0]);
+          acc[b][1] = Lp<T>::mfma(A[c], x1, acc[b][1]);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      x0 = y0;
+      x1 = y1;
+    }
   }
 }
 
@@ -222,61 +206,74 @@ __device__ __forceinline__ void plane_range(int c, int nchunk, int ny, int& j0, 
   j1 = (int)(((long long)(c + 1) * ny) / nchunk);
 }
 
+__device__ __forceinline__ void zero_acc(floatx4 (&acc)[kLpMaxWaves][2]) {
+#pragma unroll
+  for (int b = 0; b < kLpMaxWaves; ++b) acc[b][0] = acc[b][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+}
+
+// acc[b][u][v] -> bin (k0 + 16 b + 4 g + v, i0 + 32 w + 16 u + n) of a plane
+// whose row k starts at out + k * kstride.
+__device__ __forceinline__ void store_acc(const floatx4 (&acc)[kLpMaxWaves][2], float* out,
+                                          size_t kstride, const LpShape& s, int k0, int i0, int w,
+                                          int g, int n) {
+#pragma unroll
+  for (int b = 0; b < kLpMaxWaves; ++b)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = k0 + 16 * b + 4 * g + v, i = i0 + 32 * w + 16 * u + n;
+        if (b < s.WKm && k < s.nz && i < s.nx) out[(size_t)k * kstride + i] = acc[b][u][v];
+      }
+}
+
 // ---------------------------------------------------------------- forward
 // partial[c][lb][k][i] = sum over the planes j of chunk c of (p_{j,l} * W_j)[k][i]
-template <class T, int NN>
-__global__ __launch_bounds__(64 * kLpMaxWaves) void conv_fwd_lp(const float* __restrict__ W,
-                                                                const float* __restrict__ psf,
-                                                                float* __restrict__ partial,
-                                                                LpShape s, int view0, int nvb) {
+template <class T, int C7>
+__global__ __launch_bounds__(256) void conv_fwd_lp(const float* __restrict__ W,
+                                                   const float* __restrict__ psf,
+                                                   float* __restrict__ partial, LpShape s,
+                                                   int view0, int nvb) {
   extern __shared__ unsigned lds[];
   unsigned* Rt = lds;                                  // RC * RS / 2 words
   unsigned* QP = lds + s.RC * s.RS / 2;                // (px + 1) * QL words
   int tk, ti, c, lb;
   decode(s, tk, ti, c, lb, s.nchunk);
   const int l = view0 + lb;
-  const int k0 = tk * 16 * s.WKm, i0 = ti * 16 * NN;
+  const int k0 = tk * 16 * s.WKm, i0 = ti * 32 * s.NN;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
   int j0, j1;
   plane_range(c, s.nchunk, s.ny, j0, j1);
   const size_t zstride = (size_t)s.ny * s.nx;
   const float* Wl = W + (size_t)lb * s.nz * zstride;
-  floatx4 acc[NN];
-#pragma unroll
-  for (int u = 0; u < NN; ++u) acc[u] = floatx4{0.f, 0.f, 0.f, 0.f};
+  floatx4 acc[kLpMaxWaves][2];
+  zero_acc(acc);
   for (int j = j0; j < j1; ++j) {
     __syncthreads();                                   // previous plane consumed
     stage_region<T, true>(Rt, Wl + (size_t)j * s.nx, zstride, s, k0, i0);
     stage_psf<T, false>(QP, psf + ((size_t)l * s.ny + j) * s.pz * s.px, s);
     __syncthreads();
-    plane_mma<T, NN, false>(acc, QP, Rt, s, g, n, n, w);
+    plane_quads<T, C7, false>(acc, QP, Rt, s, g, n, n, w);
   }
-  float* out = partial + ((size_t)c * nvb + lb) * s.nz * s.nx;
-#pragma unroll
-  for (int u = 0; u < NN; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int k = k0 + 16 * w + 4 * g + v, i = i0 + 16 * u + n;
-      if (k < s.nz && i < s.nx) out[(size_t)k * s.nx + i] = acc[u][v];
-    }
+  store_acc(acc, partial + ((size_t)c * nvb + lb) * s.nz * s.nx, (size_t)s.nx, s, k0, i0, w, g, n);
 }
 
 // ---------------------------------------------------------------- adjoint
 // U[lb][k][j][i] = zero-padded correlation of the projection of view l with
 // p_{j,l}; exact off the edge rows and columns, which the FP32 edge kernel
 // rewrites afterwards.
-template <class T, int NN>
-__global__ __launch_bounds__(64 * kLpMaxWaves) void conv_back_lp(const float* __restrict__ v,
-                                                                 const float* __restrict__ psf,
-                                                                 float* __restrict__ U, LpShape s,
-                                                                 int view0, int nvb) {
+template <class T, int C7>
+__global__ __launch_bounds__(256) void conv_back_lp(const float* __restrict__ v,
+                                                    const float* __restrict__ psf,
+                                                    float* __restrict__ U, LpShape s, int view0,
+                                                    int nvb) {
   extern __shared__ unsigned lds[];
   unsigned* Rt = lds;
   unsigned* QP = lds + s.RC * s.RS / 2;
   int tk, ti, c, lb;
   decode(s, tk, ti, c, lb, s.nchunk_back);
   const int l = view0 + lb;
-  const int k0 = tk * 16 * s.WKm, i0 = ti * 16 * NN;
+  const int k0 = tk * 16 * s.WKm, i0 = ti * 32 * s.NN;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
   int j0, j1;
   plane_range(c, s.nchunk_back, s.ny, j0, j1);
@@ -285,18 +282,11 @@ __global__ __launch_bounds__(64 * kLpMaxWaves) void conv_back_lp(const float* __
     __syncthreads();                                   // region staged / previous plane consumed
     stage_psf<T, true>(QP, psf + ((size_t)l * s.ny + j) * s.pz * s.px, s);
     __syncthreads();
-    floatx4 acc[NN];
-#pragma unroll
-    for (int u = 0; u < NN; ++u) acc[u] = floatx4{0.f, 0.f, 0.f, 0.f};
-    plane_mma<T, NN, true>(acc, QP, Rt, s, g, n, n, w);
-    float* out = U + (size_t)lb * s.nz * s.ny * s.nx + (size_t)j * s.nx;
-#pragma unroll
-    for (int u = 0; u < NN; ++u)
-#pragma unroll
-      for (int vv = 0; vv < 4; ++vv) {
-        const int k = k0 + 16 * w + 4 * g + vv, i = i0 + 16 * u + n;
-        if (k < s.nz && i < s.nx) out[(size_t)k * s.ny * s.nx + i] = acc[u][vv];
-      }
+    floatx4 acc[kLpMaxWaves][2];
+    zero_acc(acc);
+    plane_quads<T, C7, true>(acc, QP, Rt, s, g, n, n, w);
+    store_acc(acc, U + (size_t)lb * s.nz * s.ny * s.nx + (size_t)j * s.nx, (size_t)s.ny * s.nx, s,
+              k0, i0, w, g, n);
   }
 }
 
@@ -304,35 +294,26 @@ hipError_t set_lds(const void* fn, size_t bytes) {
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-// Instantiations: NN in {1, 2, 4, 8} (N-blocks per wave), T in {bf16, f16}.
-template <class T, bool kBack, class F>
-hipError_t with_nn(int NN, F&& f) {
-  switch (NN) {
-    case 1: return f(std::integral_constant<int, 1>());
-    case 2: return f(std::integral_constant<int, 2>());
-    case 4: return f(std::integral_constant<int, 4>());
-    case 8: return f(std::integral_constant<int, 8>());
-    default: return hipErrorInvalidValue;
+// Instantiations: C7 (8-row chunks of a tap band) in 2..8, T in {bf16, f16}.
+#define SPECT_C7_CASES(X) X(2) X(3) X(4) X(5) X(6) X(7) X(8)
+
+template <class T>
+const void* fwd_fn(int C7) {
+  switch (C7) {
+#define CASE(C) case C: return (const void*)conv_fwd_lp<T, C>;
+    SPECT_C7_CASES(CASE)
+#undef CASE
+    default: return nullptr;
   }
 }
 
 template <class T>
-const void* fwd_fn(int NN) {
-  switch (NN) {
-    case 1: return (const void*)conv_fwd_lp<T, 1>;
-    case 2: return (const void*)conv_fwd_lp<T, 2>;
-    case 4: return (const void*)conv_fwd_lp<T, 4>;
-    default: return (const void*)conv_fwd_lp<T, 8>;
-  }
-}
-
-template <class T>
-const void* back_fn(int NN) {
-  switch (NN) {
-    case 1: return (const void*)conv_back_lp<T, 1>;
-    case 2: return (const void*)conv_back_lp<T, 2>;
-    case 4: return (const void*)conv_back_lp<T, 4>;
-    default: return (const void*)conv_back_lp<T, 8>;
+const void* back_fn(int C7) {
+  switch (C7) {
+#define CASE(C) case C: return (const void*)conv_back_lp<T, C>;
+    SPECT_C7_CASES(CASE)
+#undef CASE
+    default: return nullptr;
   }
 }
 
@@ -340,36 +321,45 @@ template <class T>
 hipError_t launch_fwd_t(const LpShape& s, const float* W, const float* psf, float* partial,
                         int view0, int nvb, hipStream_t st) {
   const size_t sm = lp_lds_bytes(s);
-  hipError_t e = set_lds(fwd_fn<T>(s.NN), sm);
+  const void* fn = fwd_fn<T>(s.C7);
+  if (!fn) return hipErrorInvalidValue;
+  hipError_t e = set_lds(fn, sm);
   if (e != hipSuccess) return e;
-  const dim3 grid((unsigned)(s.tiles_k * s.tiles_i * s.nchunk * nvb)), block(64 * s.WKm);
-  return with_nn<T, false>(s.NN, [&](auto NN) {
-    hipLaunchKernelGGL((conv_fwd_lp<T, NN.value>), grid, block, sm, st, W, psf, partial, s, view0,
-                       nvb);
-    return hipGetLastError();
-  });
+  const dim3 grid((unsigned)(s.tiles_k * s.tiles_i * s.nchunk * nvb)), block(64 * s.NN);
+  switch (s.C7) {
+#define CASE(C) \
+  case C: hipLaunchKernelGGL((conv_fwd_lp<T, C>), grid, block, sm, st, W, psf, partial, s, view0, nvb); break;
+    SPECT_C7_CASES(CASE)
+#undef CASE
+  }
+  return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_back_t(const LpShape& s, const float* v, const float* psf, float* U, int view0,
                          int nvb, hipStream_t st) {
   const size_t sm = lp_lds_bytes(s);
-  hipError_t e = set_lds(back_fn<T>(s.NN), sm);
+  const void* fn = back_fn<T>(s.C7);
+  if (!fn) return hipErrorInvalidValue;
+  hipError_t e = set_lds(fn, sm);
   if (e != hipSuccess) return e;
-  const dim3 grid((unsigned)(s.tiles_k * s.tiles_i * s.nchunk_back * nvb)), block(64 * s.WKm);
-  return with_nn<T, true>(s.NN, [&](auto NN) {
-    hipLaunchKernelGGL((conv_back_lp<T, NN.value>), grid, block, sm, st, v, psf, U, s, view0, nvb);
-    return hipGetLastError();
-  });
+  const dim3 grid((unsigned)(s.tiles_k * s.tiles_i * s.nchunk_back * nvb)), block(64 * s.NN);
+  switch (s.C7) {
+#define CASE(C) \
+  case C: hipLaunchKernelGGL((conv_back_lp<T, C>), grid, block, sm, st, v, psf, U, s, view0, nvb); break;
+    SPECT_C7_CASES(CASE)
+#undef CASE
+  }
+  return hipGetLastError();
 }
 
 template <class T>
 int lp_wgs_per_cu(const LpShape& s, bool back) {
   int nb = 0;
-  const void* fn = back ? back_fn<T>(s.NN) : fwd_fn<T>(s.NN);
+  const void* fn = back ? back_fn<T>(s.C7) : fwd_fn<T>(s.C7);
   const size_t sm = lp_lds_bytes(s);
-  if (set_lds(fn, sm) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 64 * s.WKm, sm) != hipSuccess || nb < 1)
+  if (!fn || set_lds(fn, sm) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 64 * s.NN, sm) != hipSuccess || nb < 1)
     nb = (int)(kLdsBytes / (sm ? sm : 1));
   return nb < 1 ? 1 : nb;
 }
@@ -400,19 +390,16 @@ LpShape make_lp_shape(const spect_geom& g) {
   s.ha = (g.px - 1) / 2; s.hb = (g.pz - 1) / 2;
   const int nmb = (g.nz + 15) / 16;
   s.tiles_k = (nmb + kLpMaxWaves - 1) / kLpMaxWaves;
-  s.WKm = (nmb + s.tiles_k - 1) / s.tiles_k;
-  const int nblk = (g.nx + 15) / 16;
-  s.NN = nblk >= 8 ? 8 : (nblk >= 4 ? 4 : (nblk >= 2 ? 2 : 1));
-  if (nblk > 4 && nblk < 8) s.NN = 8;
-  if (nblk == 3) s.NN = 4;
-  s.tiles_i = (nblk + s.NN - 1) / s.NN;
+  s.WKm = (nmb + s.tiles_k - 1) / s.tiles_k;        // M-blocks per workgroup tile
+  const int nwv = (g.nx + 31) / 32;
+  s.NN = nwv < 4 ? nwv : 4;                          // waves per workgroup, 32 x bins each
+  s.tiles_i = (nwv + s.NN - 1) / s.NN;
   s.C7 = (15 + g.pz + 7) / 8;
-  s.nchunks = g.px * s.C7;
-  s.KSt = (s.nchunks + 3) / 4;
-  s.KSt += s.KSt & 1;                  // even: the k-step loop runs in pairs
+  s.ntq = (g.px + 3) / 4;
+  s.NR = 2 * (s.WKm - 1) + s.C7;
   s.RR = 16 * (s.WKm - 1) + 8 * s.C7;
   s.RS = odd8_stride(s.RR);
-  s.RC = 16 * s.NN + g.px - 1;
+  s.RC = 32 * s.NN + g.px - 1;
   s.QL = 8 * s.C7 + 15;
   s.nchunk = 1;
   s.nchunk_back = 1;
@@ -424,7 +411,8 @@ size_t lp_lds_bytes(const LpShape& s) {
 }
 
 bool lp_supported(const spect_geom& g) {
-  return lp_lds_bytes(make_lp_shape(g)) <= kLdsBytes;
+  const LpShape s = make_lp_shape(g);
+  return s.C7 >= 2 && s.C7 <= 8 && lp_lds_bytes(s) <= kLdsBytes;
 }
 
 void tune_lp_chunks(LpShape& s, int views, int precision) {

@@ -45,12 +45,12 @@ struct ConvShape {
 };
 
 // Tiling of the BF16 / FP16 convolution (see conv_lp.hip).
-constexpr int kLpMaxWaves = 8;   // M-blocks (waves) per workgroup at most
+constexpr int kLpMaxWaves = 8;   // M-blocks (16 z each) per workgroup tile at most
 struct LpShape {
   int nx, ny, nz, px, pz, ha, hb;
-  int WKm, NN;            // waves (M-blocks of 16 z) per workgroup, N-blocks of 16 x per wave
-  int tiles_k, tiles_i;   // workgroup tiles of 16 WKm x 16 NN output bins
-  int C7, nchunks, KSt;   // 8-row chunks per tap band, px * C7, k-steps of 4 chunks
+  int WKm, NN;            // M-blocks per tile; waves per workgroup (32 x bins each)
+  int tiles_k, tiles_i;   // workgroup tiles of 16 WKm x 32 NN output bins
+  int C7, ntq, NR;        // 8-row chunks per tap band, tap quads, region chunks
   int RR, RS, RC;         // region rows used, column stride (elements), columns
   int QL;                 // PSF pair-table row length (words)
   int nchunk, nchunk_back;// depth chunks (forward, adjoint)
