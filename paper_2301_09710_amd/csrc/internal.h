@@ -51,7 +51,8 @@ struct LpShape {
   int WKm, NN;            // M-blocks per tile; waves per workgroup (32 x bins each)
   int tiles_k, tiles_i;   // workgroup tiles of 16 WKm x 32 NN output bins
   int C7, ntq, NR;        // 8-row chunks per tap band, tap quads, region chunks
-  int RR, RS, RC;         // region rows used, column stride (elements), columns
+  int RR, RS, RC;         // region rows used, column stride (elements), columns used
+  int dx, RCa;            // column shift aligning the region origin to 4; columns staged
   int QL;                 // PSF pair-table row length (words)
   int nchunk, nchunk_back;// depth chunks (forward, adjoint)
 };
