@@ -14,6 +14,9 @@ namespace spect {
 // floats), the scan segments and the per-view tables fit in the 160 KiB LDS
 // of a gfx950 CU.
 constexpr int kMaxLdsN = 136;
+// Largest in-plane size: beyond kMaxLdsN the rotation kernels keep their
+// working slices in global scratch (one per workgroup) instead of LDS.
+constexpr int kMaxN = 256;
 // Threads per workgroup of the rotation kernels.
 constexpr int kRotThreads = 1024;
 // Depth planes per workgroup (one partial sum each) of the forward convolution.
@@ -79,6 +82,7 @@ struct Layout {
   size_t mubar_batch;   // view_batch * N floats (only without SPECT_CACHE_MUBAR)
   size_t em_proj;       // nview * nz * nx floats
   size_t em_vol;        // N floats
+  size_t rot_scratch;   // working slices of the rotation kernels when nx > kMaxLdsN
   size_t em_proj2;      // nview * nz * nx floats (EM vector-Jacobian product)
   size_t em_vol2;       // N floats (EM vector-Jacobian product)
   size_t total;
@@ -109,6 +113,7 @@ struct Plan {
   Tables tab;
   const float* mubar;   // cache or nullptr
   float* mubar_batch;   // per-batch attenuation factors when not cached
+  float* rot_scratch;   // rotation working slices (nx > kMaxLdsN), else nullptr
   bool use_mfma;        // MFMA convolution path (else the direct kernels)
   ConvShape conv;
   int conv_precision;   // SPECT_CONV_FP32 / _BF16 / _FP16
@@ -149,6 +154,7 @@ size_t lp_lds_bytes(const LpShape& s);
 bool lp_supported(const spect_geom& g);
 void tune_lp_chunks(LpShape& s, int views, int precision);
 size_t rotation_lds_bytes(int n);
+size_t rotation_scratch_bytes(int n, int nz, int nview);
 
 // ---- kernel launchers (return hipGetLastError() of the launch) ----
 hipError_t launch_mubar(const Plan& p, float* out, int view0, int nviews, int out_view0,

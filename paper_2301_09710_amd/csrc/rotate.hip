@@ -18,6 +18,7 @@
 // quarter-turned reads are then free of bank conflicts), with each wave
 // owning whole lines.  The forward rotation fuses the three passes into one
 // gather per pixel from a single staged slice (see rot_fwd_kernel).
+#include <algorithm>
 #include <type_traits>
 
 #include "internal.h"
@@ -147,9 +148,9 @@ __device__ __forceinline__ void line_pass(float* Y, int n, int S, const ViewTab&
 // Passes 1 and 2 of R_l X into Y (and pass 3 when kAllThree; otherwise the
 // caller fuses pass 3 with its output).  Ends with Y complete (barrier).
 template <bool kAllThree, int EPL>
-__device__ __forceinline__ void rotate_into(float* Y, const float* X, int n, int S, int m,
+__device__ __forceinline__ void rotate_into(float* Y, const float* X, int n, int S, int SX, int m,
                                             const ViewTab& t) {
-  const QAddr qa = quarter_addr(m, n, S);
+  const QAddr qa = quarter_addr(m, n, SX);
   const int lane = lane_id();
   for (int j = wave_id(); j < n; j += NW)
 #pragma unroll
@@ -195,27 +196,43 @@ __device__ void mubar_scan(float* Y, double* seg, int n, int S, double dy) {
 }
 
 // grid (nz, ceil(nviews / VG)): out[(l - out_view0)][k] = mubar of view l.
-template <int EPL>
+// kGlobal (slices larger than LDS allows): the source slice is read in place
+// from mu and the working slice Y is the workgroup's own slice of `scratch`
+// (L2-resident); the scan segments and tables stay in LDS.
+template <int EPL, bool kGlobal>
 __global__ __launch_bounds__(NT) void mubar_kernel(const float* __restrict__ mu,
                                                    float* __restrict__ out, int n, int nz,
                                                    int view0, int nviews, int VG, int out_view0,
-                                                   Tables tab, double dy) {
+                                                   Tables tab, double dy, float* scratch) {
   extern __shared__ float smem[];
   const int S = slice_stride(n);
-  float* X = smem;
-  float* Y = X + n * S;
-  double* seg = reinterpret_cast<double*>(Y + n * S);   // offset 2 n (n+1) floats: 8-byte aligned
-  ViewTab t = carve_tab(reinterpret_cast<float*>(seg + kScanSeg * n), n);
   const int k = blockIdx.x;
   const size_t nn = (size_t)n * n;
-  stage_slice(X, mu + (size_t)k * nn, n, S);
+  const float* X;
+  float* Y;
+  double* seg;
+  int SX;
+  if (kGlobal) {
+    X = mu + (size_t)k * nn;
+    SX = n;
+    Y = scratch + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * n * S;
+    seg = reinterpret_cast<double*>(smem);
+  } else {
+    float* Xs = smem;
+    Y = Xs + n * S;
+    seg = reinterpret_cast<double*>(Y + n * S);         // offset 2 n (n+1) floats: 8-byte aligned
+    stage_slice(Xs, mu + (size_t)k * nn, n, S);
+    X = Xs;
+    SX = S;
+  }
+  ViewTab t = carve_tab(reinterpret_cast<float*>(seg + kScanSeg * n), n);
   const int lb0 = blockIdx.y * VG, lb1 = min(nviews, lb0 + VG);
   for (int lb = lb0; lb < lb1; ++lb) {
     const int l = view0 + lb;
     __syncthreads();                                   // X staged / previous view written out
     load_tab(tab, l, n, t);
     __syncthreads();
-    rotate_into<true, EPL>(Y, X, n, S, tab.quarter[l], t);
+    rotate_into<true, EPL>(Y, X, n, S, SX, tab.quarter[l], t);
     mubar_scan(Y, seg, n, S, dy);
     float* dst = out + ((size_t)(l - out_view0) * nz + k) * nn;
     for (int p = threadIdx.x; p < n * n; p += NT) {
@@ -279,18 +296,26 @@ __device__ __forceinline__ float rotated_pixel(const float* X, int n, const QAdd
 // lb of this group; mubar of view lb is at mb + (lb + mb_off) * N.  RM = 8x8
 // tiles per wave, visited kCh at a time.
 constexpr int kCh = 4;
-template <int RM>
+// kGlobal: the slice is gathered in place from x (L2-resident), no staging.
+template <int RM, bool kGlobal>
 __global__ __launch_bounds__(NT) void rot_fwd_kernel(const float* __restrict__ x,
                                                      const float* __restrict__ mb, int mb_off,
                                                      float* __restrict__ W, int n, int nz,
                                                      int view0, int nvb, int VG, Tables tab) {
   extern __shared__ float smem[];
-  const int S = gather_stride(n);
-  float* X = smem;
-  ViewTab t = carve_tab(X + n * S, n);
   const int k = blockIdx.x;
   const size_t nn = (size_t)n * n, N = nn * nz;
-  stage_slice(X, x + (size_t)k * nn, n, S);
+  const int S = kGlobal ? n : gather_stride(n);
+  const float* X;
+  ViewTab t;
+  if (kGlobal) {
+    X = x + (size_t)k * nn;
+    t = carve_tab(smem, n);
+  } else {
+    stage_slice(smem, x + (size_t)k * nn, n, S);
+    X = smem;
+    t = carve_tab(smem + n * S, n);
+  }
   const int lb0 = blockIdx.y * VG, lb1 = min(nvb, lb0 + VG);
   for (int lb = lb0; lb < lb1; ++lb) {
     const int l = view0 + lb;
@@ -332,17 +357,18 @@ __global__ __launch_bounds__(NT) void rot_fwd_kernel(const float* __restrict__ x
 // grid (nz, G): partial[g][k] (+)= sum over views lb = g, g+G, ... of
 //   P_m^T S1^T S2^T S3^T (U[lb][k] * mubar_l[k]).
 // Output pixel (i, j) accumulates in wave j mod NW, lane i mod 64.
-template <int EPL, int LPW>
+// kGlobal: the working slice Y is the workgroup's own slice of `scratch`.
+template <int EPL, int LPW, bool kGlobal>
 __global__ __launch_bounds__(NT) void rot_back_kernel(const float* __restrict__ U,
                                                       const float* __restrict__ mb, int mb_off,
                                                       float* __restrict__ partial, int n, int nz,
                                                       int view0, int nvb, int G, int accumulate,
-                                                      Tables tab) {
+                                                      Tables tab, float* scratch) {
   extern __shared__ float smem[];
   const int S = slice_stride(n);
-  float* Y = smem;
-  ViewTab t = carve_tab(Y + n * S, n);
   const int k = blockIdx.x, g = blockIdx.y, lane = lane_id(), w = wave_id();
+  float* Y = kGlobal ? scratch + ((size_t)g * nz + k) * n * S : smem;
+  ViewTab t = carve_tab(kGlobal ? smem : Y + n * S, n);
   const size_t nn = (size_t)n * n, N = nn * nz;
   float acc[LPW][EPL];
 #pragma unroll
@@ -365,6 +391,28 @@ __global__ __launch_bounds__(NT) void rot_back_kernel(const float* __restrict__ 
     __syncthreads();
     line_pass<-1, false, EPL>(Y, n, S, t);             // pass 2 transpose
     __syncthreads();
+    if (kGlobal) {
+      // large slices: accumulate in this workgroup's own slice of `partial`
+      // (each pixel has one owner lane, so the order of additions is fixed)
+      float* dst = partial + (size_t)g * N + (size_t)k * nn;
+      const bool first = lb == g;
+#pragma unroll 1
+      for (int r = 0; r < LPW; ++r) {
+        const int j = w + NW * r;
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+          const int i = lane + 64 * e;
+          if (j < n && i < n) {
+            int di, dj;
+            quarter_dst(m, n, i, j, di, dj);
+            const float val = row_px<-1>(Y, n, S, t, di, dj);
+            const float prev = (first && !accumulate) ? 0.0f : dst[j * n + i];
+            dst[j * n + i] = prev + val;
+          }
+        }
+      }
+      continue;
+    }
 #pragma unroll
     for (int r = 0; r < LPW; ++r) {                    // pass 1 transpose, then P_m^T
       const int j = w + NW * r;
@@ -378,6 +426,14 @@ __global__ __launch_bounds__(NT) void rot_back_kernel(const float* __restrict__ 
         }
       }
     }
+  }
+  if (kGlobal) {
+    // a workgroup with no view in this batch still owns its slice
+    if (g >= nvb && !accumulate) {
+      float* dst = partial + (size_t)g * N + (size_t)k * nn;
+      for (int p = threadIdx.x; p < n * n; p += NT) dst[p] = 0.0f;
+    }
+    return;
   }
   float* dst = partial + (size_t)g * N + (size_t)k * nn;
 #pragma unroll
@@ -410,30 +466,44 @@ hipError_t set_smem(const void* fn, size_t bytes) {
 }  // namespace
 
 size_t rotation_lds_bytes(int n) {
-  // mubar kernel: two slices, the FP64 scan segments, tables
+  // mubar kernel with slices in LDS: two slices, the FP64 scan segments, tables
   return 2 * slice_bytes(n) + (size_t)kScanSeg * n * 8 + tab_bytes(n);
 }
 
-// Instantiation by slice size: EPL = elements of a line per lane,
-// LPW = lines per wave.
+size_t rotation_scratch_bytes(int n, int nz, int nview) {
+  if (n <= kMaxLdsN) return 0;
+  const int VG = kRotViewsPerGroup;
+  const int groups = std::max((nview + VG - 1) / VG, kBackGroups);
+  return (size_t)groups * nz * n * slice_stride(n) * sizeof(float);
+}
+
+// Instantiation by slice size: EPL = elements of a line per lane, LPW =
+// lines per wave, and whether the working slices live in LDS or in global
+// scratch (n > kMaxLdsN).
 template <class F>
 hipError_t with_shape(int n, F&& f) {
-  if (n <= 64) return f(std::integral_constant<int, 1>(), std::integral_constant<int, 4>());
-  if (n <= 128) return f(std::integral_constant<int, 2>(), std::integral_constant<int, 8>());
-  return f(std::integral_constant<int, 3>(), std::integral_constant<int, (kMaxLdsN + NW - 1) / NW>());
+  using std::integral_constant;
+  if (n <= 64) return f(integral_constant<int, 1>(), integral_constant<int, 4>(), std::false_type());
+  if (n <= 128) return f(integral_constant<int, 2>(), integral_constant<int, 8>(), std::false_type());
+  if (n <= kMaxLdsN)
+    return f(integral_constant<int, 3>(), integral_constant<int, (kMaxLdsN + NW - 1) / NW>(),
+             std::false_type());
+  return f(integral_constant<int, (kMaxN + 63) / 64>(), integral_constant<int, (kMaxN + NW - 1) / NW>(),
+           std::true_type());
 }
 
 hipError_t launch_mubar(const Plan& p, float* out, int view0, int nviews, int out_view0,
                         hipStream_t s) {
   const int n = p.g.nx;
-  const size_t sm = rotation_lds_bytes(n);
+  const bool glob = n > kMaxLdsN;
+  const size_t sm = glob ? (size_t)kScanSeg * n * 8 + tab_bytes(n) : rotation_lds_bytes(n);
   const int VG = kRotViewsPerGroup;
   dim3 grid(p.g.nz, (nviews + VG - 1) / VG);
-  return with_shape(n, [&](auto E, auto) {
-    hipError_t e = set_smem((const void*)mubar_kernel<E.value>, sm);
+  return with_shape(n, [&](auto E, auto, auto G) {
+    hipError_t e = set_smem((const void*)mubar_kernel<E.value, G.value>, sm);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(mubar_kernel<E.value>, grid, dim3(NT), sm, s, p.mu, out, n, p.g.nz, view0,
-                       nviews, VG, out_view0, p.tab, p.g.dy);
+    hipLaunchKernelGGL((mubar_kernel<E.value, G.value>), grid, dim3(NT), sm, s, p.mu, out, n,
+                       p.g.nz, view0, nviews, VG, out_view0, p.tab, p.g.dy, p.rot_scratch);
     return hipGetLastError();
   });
 }
@@ -441,33 +511,37 @@ hipError_t launch_mubar(const Plan& p, float* out, int view0, int nviews, int ou
 hipError_t launch_rot_fwd(const Plan& p, const float* x, const float* mb, int mb_off, float* W,
                           int view0, int nvb, hipStream_t s) {
   const int n = p.g.nx;
-  const size_t sm = (size_t)n * gather_stride(n) * 4 + tab_bytes(n);
+  const bool glob = n > kMaxLdsN;
+  const size_t sm = glob ? tab_bytes(n) : (size_t)n * gather_stride(n) * 4 + tab_bytes(n);
   const int VG = kRotViewsPerGroup;
   dim3 grid(p.g.nz, (nvb + VG - 1) / VG);
-  auto go = [&](auto RM) {
-    hipError_t e = set_smem((const void*)rot_fwd_kernel<RM.value>, sm);
+  auto go = [&](auto RM, auto G) {
+    hipError_t e = set_smem((const void*)rot_fwd_kernel<RM.value, G.value>, sm);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(rot_fwd_kernel<RM.value>, grid, dim3(NT), sm, s, x, mb, mb_off, W, n,
-                       p.g.nz, view0, nvb, VG, p.tab);
+    hipLaunchKernelGGL((rot_fwd_kernel<RM.value, G.value>), grid, dim3(NT), sm, s, x, mb, mb_off, W,
+                       n, p.g.nz, view0, nvb, VG, p.tab);
     return hipGetLastError();
   };
   // 8x8 tiles per wave: ceil(ceil(n/8)^2 / NW)
-  if (n <= 64) return go(std::integral_constant<int, 4>());
-  if (n <= 128) return go(std::integral_constant<int, 16>());
-  constexpr int tpr = (kMaxLdsN + 7) / 8;
-  return go(std::integral_constant<int, (tpr * tpr + NW - 1) / NW>());
+  using std::integral_constant;
+  if (n <= 64) return go(integral_constant<int, 4>(), std::false_type());
+  if (n <= 128) return go(integral_constant<int, 16>(), std::false_type());
+  constexpr int tl = (kMaxLdsN + 7) / 8, tg = (kMaxN + 7) / 8;
+  if (n <= kMaxLdsN) return go(integral_constant<int, (tl * tl + NW - 1) / NW>(), std::false_type());
+  return go(integral_constant<int, (tg * tg + NW - 1) / NW>(), std::true_type());
 }
 
 hipError_t launch_rot_back(const Plan& p, const float* U, const float* mb, int mb_off,
                            float* partial, int view0, int nvb, bool accumulate, hipStream_t s) {
   const int n = p.g.nx;
-  const size_t sm = slice_bytes(n) + tab_bytes(n);
-  return with_shape(n, [&](auto E, auto L) {
-    hipError_t e = set_smem((const void*)rot_back_kernel<E.value, L.value>, sm);
+  const bool glob = n > kMaxLdsN;
+  const size_t sm = glob ? tab_bytes(n) : slice_bytes(n) + tab_bytes(n);
+  return with_shape(n, [&](auto E, auto L, auto G) {
+    hipError_t e = set_smem((const void*)rot_back_kernel<E.value, L.value, G.value>, sm);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((rot_back_kernel<E.value, L.value>), dim3(p.g.nz, kBackGroups), dim3(NT), sm,
-                       s, U, mb, mb_off, partial, n, p.g.nz, view0, nvb, kBackGroups,
-                       accumulate ? 1 : 0, p.tab);
+    hipLaunchKernelGGL((rot_back_kernel<E.value, L.value, G.value>), dim3(p.g.nz, kBackGroups),
+                       dim3(NT), sm, s, U, mb, mb_off, partial, n, p.g.nz, view0, nvb, kBackGroups,
+                       accumulate ? 1 : 0, p.tab, p.rot_scratch);
     return hipGetLastError();
   });
 }

@@ -26,7 +26,7 @@ static spect_status validate(const spect_geom* g) {
   if (g->angles)
     for (int l = 0; l < g->nview; ++l)
       if (!std::isfinite(g->angles[l])) return SPECT_ERR_VALUE;
-  if (g->nx > kMaxLdsN) return SPECT_ERR_UNSUPPORTED;
+  if (g->nx > kMaxN) return SPECT_ERR_UNSUPPORTED;
   // index arithmetic inside a plane / slice uses 32-bit ints
   if ((int64_t)g->nx * g->nz > (1 << 30) || (int64_t)g->px * g->pz > (1 << 20))
     return SPECT_ERR_UNSUPPORTED;
@@ -57,6 +57,7 @@ spect_status compute_layout(const spect_geom& g, Layout* lay, int* view_batch, i
   lay->mubar_cache = cache ? take((size_t)g.nview * N * sizeof(float)) : 0;
   lay->mubar_batch = cache ? 0 : take((size_t)vb * N * sizeof(float));
 
+  lay->rot_scratch = take(rotation_scratch_bytes(g.nx, g.nz, g.nview));
   lay->em_proj = take(M * sizeof(float));
   lay->em_vol = take(N * sizeof(float));
   lay->em_proj2 = take(M * sizeof(float));
@@ -200,6 +201,7 @@ spect_status spect_plan_create(spect_plan* out, const spect_geom* g, const float
                        hipMemcpyHostToDevice, stream);
   p->mubar = nullptr;
   p->mubar_batch = nullptr;
+  p->rot_scratch = g->nx > kMaxLdsN ? reinterpret_cast<float*>(p->ws + lay.rot_scratch) : nullptr;
   p->use_mfma = conv_mfma_supported(*g);
   p->conv = make_conv_shape(*g, kFwdJChunk, kBackJChunk);
   if (p->use_mfma) {

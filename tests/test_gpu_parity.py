@@ -275,3 +275,27 @@ def test_paper_adjoint_identity(paper):
     lhs = spect.dot_f64(plan.forward(x), y)
     rhs = spect.dot_f64(x, plan.back(y))
     assert abs(lhs - rhs) <= TOL * abs(lhs)
+
+
+# ------------------------------------------------------------ slices larger than LDS
+
+@pytest.mark.parametrize("case", [(144, 6, 5, 5, 7), (200, 3, 3, 9, 5)])
+def test_large_slice_parity(case):
+    """In-plane sizes above the LDS-resident limit (the rotation kernels then
+    keep their working slices in global scratch): full forward and back
+    against the oracle."""
+    nx, nz, nview, px, pz = case
+    say(f"test_large_slice_parity {case}")
+    seed = nx + nz
+    x = synth.random_volume(nx, nx, nz, seed=seed)
+    mu = synth.random_volume(nx, nx, nz, seed=seed + 1, high=0.02)
+    psf = synth.random_psf(px, pz, nx, nview, seed=seed + 2, symmetric=False)
+    dy = 1.0
+    g = Geometry(nx, nx, nz, nview, px, pz, dy)
+    for cache in (True, False):
+        plan = make_plan(mu, psf, dy, cache_mubar=cache)
+        v = gpu_fwd(plan, x)
+        assert rel_l2(v, oracle.forward(x, mu, psf, g)) <= TOL
+        y = synth.random_volume(nx, nz, nview, seed=seed + 3)
+        b = gpu_back(plan, y)
+        assert rel_l2(b, oracle.back(y, mu, psf, g)) <= TOL

@@ -164,3 +164,31 @@ def test_lp_accuracy_paper_sampled_views(prec):
     u = precision.unit_roundoff(prec)
     say(f"{prec} paper: forward {ef:.2e}, back {eb:.2e} (2u = {2 * u:.2e})")
     assert ef <= 2 * u and eb <= 2 * u
+
+
+def test_large_config_all_precisions_sampled_views():
+    """The 256x256x160 / 128-view / 37x37 precision workload: FP32 within the
+    1e-5 bar and BF16 / FP16 within 2u of the FP64 oracle, forward on two
+    sampled views and the back projection of a projection nonzero on those
+    views only."""
+    say("large config: oracle")
+    x, mu, psf, dy = synth.config_inputs("large", seed=0)
+    g = Geometry(256, 256, 160, 128, 37, 37, dy)
+    views = [5, 70]
+    v_ref = oracle.forward(x, mu, psf, g, views=views, conv="fft")
+    y = np.zeros((128, 160, 256), dtype=np.float32)
+    y[views] = np.random.default_rng(9).uniform(0.5, 1.5, size=(len(views), 160, 256))
+    b_ref = oracle.back(y, mu, psf, g, views=views, conv="fft")
+    for prec in ("fp32", "bf16", "fp16"):
+        say(f"large config: {prec}")
+        plan = spect.Plan(to_dev(mu), to_dev(psf), dy, cache_mubar=False, view_batch=32,
+                          precision=prec)
+        v = host(plan.forward(to_dev(x)))
+        b = host(plan.back(to_dev(y)))
+        ef, eb = rel_l2(v[views], v_ref[views]), rel_l2(b, b_ref)
+        bound = 1e-5 if prec == "fp32" else 2 * precision.unit_roundoff(prec)
+        say(f"{prec} large: forward {ef:.2e}, back {eb:.2e} (bound {bound:.2e})")
+        assert ef <= bound and eb <= bound
+        plan.close()
+        del plan
+        torch.cuda.empty_cache()
