@@ -46,7 +46,7 @@ def test_status_strings():
     (dict(dy=float("nan")), 3),
     (dict(flags=0x10), 3),
     (dict(view_batch=-1), 3),
-    (dict(nx=200, ny=200), 5),        # slice larger than the LDS rotation path supports
+    (dict(nx=300, ny=300), 5),        # in-plane size above the largest supported (256)
 ])
 def test_workspace_bytes_validation(kw, status):
     args = dict(nx=32, ny=32, nz=20, nview=16, px=7, pz=7, dy=1.0, angles=None, flags=0, view_batch=0)
