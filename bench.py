@@ -45,6 +45,8 @@ def parse():
                     help="unrolled EM iterations differentiated end to end (0 disables)")
     ap.add_argument("--precision-steps", type=int, default=10,
                     help="pairs timed for each reduced-precision (BF16, FP16) convolution plan (0 disables)")
+    ap.add_argument("--large-steps", type=int, default=3,
+                    help="pairs timed per precision on the 256x256x160 precision workload (0 disables)")
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="requests in the continuous-batching serving trace (0 disables)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="mean arrivals per second")
@@ -260,6 +262,49 @@ def main():
             pl.close()
             del pl, v2, b2
 
+    # The precision workload: 256x256x160, 128 views, 37x37 PSFs, the pair and
+    # a 10-iteration EM image in FP32, BF16 and FP16 (not part of `value`).
+    # Distances are to the FP32 results, which the tests hold within 1e-5 of
+    # the FP64 oracle at this size.
+    large = None
+    if args.large_steps > 0:
+        xl, mul, psfl, dyl = synth.config_inputs("large", seed=args.seed)
+        xld, muld, psfld = (torch.from_numpy(a).to(dev) for a in (xl, mul, psfl))
+        large = {"workload": "256x256x160 (2.4 mm), 128 views, 37x37 PSF", "precisions": {}}
+        ref = None
+        for prec in ("fp32", "bf16", "fp16"):
+            pl = spect.Plan(muld, psfld, dyl, cache_mubar=True, precision=prec)
+            v2 = pl.forward(xld)
+            b2 = pl.back(v2)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(args.large_steps):
+                pl.forward(xld, out=v2)
+                pl.back(v2, out=b2)
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / args.large_steps
+            yl = v2.clone() if ref is None else ref["v"]          # noiseless data from FP32
+            sens = pl.back(torch.ones_like(yl))
+            xe = torch.ones_like(xld)
+            for _ in range(10):
+                pl.em_step(xe, yl, sens)
+            torch.cuda.synchronize()
+            rec = {"ms_per_pair": ms, "pairs_per_s": 1000.0 / ms}
+            if ref is None:
+                ref = {"v": v2.clone(), "b": b2.clone(), "x": xe.clone()}
+            else:
+                rel = lambda p_, q_: float((p_.double() - q_.double()).norm() / q_.double().norm())
+                rec.update({"rel_l2_forward_vs_fp32": rel(v2, ref["v"]),
+                            "rel_l2_back_vs_fp32": rel(pl.back(ref["v"]), ref["b"]),
+                            "rel_l2_em10_vs_fp32": rel(xe, ref["x"])})
+            large["precisions"][prec] = rec
+            pl.close()
+            del pl, v2, b2, sens, xe
+        del ref, xld, muld, psfld
+        torch.cuda.empty_cache()
+
     # Differentiation through unrolled EM (not part of `value`): MSE against the
     # phantom backpropagated to x0 and y through `grad_iters` EM updates.
     grad = None
@@ -357,6 +402,7 @@ def main():
         "em_recon_latency": em,
         "unrolled_em_grad": grad,
         "reduced_precision": lp,
+        "large_precision": large,
         "serving": serving,
         "kernels_ms_per_launch": avg_ms,
         "roofline": roof,
