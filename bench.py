@@ -219,14 +219,15 @@ def main():
               "p99_ms": pct(lat, 99)}
 
     # Reduced-precision convolution (not part of `value`): the same pair with
-    # BF16 / FP16 matrix-core operands, its speed and its distance from the
-    # FP32 path (itself within 1e-5 of the FP64 oracle).
+    # BF16 / FP16 matrix-core operands, and with split-BF16 operands (three
+    # BF16 products per FP32 product), their speed and distance from the FP32
+    # path (itself within 1e-5 of the FP64 oracle).
     lp = None
     if args.precision_steps > 0:
         lp = {}
         ref_v = vd.double()
         ref_b = bd.double()
-        for prec in ("bf16", "fp16"):
+        for prec in ("bf16", "fp16", "bf16x3"):
             pl = spect.Plan(mud, psfd, dy, cache_mubar=bool(args.cache_mubar), precision=prec)
             v2 = torch.empty_like(vd)
             b2 = torch.empty_like(bd)
@@ -272,7 +273,7 @@ def main():
         xld, muld, psfld = (torch.from_numpy(a).to(dev) for a in (xl, mul, psfl))
         large = {"workload": "256x256x160 (2.4 mm), 128 views, 37x37 PSF", "precisions": {}}
         ref = None
-        for prec in ("fp32", "bf16", "fp16"):
+        for prec in ("fp32", "bf16", "fp16", "bf16x3"):
             pl = spect.Plan(muld, psfld, dyl, cache_mubar=True, precision=prec)
             v2 = pl.forward(xld)
             b2 = pl.back(v2)

@@ -69,6 +69,11 @@ typedef enum {
 #define SPECT_CONV_FP16 2  /* the same with FP16 operands: values of the weighted
                               volume and of projections handed to spect_back must
                               stay below 65504 in magnitude */
+#define SPECT_CONV_BF16X3 3 /* each FP32 operand split as a BF16 leading part plus
+                               a BF16 remainder (16 significant bits), each product
+                               as three BF16 matrix-core products (hi*hi + hi*lo +
+                               lo*hi) with FP32 accumulation: FP32-level accuracy on
+                               the BF16 matrix cores */
 
 /* flags */
 #define SPECT_CACHE_MUBAR 0x1u  /* keep the attenuation factor of Eq. (1) for all
@@ -87,7 +92,8 @@ typedef struct {
   uint32_t flags;         /* SPECT_CACHE_MUBAR or 0 */
   int32_t view_batch;     /* views processed per internal batch; 0 = all.
                              Smaller batches need less workspace. */
-  int32_t conv_precision; /* SPECT_CONV_FP32 (0), SPECT_CONV_BF16 or SPECT_CONV_FP16;
+  int32_t conv_precision; /* SPECT_CONV_FP32 (0), SPECT_CONV_BF16, SPECT_CONV_FP16 or
+                             SPECT_CONV_BF16X3;
                              other values give SPECT_ERR_VALUE */
 } spect_geom;
 

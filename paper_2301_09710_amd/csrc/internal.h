@@ -150,7 +150,7 @@ void tune_conv_chunks(ConvShape& cs, int views);
 size_t conv_mfma_lds_bytes(const ConvShape& cs, bool back);
 size_t conv_edges_lds_bytes(const ConvShape& cs);
 LpShape make_lp_shape(const spect_geom& g);
-size_t lp_lds_bytes(const LpShape& s);
+size_t lp_lds_bytes(const LpShape& s, bool split);
 bool lp_supported(const spect_geom& g);
 void tune_lp_chunks(LpShape& s, int views, int precision);
 size_t rotation_lds_bytes(int n);

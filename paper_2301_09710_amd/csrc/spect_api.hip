@@ -21,7 +21,7 @@ static spect_status validate(const spect_geom* g) {
   if (g->flags & ~SPECT_CACHE_MUBAR) return SPECT_ERR_VALUE;
   if (g->view_batch < 0) return SPECT_ERR_VALUE;
   if (g->conv_precision != SPECT_CONV_FP32 && g->conv_precision != SPECT_CONV_BF16 &&
-      g->conv_precision != SPECT_CONV_FP16)
+      g->conv_precision != SPECT_CONV_FP16 && g->conv_precision != SPECT_CONV_BF16X3)
     return SPECT_ERR_VALUE;
   if (g->angles)
     for (int l = 0; l < g->nview; ++l)

@@ -19,8 +19,9 @@ LIB_PATH = os.path.join(_HERE, "libspect.so")
 
 SPECT_OK = 0
 SPECT_CACHE_MUBAR = 0x1
-SPECT_CONV_FP32, SPECT_CONV_BF16, SPECT_CONV_FP16 = 0, 1, 2
-PRECISIONS = {"fp32": SPECT_CONV_FP32, "bf16": SPECT_CONV_BF16, "fp16": SPECT_CONV_FP16}
+SPECT_CONV_FP32, SPECT_CONV_BF16, SPECT_CONV_FP16, SPECT_CONV_BF16X3 = 0, 1, 2, 3
+PRECISIONS = {"fp32": SPECT_CONV_FP32, "bf16": SPECT_CONV_BF16, "fp16": SPECT_CONV_FP16,
+              "bf16x3": SPECT_CONV_BF16X3}
 STATUS_NAMES = {
     0: "SPECT_OK", 1: "SPECT_ERR_NULL", 2: "SPECT_ERR_SHAPE", 3: "SPECT_ERR_VALUE",
     4: "SPECT_ERR_WORKSPACE", 5: "SPECT_ERR_UNSUPPORTED", 6: "SPECT_ERR_HIP", 7: "SPECT_ERR_ALIGN",

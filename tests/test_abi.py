@@ -122,10 +122,10 @@ def test_entry_points_reject_null():
 
 
 def test_conv_precision_validation():
-    for prec in (0, 1, 2):
+    for prec in (0, 1, 2, 3):
         g, _ = spect.make_geom(32, 32, 20, 16, 7, 7, 1.0, conv_precision=prec)
         assert spect.spect_workspace_bytes(g) > 0
-    for bad in (-1, 3, 99):
+    for bad in (-1, 4, 99):
         g, _ = spect.make_geom(32, 32, 20, 16, 7, 7, 1.0, conv_precision=bad)
         with pytest.raises(spect.SpectError) as e:
             spect.spect_workspace_bytes(g)
