@@ -51,28 +51,40 @@ __device__ __forceinline__ QAddr quarter_addr(int m, int n, int S) {
   return {n - 1, S, -1};
 }
 
+// One line's two-tap interpolation: weights (w.x, w.y) and offset o, packed
+// so that a lookup is a single 16-byte LDS read.
+struct __align__(16) TabEntry {
+  float2 w;
+  int o, pad;
+};
+
 struct ViewTab {          // per-view tables in LDS
-  int* o13;  float2* w13; // passes 1 and 3, indexed by row j
-  int* o2;   float2* w2;  // pass 2, indexed by column i
+  TabEntry* e13;          // passes 1 and 3, indexed by row j
+  TabEntry* e2;           // pass 2, indexed by column i
 };
 
 __device__ __forceinline__ bool inside(int q, int n) { return (unsigned)q < (unsigned)n; }
 
+// Tables (2n entries) at `after`, which callers keep 16-byte aligned.
 __device__ __forceinline__ ViewTab carve_tab(float* after, int n) {
   ViewTab t;
-  t.o13 = reinterpret_cast<int*>(after);
-  t.o2 = t.o13 + n;
-  t.w13 = reinterpret_cast<float2*>(t.o2 + n);   // 8-byte aligned: 2n ints precede
-  t.w2 = t.w13 + n;
+  t.e13 = reinterpret_cast<TabEntry*>(after);
+  t.e2 = t.e13 + n;
   return t;
 }
+
+// Floats of an LDS slice rounded up to 16 bytes.
+__host__ __device__ __forceinline__ int round4(int floats) { return (floats + 3) & ~3; }
 
 __device__ __forceinline__ void load_tab(const Tables& tab, int l, int n, const ViewTab& t) {
   const int32_t* off = tab.off + (size_t)l * 2 * n;
   const float2* w = tab.w + (size_t)l * 2 * n;
   for (int e = threadIdx.x; e < 2 * n; e += NT) {
-    t.o13[e] = off[e];   // o13 and o2 are contiguous: [0, n) pass 1/3, [n, 2n) pass 2
-    t.w13[e] = w[e];
+    TabEntry te;                       // e13 and e2 are contiguous: [0, n) passes 1/3, [n, 2n) pass 2
+    te.w = w[e];
+    te.o = off[e];
+    te.pad = 0;
+    t.e13[e] = te;
   }
 }
 
@@ -91,8 +103,9 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 // pass 1 (forward) read from the unrotated slice X through the quarter turn
 __device__ __forceinline__ float pass1_px(const float* X, int n, const QAddr& qa,
                                           const ViewTab& t, int i, int j) {
-  const int o = t.o13[j];
-  const float2 w = t.w13[j];
+  const TabEntry te = t.e13[j];
+  const int o = te.o;
+  const float2 w = te.w;
   const int ia = i + o, ib = ia + 1;
   const float a = inside(ia, n) ? X[qa.base + qa.ci * ia + qa.cj * j] : 0.0f;
   const float b = inside(ib, n) ? X[qa.base + qa.ci * ib + qa.cj * j] : 0.0f;
@@ -103,8 +116,9 @@ __device__ __forceinline__ float pass1_px(const float* X, int n, const QAddr& qa
 template <int kSgn>
 __device__ __forceinline__ float row_px(const float* Y, int n, int S, const ViewTab& t, int i,
                                         int j) {
-  const int o = t.o13[j];
-  const float2 w = t.w13[j];
+  const TabEntry te = t.e13[j];
+  const int o = te.o;
+  const float2 w = te.w;
   const int ia = i + kSgn * o, ib = ia + kSgn;
   const float a = inside(ia, n) ? Y[j * S + ia] : 0.0f;
   const float b = inside(ib, n) ? Y[j * S + ib] : 0.0f;
@@ -115,8 +129,9 @@ __device__ __forceinline__ float row_px(const float* Y, int n, int S, const View
 template <int kSgn>
 __device__ __forceinline__ float col_px(const float* Y, int n, int S, const ViewTab& t, int i,
                                         int j) {
-  const int o = t.o2[i];
-  const float2 w = t.w2[i];
+  const TabEntry te = t.e2[i];
+  const int o = te.o;
+  const float2 w = te.w;
   const int ja = j + kSgn * o, jb = ja + kSgn;
   const float a = inside(ja, n) ? Y[ja * S + i] : 0.0f;
   const float b = inside(jb, n) ? Y[jb * S + i] : 0.0f;
@@ -253,11 +268,12 @@ __global__ __launch_bounds__(NT) void mubar_kernel(const float* __restrict__ mu,
 // a rotated tile spread over the LDS banks for every angle.
 __host__ __device__ __forceinline__ int gather_stride(int n) { return n + ((8 - n % 16) + 16) % 16; }
 
-// Pixel of this lane in iteration r: 8x8 tile (w + NW r) of the slice.
-__device__ __forceinline__ bool tile_pixel(int n, int r, int& i, int& j) {
-  const int tpr = (n + 7) >> 3;
+// Pixel of this lane in iteration r: 8x8 tile (w + NW r) of the slice, with
+// tpr = ceil(n / 8) tiles per row and rtpr = 1 / tpr (tile < 2^12 and tpr <= 32,
+// so the float quotient rounds to the exact integer division).
+__device__ __forceinline__ bool tile_pixel(int n, int tpr, float rtpr, int r, int& i, int& j) {
   const int tile = wave_id() + NW * r;
-  const int tj = tile / tpr, ti = tile - tj * tpr;
+  const int tj = (int)(((float)tile + 0.5f) * rtpr), ti = tile - tj * tpr;
   i = 8 * ti + (lane_id() & 7);
   j = 8 * tj + (lane_id() >> 3);
   return tj < tpr && i < n && j < n;
@@ -267,24 +283,29 @@ __device__ __forceinline__ bool tile_pixel(int n, int r, int& i, int& j) {
 __device__ __forceinline__ float rotated_pixel(const float* X, int n, const QAddr& qa,
                                                const ViewTab& t, int i, int j) {
   float f3 = 0.0f;
-  const int o3 = t.o13[j];
-  const float2 w3 = t.w13[j];
+  const TabEntry e3 = t.e13[j];
+  const int o3 = e3.o;
+  const float2 w3 = e3.w;
 #pragma unroll
   for (int t3 = 0; t3 < 2; ++t3) {
     const int i2 = i + o3 + t3;
     if (!inside(i2, n)) continue;
-    const int o2 = t.o2[i2];
-    const float2 w2 = t.w2[i2];
+    const TabEntry e2 = t.e2[i2];
+    const int o2 = e2.o;
+    const float2 w2 = e2.w;
     float f2 = 0.0f;
 #pragma unroll
     for (int t2 = 0; t2 < 2; ++t2) {
       const int j1 = j + o2 + t2;
       if (!inside(j1, n)) continue;
-      const int o1 = t.o13[j1];
-      const float2 w1 = t.w13[j1];
+      const TabEntry e1 = t.e13[j1];
+      const int o1 = e1.o;
+      const float2 w1 = e1.w;
       const int ia = i2 + o1, ib = ia + 1;
-      const float a = inside(ia, n) ? X[qa.base + qa.ci * ia + qa.cj * j1] : 0.0f;
-      const float b = inside(ib, n) ? X[qa.base + qa.ci * ib + qa.cj * j1] : 0.0f;
+      // |ci|, |cj| <= S and indices < n: 24-bit multiplies are exact (full rate)
+      const int row = qa.base + __mul24(qa.cj, j1);
+      const float a = inside(ia, n) ? X[row + __mul24(qa.ci, ia)] : 0.0f;
+      const float b = inside(ib, n) ? X[row + __mul24(qa.ci, ib)] : 0.0f;
       f2 += (t2 == 0 ? w2.x : w2.y) * (w1.x * a + w1.y * b);
     }
     f3 += (t3 == 0 ? w3.x : w3.y) * f2;
@@ -316,6 +337,8 @@ __global__ __launch_bounds__(NT) void rot_fwd_kernel(const float* __restrict__ x
     X = smem;
     t = carve_tab(smem + n * S, n);
   }
+  const int tpr = (n + 7) >> 3;
+  const float rtpr = 1.0f / (float)tpr;
   const int lb0 = blockIdx.y * VG, lb1 = min(nvb, lb0 + VG);
   for (int lb = lb0; lb < lb1; ++lb) {
     const int l = view0 + lb;
@@ -327,7 +350,7 @@ __global__ __launch_bounds__(NT) void rot_fwd_kernel(const float* __restrict__ x
 #pragma unroll
     for (int c = 0; c < kCh; ++c) {
       int i, j;
-      att[c] = tile_pixel(n, c, i, j) ? mbs[j * n + i] : 0.0f;
+      att[c] = tile_pixel(n, tpr, rtpr, c, i, j) ? mbs[j * n + i] : 0.0f;
     }
     __syncthreads();                       // X staged / previous view's readers done
     load_tab(tab, l, n, t);
@@ -339,12 +362,12 @@ __global__ __launch_bounds__(NT) void rot_fwd_kernel(const float* __restrict__ x
 #pragma unroll
       for (int c = 0; c < kCh; ++c) {
         int i, j;
-        nxt[c] = (r0 + kCh + c < RM && tile_pixel(n, r0 + kCh + c, i, j)) ? mbs[j * n + i] : 0.0f;
+        nxt[c] = (r0 + kCh + c < RM && tile_pixel(n, tpr, rtpr, r0 + kCh + c, i, j)) ? mbs[j * n + i] : 0.0f;
       }
 #pragma unroll
       for (int c = 0; c < kCh; ++c) {
         int i, j;
-        if (r0 + c < RM && tile_pixel(n, r0 + c, i, j))
+        if (r0 + c < RM && tile_pixel(n, tpr, rtpr, r0 + c, i, j))
           dst[j * n + i] = rotated_pixel(X, n, qa, t, i, j) * att[c];
       }
 #pragma unroll
@@ -368,7 +391,7 @@ __global__ __launch_bounds__(NT) void rot_back_kernel(const float* __restrict__ 
   const int S = slice_stride(n);
   const int k = blockIdx.x, g = blockIdx.y, lane = lane_id(), w = wave_id();
   float* Y = kGlobal ? scratch + ((size_t)g * nz + k) * n * S : smem;
-  ViewTab t = carve_tab(kGlobal ? smem : Y + n * S, n);
+  ViewTab t = carve_tab(kGlobal ? smem : Y + round4(n * S), n);
   const size_t nn = (size_t)n * n, N = nn * nz;
   float acc[LPW][EPL];
 #pragma unroll
@@ -456,7 +479,7 @@ __global__ void back_reduce_kernel(const float* __restrict__ partial, float* __r
   x[p] = s;
 }
 
-size_t tab_bytes(int n) { return (size_t)2 * n * 4 + (size_t)2 * n * 8; }
+size_t tab_bytes(int n) { return (size_t)2 * n * sizeof(TabEntry); }
 size_t slice_bytes(int n) { return (size_t)n * slice_stride(n) * 4; }
 
 hipError_t set_smem(const void* fn, size_t bytes) {
@@ -535,7 +558,7 @@ hipError_t launch_rot_back(const Plan& p, const float* U, const float* mb, int m
                            float* partial, int view0, int nvb, bool accumulate, hipStream_t s) {
   const int n = p.g.nx;
   const bool glob = n > kMaxLdsN;
-  const size_t sm = glob ? tab_bytes(n) : slice_bytes(n) + tab_bytes(n);
+  const size_t sm = glob ? tab_bytes(n) : (size_t)round4(n * slice_stride(n)) * 4 + tab_bytes(n);
   return with_shape(n, [&](auto E, auto L, auto G) {
     hipError_t e = set_smem((const void*)rot_back_kernel<E.value, L.value, G.value>, sm);
     if (e != hipSuccess) return e;
