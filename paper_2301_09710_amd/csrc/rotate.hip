@@ -381,6 +381,7 @@ __global__ __launch_bounds__(NT) void rot_fwd_kernel(const float* __restrict__ x
 //   P_m^T S1^T S2^T S3^T (U[lb][k] * mubar_l[k]).
 // Output pixel (i, j) accumulates in wave j mod NW, lane i mod 64.
 // kGlobal: the working slice Y is the workgroup's own slice of `scratch`.
+constexpr int kStageRows = 4;
 template <int EPL, int LPW, bool kGlobal>
 __global__ __launch_bounds__(NT) void rot_back_kernel(const float* __restrict__ U,
                                                       const float* __restrict__ mb, int mb_off,
@@ -405,9 +406,27 @@ __global__ __launch_bounds__(NT) void rot_back_kernel(const float* __restrict__ 
     load_tab(tab, l, n, t);
     const float* src = U + (size_t)lb * N + (size_t)k * nn;
     const float* mbs = mb + (size_t)(lb + mb_off) * N + (size_t)k * nn;
-    for (int p = threadIdx.x; p < n * n; p += NT) {
-      const int j = p / n, i = p - j * n;
-      Y[j * S + i] = src[p] * mbs[p];
+    {
+      // stage U * mubar: a thread keeps column i = tid mod n and visits rows
+      // j = tid / n + lpi r, with the loads of kStageRows rows issued first
+      const int lpi = NT / n, i = threadIdx.x % n, v0 = threadIdx.x / n;
+      if (v0 < lpi) {
+#pragma unroll 1
+        for (int jb = v0; jb < n; jb += kStageRows * lpi) {
+          float u[kStageRows], a[kStageRows];
+#pragma unroll
+          for (int c = 0; c < kStageRows; ++c) {
+            const int j = jb + c * lpi;
+            u[c] = j < n ? src[j * n + i] : 0.0f;
+            a[c] = j < n ? mbs[j * n + i] : 0.0f;
+          }
+#pragma unroll
+          for (int c = 0; c < kStageRows; ++c) {
+            const int j = jb + c * lpi;
+            if (j < n) Y[j * S + i] = u[c] * a[c];
+          }
+        }
+      }
     }
     __syncthreads();
     line_pass<-1, true, EPL>(Y, n, S, t);              // pass 3 transpose
