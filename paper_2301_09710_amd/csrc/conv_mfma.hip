@@ -380,13 +380,17 @@ __global__ __launch_bounds__(256, 2) void conv_back_mfma(const float* __restrict
 // columns (N), looped over a: no band waste.  Corner bins (i' = 0, nx-1)
 // also fold along i: their B value is sum_{i in I(a)} Tk[b][i].  Edge columns
 // are the same with the roles of (a, i) and (b, k) swapped, rows excluded.
-// grid: (nvb, 4 edge kinds, ceil(ny / 64)); each wave owns 16 planes.
-constexpr int kEdgeNB = 9;   // N-blocks per pass of a wave (8 bins + the corner block)
+// Tk[b] vanishes unless the fold set K(b) is nonempty: b >= hb on the edge
+// k' = 0 and b <= hb on k' = nz-1 (every b when nz = 1), so K runs over that
+// window only, about half of the taps.
+// grid: (nvb, 2 edges of one kind, ceil(ny / 64)); each wave owns 16 planes.
+// Rows and columns are two launches, each with its own NB (N-blocks per pass).
+constexpr int kEdgeMaxNB = 9;
 
 // Sizes of the edge problem: q = taps contracted in K (along the folded
 // axis), t = taps looped outside, o = output bins along the edge line.
 struct EdgeDims {
-  int nq, hq, nt, ht, nout, nfold, ksteps, nqp, TWp;
+  int nq, hq, nt, ht, nout, nfold, ksteps, nqs, TWp;
 };
 __host__ __device__ inline EdgeDims edge_dims(const ConvShape& cs, bool krow) {
   EdgeDims d;
@@ -396,18 +400,21 @@ __host__ __device__ inline EdgeDims edge_dims(const ConvShape& cs, bool krow) {
   d.ht = krow ? cs.ha : cs.hb;
   d.nout = krow ? cs.nx : cs.nz;
   d.nfold = krow ? cs.nz : cs.nx;
-  d.ksteps = (d.nq + 3) / 4;
-  d.nqp = 4 * d.ksteps;                                         // K padded with zero rows
+  // K window: the taps with a possibly nonempty fold set, the same length on both edges
+  const int nwin = d.nfold > 1 ? (d.nq - d.hq > d.hq + 1 ? d.nq - d.hq : d.hq + 1) : d.nq;
+  d.ksteps = (nwin + 3) / 4;
+  d.nqs = 4 * d.ksteps;                                         // padded with zero rows
   d.TWp = 16 * ((d.nout + 15) / 16) + 2 * d.ht;                 // columns read by the N-blocks
   return d;
 }
 
+template <int NB>
 __global__ __launch_bounds__(256) void conv_back_edges(const float* __restrict__ v,
                                                        const float* __restrict__ psf,
                                                        float* __restrict__ U, ConvShape cs,
-                                                       int view0) {
+                                                       int view0, int kind0) {
   extern __shared__ float sm[];
-  const int lb = blockIdx.x, kind = blockIdx.y, l = view0 + lb;
+  const int lb = blockIdx.x, kind = kind0 + blockIdx.y, l = view0 + lb;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
   const int jblk = blockIdx.z * 64 + w * 16;                     // this wave's 16 planes
   const bool krow = kind < 2;                                    // edge row (k) or column (i)
@@ -417,9 +424,10 @@ __global__ __launch_bounds__(256) void conv_back_edges(const float* __restrict__
   const float* vl = v + (size_t)l * cs.nz * cs.nx;
   EdgeDims d = edge_dims(cs, krow);
   const int eout = (kind & 1) ? d.nfold - 1 : 0;  // the edge position on the folded axis
-  float* T = sm;                                  // nqp x TWp: folded sums, zero-padded
-  float* Cx = T + d.nqp * d.TWp;                  // nqp x nt x 2: corner sums, then one zero
-  float* As = Cx + (krow ? d.nqp * d.nt * 2 + 1 : 1);  // 256 x nt: per-lane A scratch
+  const int qlo = (eout == 0 && d.nfold > 1) ? d.hq : 0;         // first tap of the K window
+  float* T = sm;                                  // nqs x TWp: folded sums, zero-padded
+  float* Cx = T + d.nqs * d.TWp;                  // nqs x nt x 2: corner sums, then one zero
+  float* As = Cx + (krow ? d.nqs * d.nt * 2 + 1 : 1);  // 256 x nt: per-lane A scratch
   // The fold sets of an edge lie within hq + 1 lines of it: stage that band of the
   // projection (lines along the folded axis, bins along the edge) in the A scratch.
   const int bw = min(d.hq + 1, d.nfold);
@@ -429,21 +437,23 @@ __global__ __launch_bounds__(256) void conv_back_edges(const float* __restrict__
     const int f = e / d.nout, o = e - f * d.nout;
     Vb[e] = krow ? vl[(size_t)(fbase + f) * cs.nx + o] : vl[(size_t)o * cs.nx + fbase + f];
   }
-  if (threadIdx.x == 0) Cx[krow ? d.nqp * d.nt * 2 : 0] = 0.0f;   // zero slot of empty N-blocks
+  if (threadIdx.x == 0) Cx[krow ? d.nqs * d.nt * 2 : 0] = 0.0f;   // zero slot of empty N-blocks
   __syncthreads();
 
-  // T[q][c] = sum over f in F(q) of v at (fold f, other c - ht), with
+  // T[q - qlo][c] = sum over f in F(q) of v at (fold f, other c - ht), with
   // F(q) = {f : clamp(f - q + hq) = eout}.  The sets grow monotonically in q
   // (ascending for eout = 0, descending for eout = nfold-1), so one running
-  // sum per column fills all q with additions only.
+  // sum per column fills every q with additions only; rows outside the taps
+  // (q >= nq) are zero.
   const bool up = (eout == 0);
+  const int qend = max(d.nq, qlo + d.nqs);
   for (int cc = threadIdx.x; cc < d.TWp; cc += 256) {
     const int o = cc - d.ht;
     const bool live = o >= 0 && o < d.nout;
     float sum = 0.0f;
     int clo = 0, chi = -1;                                        // current set [clo, chi]
-    for (int step = 0; step < d.nqp; ++step) {
-      const int q = up ? step : d.nqp - 1 - step;
+    for (int step = 0; step < qend; ++step) {
+      const int q = up ? step : qend - 1 - step;
       int flo = (eout == 0) ? 0 : eout + q - d.hq;
       int fhi = (eout == d.nfold - 1) ? d.nfold - 1 : eout + q - d.hq;
       flo = max(flo, 0);
@@ -456,17 +466,18 @@ __global__ __launch_bounds__(256) void conv_back_edges(const float* __restrict__
         clo = min(clo, flo);
         chi = max(chi, fhi);
       }
-      T[q * d.TWp + cc] = ok ? sum : 0.0f;
+      if (q >= qlo && q < qlo + d.nqs) T[(q - qlo) * d.TWp + cc] = ok ? sum : 0.0f;
     }
   }
   __syncthreads();
-  // corners (edge rows only): Cx[q][t][side] = sum over o in O_side(t) of T[q][o + ht];
-  // Cx[nqp nt 2] is a zero read by the other lanes of the corner N-block
+  // corners (edge rows only): Cx[q - qlo][t][side] = sum over o in O_side(t) of
+  // T[q - qlo][o + ht]; Cx[nqs nt 2] is a zero read by the other lanes of the corner N-block
   if (krow) {
-    for (int e = threadIdx.x; e < d.nqp * d.nt * 2 + 1; e += 256) Cx[e] = 0.0f;
+    for (int e = threadIdx.x; e < d.nqs * d.nt * 2 + 1; e += 256) Cx[e] = 0.0f;
     __syncthreads();
-    for (int e = threadIdx.x; e < 2 * d.nq; e += 256) {
-      const int side = e / d.nq, q = e - side * d.nq;
+    for (int e = threadIdx.x; e < 2 * d.nqs; e += 256) {
+      const int side = e / d.nqs, qq = e - side * d.nqs;         // qq = q - qlo
+      if (qlo + qq >= d.nq) continue;
       const int oe = side ? d.nout - 1 : 0;
       const bool oup = (oe == 0);
       float sum = 0.0f;
@@ -479,12 +490,12 @@ __global__ __launch_bounds__(256) void conv_back_edges(const float* __restrict__
         ohi = min(ohi, d.nout - 1);
         if (olo <= ohi) {
           if (chi < clo) { clo = ohi + 1; chi = ohi; }
-          for (int o = clo - 1; o >= olo; --o) sum += T[q * d.TWp + o + d.ht];
-          for (int o = chi + 1; o <= ohi; ++o) sum += T[q * d.TWp + o + d.ht];
+          for (int o = clo - 1; o >= olo; --o) sum += T[qq * d.TWp + o + d.ht];
+          for (int o = chi + 1; o <= ohi; ++o) sum += T[qq * d.TWp + o + d.ht];
           clo = min(clo, olo);
           chi = max(chi, ohi);
         }
-        if (!(side == 1 && d.nout == 1)) Cx[(q * d.nt + t) * 2 + side] = (olo <= ohi) ? sum : 0.0f;
+        if (!(side == 1 && d.nout == 1)) Cx[(qq * d.nt + t) * 2 + side] = (olo <= ohi) ? sum : 0.0f;
       }
     }
     __syncthreads();
@@ -497,12 +508,12 @@ __global__ __launch_bounds__(256) void conv_back_edges(const float* __restrict__
   // block whose lanes 0 and 1 are the two corners
   const int nblocks = (d.nout + 15) / 16;
   const int nall = nblocks + (krow ? 1 : 0);
-  for (int nb0 = 0; nb0 < nall; nb0 += kEdgeNB) {
-    floatx4 acc[kEdgeNB];
+  for (int nb0 = 0; nb0 < nall; nb0 += NB) {
+    floatx4 acc[NB];
 #pragma unroll
-    for (int u = 0; u < kEdgeNB; ++u) acc[u] = {0.f, 0.f, 0.f, 0.f};
+    for (int u = 0; u < NB; ++u) acc[u] = {0.f, 0.f, 0.f, 0.f};
     for (int s = 0; s < d.ksteps; ++s) {
-      const int q = 4 * s + g;                                   // K index of this lane
+      const int qq = 4 * s + g, q = qlo + qq;                    // K index of this lane
       // A[m = plane][K = q] = p[a][b]: krow -> (a = t, b = q), else (a = q, b = t)
       for (int t0 = 0; t0 < d.nt; t0 += 16) {                   // 16 independent loads at a time
         float r16[16];
@@ -516,26 +527,26 @@ __global__ __launch_bounds__(256) void conv_back_edges(const float* __restrict__
           if (t0 + u < d.nt) Al[t0 + u] = r16[u];
       }
       // B source of each N-block for this lane: a pointer advanced by `step` per tap t
-      const float* zero = Cx + (krow ? d.nqp * d.nt * 2 : 0);   // a zero slot
-      const float* bp[kEdgeNB];
-      int bst[kEdgeNB];
+      const float* zero = Cx + (krow ? d.nqs * d.nt * 2 : 0);   // a zero slot
+      const float* bp[NB];
+      int bst[NB];
 #pragma unroll
-      for (int u = 0; u < kEdgeNB; ++u) {
+      for (int u = 0; u < NB; ++u) {
         const int blk = nb0 + u;
-        if (blk < nblocks) { bp[u] = T + q * d.TWp + 16 * blk + n; bst[u] = 1; }
-        else if (blk == nblocks && krow && n < 2) { bp[u] = Cx + q * d.nt * 2 + n; bst[u] = 2; }
+        if (blk < nblocks) { bp[u] = T + qq * d.TWp + 16 * blk + n; bst[u] = 1; }
+        else if (blk == nblocks && krow && n < 2) { bp[u] = Cx + qq * d.nt * 2 + n; bst[u] = 2; }
         else { bp[u] = zero; bst[u] = 0; }
       }
       // pipelined over taps: the operands of t+1 are read while t's MFMAs run
-      float avA, avB, bvA[kEdgeNB], bvB[kEdgeNB];
-      auto load = [&](float& av, float (&bv)[kEdgeNB], int t) {
+      float avA, avB, bvA[NB], bvB[NB];
+      auto load = [&](float& av, float (&bv)[NB], int t) {
         av = Al[t];
 #pragma unroll
-        for (int u = 0; u < kEdgeNB; ++u) bv[u] = bp[u][t * bst[u]];
+        for (int u = 0; u < NB; ++u) bv[u] = bp[u][t * bst[u]];
       };
-      auto run = [&](float av, const float (&bv)[kEdgeNB]) {
+      auto run = [&](float av, const float (&bv)[NB]) {
 #pragma unroll
-        for (int u = 0; u < kEdgeNB; ++u) acc[u] = mfma(av, bv[u], acc[u]);
+        for (int u = 0; u < NB; ++u) acc[u] = mfma(av, bv[u], acc[u]);
       };
       load(avA, bvA, 0);
       for (int t = 0; t < d.nt; t += 2) {
@@ -551,7 +562,7 @@ __global__ __launch_bounds__(256) void conv_back_edges(const float* __restrict__
     }
     // D[4g + r][n]: plane jblk + 4g + r, output position of (block, lane)
 #pragma unroll
-    for (int u = 0; u < kEdgeNB; ++u) {
+    for (int u = 0; u < NB; ++u) {
       const int blk = nb0 + u;
       int o;
       if (blk < nblocks) {
@@ -571,6 +582,37 @@ __global__ __launch_bounds__(256) void conv_back_edges(const float* __restrict__
       }
     }
   }
+}
+
+// N-blocks per pass for nall blocks: fewest issued blocks, then fewest passes.
+int edge_pick_nb(int nall) {
+  int best = kEdgeMaxNB, cost = -1;
+  for (int nb = kEdgeMaxNB; nb >= 1; --nb) {
+    const int c = (nall + nb - 1) / nb * nb;
+    if (cost < 0 || c < cost) { cost = c; best = nb; }
+  }
+  return best;
+}
+
+size_t edge_lds_floats(const ConvShape& cs, bool krow) {
+  const EdgeDims e = edge_dims(cs, krow);
+  const size_t band = (size_t)(e.hq + 1 < e.nfold ? e.hq + 1 : e.nfold) * e.nout;
+  const size_t lanes = 256 * (size_t)e.nt;
+  const size_t scratch = band > lanes ? band : lanes;
+  return (size_t)e.nqs * e.TWp + (krow ? (size_t)e.nqs * e.nt * 2 + 1 : 1) + scratch;
+}
+
+template <int NB>
+hipError_t launch_edges_nb(const ConvShape& cs, const float* v, const float* psf, float* U,
+                           int view0, int nvb, bool krow, hipStream_t s) {
+  const size_t sm = edge_lds_floats(cs, krow) * sizeof(float);
+  hipError_t e = hipFuncSetAttribute((const void*)conv_back_edges<NB>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+  if (e != hipSuccess) return e;
+  dim3 grid(nvb, 2, (cs.ny + 63) / 64);
+  hipLaunchKernelGGL(conv_back_edges<NB>, grid, dim3(256), sm, s, v, psf, U, cs, view0,
+                     krow ? 0 : 2);
+  return hipGetLastError();
 }
 
 template <int KS>
@@ -700,27 +742,32 @@ hipError_t launch_conv_back_mfma(const Plan& p, const float* v, float* U, int vi
 
 namespace spect {
 size_t conv_edges_lds_bytes(const ConvShape& cs) {
-  const EdgeDims r = edge_dims(cs, true), c = edge_dims(cs, false);
-  auto scratch = [](const EdgeDims& e) {
-    const size_t band = (size_t)(e.hq + 1 < e.nfold ? e.hq + 1 : e.nfold) * e.nout;
-    const size_t lanes = 256 * (size_t)e.nt;
-    return band > lanes ? band : lanes;
-  };
-  const size_t rows = (size_t)r.nqp * r.TWp + (size_t)r.nqp * r.nt * 2 + 1 + scratch(r);
-  const size_t cols = (size_t)c.nqp * c.TWp + 1 + scratch(c);
-  return (rows > cols ? rows : cols) * sizeof(float);
+  const size_t r = edge_lds_floats(cs, true), c = edge_lds_floats(cs, false);
+  return (r > c ? r : c) * sizeof(float);
 }
 
 hipError_t launch_conv_back_edges(const Plan& p, const float* v, float* U, int view0, int nvb,
                                   hipStream_t s) {
   const ConvShape& cs = p.conv;
-  const size_t sm = conv_edges_lds_bytes(cs);
-  hipError_t e = hipFuncSetAttribute((const void*)conv_back_edges,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-  if (e != hipSuccess) return e;
-  dim3 grid(nvb, 4, (cs.ny + 63) / 64);
-  hipLaunchKernelGGL(conv_back_edges, grid, dim3(256), sm, s, v, p.psf, U, cs, view0);
-  return hipGetLastError();
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool krow = pass == 0;
+    if (!krow && cs.nz <= 2) break;                       // no interior rows: no column edges
+    const int nall = (krow ? cs.nx : cs.nz) / 16 + ((krow ? cs.nx : cs.nz) % 16 != 0) + krow;
+    hipError_t e;
+    switch (edge_pick_nb(nall)) {
+      case 1: e = launch_edges_nb<1>(cs, v, p.psf, U, view0, nvb, krow, s); break;
+      case 2: e = launch_edges_nb<2>(cs, v, p.psf, U, view0, nvb, krow, s); break;
+      case 3: e = launch_edges_nb<3>(cs, v, p.psf, U, view0, nvb, krow, s); break;
+      case 4: e = launch_edges_nb<4>(cs, v, p.psf, U, view0, nvb, krow, s); break;
+      case 5: e = launch_edges_nb<5>(cs, v, p.psf, U, view0, nvb, krow, s); break;
+      case 6: e = launch_edges_nb<6>(cs, v, p.psf, U, view0, nvb, krow, s); break;
+      case 7: e = launch_edges_nb<7>(cs, v, p.psf, U, view0, nvb, krow, s); break;
+      case 8: e = launch_edges_nb<8>(cs, v, p.psf, U, view0, nvb, krow, s); break;
+      default: e = launch_edges_nb<9>(cs, v, p.psf, U, view0, nvb, krow, s); break;
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 void tune_conv_chunks(ConvShape& cs, int views) {
