@@ -29,10 +29,18 @@ CFLAGS = [
     "-I", os.path.join(ROOT, "include"), "-Wno-unused-result",
 ]
 
+# Per-file code generation options.  The 4x4-block FP32 convolution keeps its
+# matrix-core accumulators in ordinary VGPRs: with accumulation registers the
+# allocator rotates them at the end of each tap and restores them with a run
+# of register moves at the head of the next.
+EXTRA = {
+    "conv_m4.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *CFLAGS, *EXTRA.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

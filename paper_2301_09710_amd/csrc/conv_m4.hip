@@ -1,0 +1,474 @@
+// PSF convolution on FP32 matrix cores with 4x4 blocks (v_mfma_f32_4x4x1f32:
+// sixteen independent 4x4 rank-1 updates per instruction), the replicate-
+// padded convolution of Sec. II-A (Alg. 1) and its zero-padded correlation
+// (Alg. 2, interior of the adjoint).
+//
+// The 16x16x4 Toeplitz form (conv_mfma.hip) executes (16 + pz - 1) / pz of
+// the algorithmic work because an M-block is 16 output rows tall and the band
+// of a PSF row spans 16 + pz - 1 input rows.  With 4-row blocks the band
+// costs (pz + 3) / pz instead (1.08x for pz = 37), at the same FP32 matrix
+// rate per instruction cycle.
+//
+// Mapping.  Lane 4b + q of a wave belongs to block b (of 16) and holds row q
+// of the block's A column, column q of its B row, and column q of its 4x4
+// result (result row = accumulator register).  Each block owns kZt x kXt
+// output tiles of 4 x 4 bins (z x x); for one PSF column a (x tap) and one
+// input row, a tile's update is
+//   C[m][n] += p[b(m, row)][a] * in[row][x_n -/+ a]
+// with b(m, row) the z tap that links output row m to the input row.  For a
+// tile whose first output row lies delta rows before the input row, the A
+// column depends on delta only, so the steps of one tap run over delta: one
+// A value (one LDS read) serves every tile of the step, and each input row is
+// read from LDS once per tap and kept in registers while the tiles that need
+// it pass (rows delta, delta + 4, ..., delta + 4 (kZt - 1)).
+//
+// Operands come from LDS:
+//   - the input region is stored transposed (z contiguous, column stride RRS
+//     chosen so that the 32 lanes of a half wave fall in distinct banks), so
+//     every row offset is an instruction immediate;
+//   - the PSF is stored as one zero-padded column per x tap, laid out so that
+//     step delta of lane q reads a fixed immediate offset from a per-tap base.
+//
+// Forward: a workgroup owns a (4 kZt BZ) x (32 BX) output tile of one view and
+// a chunk of depth planes, stages each plane's region (replicate padding by
+// clamped source indices) and PSF, and adds the plane into the accumulators;
+// each plane's sum is folded into a second set, so FP32 chains stay one plane
+// long.  The next plane's region and PSF are loaded into registers while the
+// current plane is being computed.  Partial sums per chunk are reduced in a
+// fixed order afterwards.  Adjoint: the projection region is staged once with
+// zero padding and every depth plane of the chunk is computed from it with its
+// own PSF; the edge rows and columns are rewritten by conv_back_edges.
+#include "internal.h"
+
+namespace spect {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kZt = 5;       // z tiles (4 rows each) per block
+constexpr int kXt = 2;       // x tiles (4 columns each) per block
+constexpr int kLook = 2;     // steps of operands loaded ahead of their MFMAs
+constexpr int kPfRows = 32;  // region rows per wave held for the next plane (RR <= 128)
+constexpr int kPfCols = 3;   // 64-column sweeps of a region row (RC <= 192)
+constexpr int kPfPsf = 16;   // PSF table elements per thread (px * PL4 <= 4096)
+
+__device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ int clampi(int q, int lo, int hi) { return q < lo ? lo : (q > hi ? hi : q); }
+
+// Workgroup id -> logical id, so that consecutive logical ids (which share
+// input planes) land on the same XCD; workgroups are dealt to the 8 XCDs
+// round-robin.
+__device__ __forceinline__ int xcd_remap(int wg, int total) {
+  const int per = total / 8, rem = total % 8, x = wg % 8, slot = wg / 8;
+  return x * per + min(x, rem) + slot;
+}
+
+// Depth planes of chunk c: [c ny / nchunk, (c+1) ny / nchunk).
+__device__ __forceinline__ void chunk_range(int c, int nchunk, int ny, int& j0, int& j1) {
+  j0 = (int)(((long long)c * ny) / nchunk);
+  j1 = (int)(((long long)(c + 1) * ny) / nchunk);
+}
+
+// All taps of one plane into acc.  Lane pointers: pa = P + pa_lane (tap 0),
+// advanced by PL4 per tap, read at offset (ND - 1 - t) forward or t adjoint
+// for step t; pb = RT + pb_lane (tap 0, x tile 0), moved by -RRS (forward) or
+// +RRS (adjoint) per tap, x tile j at +4 j RRS, input row r at +r.
+template <int ND4, bool kBack>
+__device__ __forceinline__ void m4_plane(const float* __restrict__ P, const float* __restrict__ RT,
+                                         int pa_lane, int pb_lane, int PL4, int RRS, int px,
+                                         floatx4 (&acc)[kZt][kXt]) {
+  constexpr int ND = 4 * ND4;                 // steps per tap
+  constexpr int NR = 4 * (kZt - 1) + ND;      // input rows per tap
+  float A[ND], B[NR][kXt];
+  const int tstep = kBack ? RRS : -RRS;
+  const int xstep = 4 * RRS;
+  // operands first used at step t of a tap: its A value and the input rows
+  // t + 4 i (t < 4: every tile's first row) or t + 4 (kZt - 1) (later steps)
+  auto load = [&](int t, const float* pa, const float* pb) {
+    A[t] = pa[kBack ? t : ND - 1 - t];
+    if (t < 4) {
+#pragma unroll
+      for (int i = 0; i < kZt; ++i)
+#pragma unroll
+        for (int j = 0; j < kXt; ++j) B[t + 4 * i][j] = pb[j * xstep + t + 4 * i];
+    } else {
+#pragma unroll
+      for (int j = 0; j < kXt; ++j) B[t + 4 * (kZt - 1)][j] = pb[j * xstep + t + 4 * (kZt - 1)];
+    }
+  };
+  const float* pa = P + pa_lane;
+  const float* pb = RT + pb_lane;
+#pragma unroll
+  for (int t = 0; t < kLook; ++t) load(t, pa, pb);
+  for (int a = 0; a < px; ++a) {
+    const int an = a + 1 < px ? a + 1 : a;    // the last tap reloads itself (values unused)
+    const float* pan = P + pa_lane + an * PL4;
+    const float* pbn = RT + pb_lane + an * tstep;
+    float An[kLook], Bn[kLook][kZt][kXt];
+#pragma unroll
+    for (int s = 0; s < ND; ++s) {
+      const int t = s + kLook;
+      if (t < ND) {
+        load(t, pa, pb);
+      } else {
+        const int u = t - ND;                   // < kLook <= 4: rows u + 4 i of the next tap
+        An[u] = pan[kBack ? u : ND - 1 - u];
+#pragma unroll
+        for (int i = 0; i < kZt; ++i)
+#pragma unroll
+          for (int j = 0; j < kXt; ++j) Bn[u][i][j] = pbn[j * xstep + u + 4 * i];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int i = 0; i < kZt; ++i)
+#pragma unroll
+        for (int j = 0; j < kXt; ++j) acc[i][j] = mfma4(A[s], B[s + 4 * i][j], acc[i][j]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kLook; ++u) {
+      A[u] = An[u];
+#pragma unroll
+      for (int i = 0; i < kZt; ++i)
+#pragma unroll
+        for (int j = 0; j < kXt; ++j) B[u + 4 * i][j] = Bn[u][i][j];
+    }
+    pa = pan;
+    pb = pbn;
+  }
+}
+
+// PSF table of one plane: P[a PL4 + t] = p[t - Z][a] (zero outside the taps),
+// Z = ND - pz forward (column reversed by the read order), 3 adjoint.
+struct PsfTable {
+  float v[kPfPsf];
+  __device__ __forceinline__ void load(const M4Shape& s, const float* __restrict__ pj, int Z) {
+#pragma unroll
+    for (int u = 0; u < kPfPsf; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      float x = 0.0f;
+      if (e < s.px * s.PL4) {
+        const int a = e / s.PL4, b = e - a * s.PL4 - Z;
+        if (b >= 0 && b < s.pz) x = pj[b * s.px + a];
+      }
+      v[u] = x;
+    }
+  }
+  __device__ __forceinline__ void store(const M4Shape& s, float* P) const {
+#pragma unroll
+    for (int u = 0; u < kPfPsf; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      if (e < s.px * s.PL4) P[e] = v[u];
+    }
+  }
+};
+
+// Forward input region of one plane, rows w + 4 r (input k = k0 - hb + row,
+// clamped) and columns lane + 64 u (input i = i0 - ha + column, clamped).
+struct FwdRegion {
+  float r[kPfRows][kPfCols];
+  __device__ __forceinline__ void load(const M4Shape& s, const float* __restrict__ Wj, int k0,
+                                       int i0, size_t row_stride, int w, int lane) {
+#pragma unroll
+    for (int rr = 0; rr < kPfRows; ++rr) {
+      const int row = w + 4 * rr;
+      const float* src = Wj + (size_t)clampi(k0 - s.hb + row, 0, s.nz - 1) * row_stride;
+#pragma unroll
+      for (int u = 0; u < kPfCols; ++u) {
+        const int col = lane + 64 * u;
+        r[rr][u] = (row < s.RR && col < s.RC) ? src[clampi(i0 - s.ha + col, 0, s.nx - 1)] : 0.0f;
+      }
+    }
+  }
+  __device__ __forceinline__ void store(const M4Shape& s, float* RT, int w, int lane) const {
+#pragma unroll
+    for (int rr = 0; rr < kPfRows; ++rr) {
+      const int row = w + 4 * rr;
+#pragma unroll
+      for (int u = 0; u < kPfCols; ++u) {
+        const int col = lane + 64 * u;
+        if (row < s.RR && col < s.RC) RT[col * s.RRS + row] = r[rr][u];
+      }
+    }
+  }
+};
+
+// ---------------------------------------------------------------- forward
+template <int ND4>
+__global__ __launch_bounds__(256, 1) void conv_fwd_m4(const float* __restrict__ W,
+                                                      const float* __restrict__ psf,
+                                                      float* __restrict__ partial, M4Shape s,
+                                                      int view0, int nvb) {
+  extern __shared__ float sm[];
+  float* RT = sm;                                  // RC x RRS: input region, z contiguous
+  float* P = sm + s.RC * s.RRS;                    // px x PL4: PSF columns
+  const int ntile = s.tiles_k * s.tiles_i;
+  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = logical % ntile, rest = logical / ntile;
+  const int tk = tile / s.tiles_i, ti = tile - tk * s.tiles_i;
+  const int c = rest % s.nchunk, lb = rest / s.nchunk, l = view0 + lb;
+  const int k0 = tk * 4 * kZt * s.BZ, i0 = ti * 32 * s.BX;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane & 3, blk = lane >> 2;
+  const int bz = blk / s.BX, bx = blk - bz * s.BX;
+  const int zb = 4 * kZt * bz, xo = 8 * s.BX * w + 8 * bx;  // block origin in the tile
+  int j0, j1;
+  chunk_range(c, s.nchunk, s.ny, j0, j1);
+  const size_t row_stride = (size_t)s.ny * s.nx;
+  const float* Wl = W + (size_t)lb * s.nz * row_stride;
+  const float* psf_l = psf + (size_t)l * s.ny * s.pz * s.px;
+  constexpr int ND = 4 * ND4;
+  const int Z = ND - s.pz;
+  // step t of tap a: A = P[a PL4 + q + ND - 1 - t] = p[2 hb - t + q][a];
+  // B (x tile j, row r) = RT[(xo + 4 j + q + 2 ha - a) RRS + zb + r]
+  const int pa_lane = q;
+  const int pb_lane = (xo + q + 2 * s.ha) * s.RRS + zb;
+
+  floatx4 tot[kZt][kXt];
+#pragma unroll
+  for (int i = 0; i < kZt; ++i)
+#pragma unroll
+    for (int j = 0; j < kXt; ++j) tot[i][j] = {0.f, 0.f, 0.f, 0.f};
+  FwdRegion reg;
+  PsfTable tab;
+  if (j0 < j1) {
+    reg.load(s, Wl + (size_t)j0 * s.nx, k0, i0, row_stride, w, lane);
+    tab.load(s, psf_l + (size_t)j0 * s.pz * s.px, Z);
+  }
+  for (int j = j0; j < j1; ++j) {
+    __syncthreads();                               // previous plane consumed
+    reg.store(s, RT, w, lane);
+    tab.store(s, P);
+    __syncthreads();
+    if (j + 1 < j1) {
+      reg.load(s, Wl + (size_t)(j + 1) * s.nx, k0, i0, row_stride, w, lane);
+      tab.load(s, psf_l + (size_t)(j + 1) * s.pz * s.px, Z);
+    }
+    floatx4 acc[kZt][kXt];
+#pragma unroll
+    for (int i = 0; i < kZt; ++i)
+#pragma unroll
+      for (int jj = 0; jj < kXt; ++jj) acc[i][jj] = {0.f, 0.f, 0.f, 0.f};
+    m4_plane<ND4, false>(P, RT, pa_lane, pb_lane, s.PL4, s.RRS, s.px, acc);
+#pragma unroll
+    for (int i = 0; i < kZt; ++i)
+#pragma unroll
+      for (int jj = 0; jj < kXt; ++jj) tot[i][jj] += acc[i][jj];
+  }
+  // result row v of tile (i, jj): k = k0 + zb + 4 i + v, x = i0 + xo + 4 jj + q
+  float* out = partial + ((size_t)c * nvb + lb) * s.nz * s.nx;
+#pragma unroll
+  for (int i = 0; i < kZt; ++i)
+#pragma unroll
+    for (int jj = 0; jj < kXt; ++jj) {
+      const int x = i0 + xo + 4 * jj + q;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = k0 + zb + 4 * i + v;
+        if (k < s.nz && x < s.nx) out[(size_t)k * s.nx + x] = tot[i][jj][v];
+      }
+    }
+}
+
+// ---------------------------------------------------------------- adjoint
+// u[k][i] = sum_{a,b} p[b][a] v[k + b - hb][i + a - ha] (v zero outside) for
+// every bin of the tile and every plane of the chunk.
+template <int ND4>
+__global__ __launch_bounds__(256, 1) void conv_back_m4(const float* __restrict__ v,
+                                                       const float* __restrict__ psf,
+                                                       float* __restrict__ U, M4Shape s,
+                                                       int view0, int nvb) {
+  extern __shared__ float sm[];
+  float* RT = sm;                                  // RC x RRS: projection region, z contiguous
+  float* P = sm + s.RC * s.RRS;                    // px x PL4: PSF columns
+  const int ntile = s.tiles_k * s.tiles_i;
+  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = logical % ntile, rest = logical / ntile;
+  const int tk = tile / s.tiles_i, ti = tile - tk * s.tiles_i;
+  const int c = rest % s.nchunk_back, lb = rest / s.nchunk_back, l = view0 + lb;
+  const int k0 = tk * 4 * kZt * s.BZ, i0 = ti * 32 * s.BX;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane & 3, blk = lane >> 2;
+  const int bz = blk / s.BX, bx = blk - bz * s.BX;
+  const int zb = 4 * kZt * bz, xo = 8 * s.BX * w + 8 * bx;
+  int j0, j1;
+  chunk_range(c, s.nchunk_back, s.ny, j0, j1);
+  const float* vl = v + (size_t)l * s.nz * s.nx;
+  const float* psf_l = psf + (size_t)l * s.ny * s.pz * s.px;
+
+  // region row r <-> input k = k0 - hb + r, column cc <-> input i = i0 - ha + cc
+  for (int e = threadIdx.x; e < s.RR * s.RC; e += 256) {
+    const int r = e / s.RC, cc = e - r * s.RC;
+    const int kk = k0 - s.hb + r, ii = i0 - s.ha + cc;
+    RT[cc * s.RRS + r] =
+        (kk >= 0 && kk < s.nz && ii >= 0 && ii < s.nx) ? vl[(size_t)kk * s.nx + ii] : 0.0f;
+  }
+  // step t of tap a: A = P[a PL4 + 3 - q + t] = p[t - q][a];
+  // B (x tile j, row r) = RT[(xo + 4 j + q + a) RRS + zb + r]
+  const int pa_lane = 3 - q;
+  const int pb_lane = (xo + q) * s.RRS + zb;
+  PsfTable tab;
+  if (j0 < j1) tab.load(s, psf_l + (size_t)j0 * s.pz * s.px, 3);
+  for (int j = j0; j < j1; ++j) {
+    __syncthreads();                               // region staged / previous plane consumed
+    tab.store(s, P);
+    __syncthreads();
+    if (j + 1 < j1) tab.load(s, psf_l + (size_t)(j + 1) * s.pz * s.px, 3);
+    floatx4 acc[kZt][kXt];
+#pragma unroll
+    for (int i = 0; i < kZt; ++i)
+#pragma unroll
+      for (int jj = 0; jj < kXt; ++jj) acc[i][jj] = {0.f, 0.f, 0.f, 0.f};
+    m4_plane<ND4, true>(P, RT, pa_lane, pb_lane, s.PL4, s.RRS, s.px, acc);
+    float* out = U + (size_t)lb * s.nz * s.ny * s.nx + (size_t)j * s.nx;
+#pragma unroll
+    for (int i = 0; i < kZt; ++i)
+#pragma unroll
+      for (int jj = 0; jj < kXt; ++jj) {
+        const int x = i0 + xo + 4 * jj + q;
+#pragma unroll
+        for (int vv = 0; vv < 4; ++vv) {
+          const int k = k0 + zb + 4 * i + vv;
+          if (k < s.nz && x < s.nx) out[(size_t)k * s.ny * s.nx + x] = acc[i][jj][vv];
+        }
+      }
+  }
+}
+
+#define SPECT_M4_CASES(X) \
+  X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+
+size_t m4_lds_bytes(const M4Shape& s) {
+  return ((size_t)s.RC * s.RRS + (size_t)s.px * s.PL4) * sizeof(float);
+}
+
+template <int ND4>
+hipError_t launch_m4(const M4Shape& s, bool back, const float* in, const float* psf, float* out,
+                     int view0, int nvb, hipStream_t st) {
+  const size_t sm = m4_lds_bytes(s);
+  const void* fn = back ? (const void*)conv_back_m4<ND4> : (const void*)conv_fwd_m4<ND4>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+  if (e != hipSuccess) return e;
+  dim3 grid(s.tiles_k * s.tiles_i * (back ? s.nchunk_back : s.nchunk) * nvb);
+  if (back)
+    hipLaunchKernelGGL(conv_back_m4<ND4>, grid, dim3(256), sm, st, in, psf, out, s, view0, nvb);
+  else
+    hipLaunchKernelGGL(conv_fwd_m4<ND4>, grid, dim3(256), sm, st, in, psf, out, s, view0, nvb);
+  return hipGetLastError();
+}
+
+template <int ND4>
+int m4_wgs_per_cu(const M4Shape& s, bool back) {
+  int nb = 0;
+  const void* fn = back ? (const void*)conv_back_m4<ND4> : (const void*)conv_fwd_m4<ND4>;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, m4_lds_bytes(s)) != hipSuccess)
+    nb = 0;
+  return nb < 1 ? 1 : nb;
+}
+
+// Largest number of lanes of one half wave (32 lanes) that share an LDS bank
+// for the B reads of a column stride rrs (32 banks of 4 bytes).
+int m4_bank_conflicts(int rrs, int BX) {
+  int worst = 0;
+  for (int h = 0; h < 2; ++h) {
+    int count[32] = {0};
+    for (int lane = 32 * h; lane < 32 * h + 32; ++lane) {
+      const int blk = lane >> 2, q = lane & 3, bz = blk / BX, bx = blk % BX;
+      const long long addr = (long long)(8 * bx + q) * rrs + 4 * kZt * bz;
+      const int bank = (int)(addr % 32);
+      if (++count[bank] > worst) worst = count[bank];
+    }
+  }
+  return worst;
+}
+
+// Depth chunks per (tile, view): minimise rounds * planes per workgroup.
+int m4_pick_chunks(int ny, long long tiles_views, long long slots) {
+  int best = 1;
+  long long best_cost = -1;
+  for (int n = 1; n <= kMaxChunks && n <= ny; ++n) {
+    const long long rounds = (tiles_views * n + slots - 1) / slots;
+    const long long cost = rounds * ((ny + n - 1) / n);
+    if (best_cost < 0 || cost < best_cost) { best_cost = cost; best = n; }
+  }
+  return best;
+}
+
+}  // namespace
+
+M4Shape make_m4_shape(const spect_geom& g) {
+  M4Shape best{};
+  best.ok = false;
+  double best_area = 0.0;
+  const int ND4 = (g.pz + 3 + 3) / 4;
+  for (int BX = 1; BX <= 16; BX *= 2) {
+    M4Shape s{};
+    s.nx = g.nx; s.ny = g.ny; s.nz = g.nz; s.px = g.px; s.pz = g.pz;
+    s.ha = (g.px - 1) / 2; s.hb = (g.pz - 1) / 2;
+    s.ND4 = ND4;
+    s.BX = BX;
+    s.BZ = 16 / BX;
+    s.tiles_k = (g.nz + 4 * kZt * s.BZ - 1) / (4 * kZt * s.BZ);
+    s.tiles_i = (g.nx + 32 * BX - 1) / (32 * BX);
+    s.RR = 4 * kZt * (s.BZ - 1) + 4 * (kZt - 1) + 4 * ND4;
+    s.RC = 32 * BX + g.px - 1;
+    s.PL4 = 4 * ND4 + 3;
+    int rrs = s.RR | 1, best_rrs = rrs, best_conf = 1 << 30;
+    for (; rrs < s.RR + 64; rrs += 2) {
+      const int cf = m4_bank_conflicts(rrs, BX);
+      if (cf < best_conf) { best_conf = cf; best_rrs = rrs; }
+      if (cf <= 1) break;
+    }
+    s.RRS = best_rrs;
+    s.nchunk = 1;
+    s.nchunk_back = 1;
+    s.ok = ND4 >= 1 && ND4 <= 16 && s.RR <= 4 * kPfRows && s.RC <= 64 * kPfCols &&
+           g.px * s.PL4 <= 256 * kPfPsf && m4_lds_bytes(s) <= kLdsBytes;
+    if (!s.ok) continue;
+    const double area = (double)s.tiles_k * 4 * kZt * s.BZ * s.tiles_i * 32 * BX;
+    if (!best.ok || area < best_area) { best = s; best_area = area; }
+  }
+  return best;
+}
+
+// Relative issue cost of the two FP32 tilings for a plane and a tap: padded
+// output area times the products issued per output bin (the K rows of a
+// 16-row band, or the steps of a 4-row one), the 4x4 blocks at the 0.92
+// relative instruction rate measured for them against 16x16x4.
+bool m4_preferred(const M4Shape& s, const ConvShape& cs) {
+  if (!s.ok) return false;
+  const double old_cost = (double)cs.tiles_k * 16 * cs.WK * cs.tiles_i * 32 * cs.WI * 4 * cs.KS;
+  const double new_cost = (double)s.tiles_k * 4 * kZt * s.BZ * s.tiles_i * 32 * s.BX * 4 * s.ND4 / 0.92;
+  return new_cost < old_cost;
+}
+
+void tune_m4_chunks(M4Shape& s, int views) {
+  int dev = 0, cus = 0;
+  if (!s.ok || hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    return;
+  int fw = 1, bw = 1;
+  switch (s.ND4) {
+#define CASE(K) case K: fw = m4_wgs_per_cu<K>(s, false); bw = m4_wgs_per_cu<K>(s, true); break;
+    SPECT_M4_CASES(CASE)
+#undef CASE
+    default: return;
+  }
+  const long long tv = (long long)s.tiles_k * s.tiles_i * views;
+  s.nchunk = m4_pick_chunks(s.ny, tv, (long long)cus * fw);
+  s.nchunk_back = m4_pick_chunks(s.ny, tv, (long long)cus * bw);
+}
+
+hipError_t launch_conv_m4(const Plan& p, bool back, const float* in, float* out, int view0,
+                          int nvb, hipStream_t st) {
+  switch (p.m4.ND4) {
+#define CASE(K) case K: return launch_m4<K>(p.m4, back, in, p.psf, out, view0, nvb, st);
+    SPECT_M4_CASES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace spect

@@ -715,6 +715,7 @@ static int pick_chunks(int ny, long long tiles_views, long long slots) {
 
 hipError_t launch_conv_fwd_mfma(const Plan& p, const float* W, float* partial, int view0, int nvb,
                                 hipStream_t s) {
+  if (p.use_m4) return launch_conv_m4(p, false, W, partial, view0, nvb, s);
   const ConvShape& cs = p.conv;
   switch (cs.KS) {
 #define CASE(K) case K: return launch_fwd_ks<K>(cs, W, p.psf, partial, view0, nvb, s);
@@ -726,6 +727,7 @@ hipError_t launch_conv_fwd_mfma(const Plan& p, const float* W, float* partial, i
 
 hipError_t launch_conv_back_mfma(const Plan& p, const float* v, float* U, int view0, int nvb,
                                  hipStream_t s) {
+  if (p.use_m4) return launch_conv_m4(p, true, v, U, view0, nvb, s);
   ConvShape cs = p.conv;
   cs.RSI = cs.RSI_back;
   cs.jc = cs.jc_back;

@@ -47,6 +47,18 @@ struct ConvShape {
   int jc_back, nchunk_back;
 };
 
+// Tiling of the FP32 convolution on 4x4 matrix blocks (see conv_m4.hip).
+struct M4Shape {
+  int nx, ny, nz, px, pz, ha, hb;
+  int ND4;              // steps per tap / 4: ceil((pz + 3) / 4)
+  int BZ, BX;           // blocks of a wave along z and x (BZ * BX = 16)
+  int tiles_k, tiles_i; // workgroup tiles of 20 BZ x 32 BX output bins
+  int RR, RC, RRS;      // region rows (z), columns (x), column stride in LDS
+  int PL4;              // PSF column length in LDS
+  int nchunk, nchunk_back;
+  bool ok;              // the tiling fits the kernels' register and LDS budgets
+};
+
 // Tiling of the BF16 / FP16 convolution (see conv_lp.hip).
 constexpr int kLpMaxWaves = 8;   // M-blocks (16 z each) per workgroup tile at most
 struct LpShape {
@@ -116,6 +128,8 @@ struct Plan {
   float* rot_scratch;   // rotation working slices (nx > kMaxLdsN), else nullptr
   bool use_mfma;        // MFMA convolution path (else the direct kernels)
   ConvShape conv;
+  M4Shape m4;           // FP32 convolution on 4x4 blocks, used when use_m4
+  bool use_m4;
   int conv_precision;   // SPECT_CONV_FP32 / _BF16 / _FP16
   LpShape lp;           // tiling of the reduced-precision convolution
   Profiler* prof;       // non-null while spect_profile_start is active
@@ -149,6 +163,10 @@ ConvShape make_conv_shape(const spect_geom& g, int jc_fwd, int jc_back);
 void tune_conv_chunks(ConvShape& cs, int views);
 size_t conv_mfma_lds_bytes(const ConvShape& cs, bool back);
 size_t conv_edges_lds_bytes(const ConvShape& cs);
+M4Shape make_m4_shape(const spect_geom& g);
+// Whether the 4x4-block tiling issues fewer matrix-core cycles than the 16x16 one.
+bool m4_preferred(const M4Shape& s, const ConvShape& cs);
+void tune_m4_chunks(M4Shape& s, int views);
 LpShape make_lp_shape(const spect_geom& g);
 size_t lp_lds_bytes(const LpShape& s, bool split);
 bool lp_supported(const spect_geom& g);
@@ -165,6 +183,8 @@ hipError_t launch_conv_fwd_mfma(const Plan& p, const float* W, float* partial, i
                                 hipStream_t s);
 hipError_t launch_conv_back_mfma(const Plan& p, const float* v, float* U, int view0, int nvb,
                                  hipStream_t s);
+hipError_t launch_conv_m4(const Plan& p, bool back, const float* in, float* out, int view0,
+                          int nvb, hipStream_t s);
 hipError_t launch_conv_back_edges(const Plan& p, const float* v, float* U, int view0, int nvb,
                                   hipStream_t s);
 hipError_t launch_conv_fwd(const Plan& p, const float* W, float* partial, int view0, int nvb,

@@ -204,9 +204,21 @@ spect_status spect_plan_create(spect_plan* out, const spect_geom* g, const float
   p->rot_scratch = g->nx > kMaxLdsN ? reinterpret_cast<float*>(p->ws + lay.rot_scratch) : nullptr;
   p->use_mfma = conv_mfma_supported(*g);
   p->conv = make_conv_shape(*g, kFwdJChunk, kBackJChunk);
+  p->m4 = make_m4_shape(*g);
+  p->use_m4 = false;
   if (p->use_mfma) {
     tune_conv_chunks(p->conv, g->nview);   // independent of view_batch: same sums
     p->nchunk = p->conv.nchunk;          // forward partial sums per view
+    // SPECT_FP32_TILING = "4x4" or "16x16" overrides the cost model ("auto")
+    const char* tiling = std::getenv("SPECT_FP32_TILING");
+    bool m4 = m4_preferred(p->m4, p->conv);
+    if (tiling && std::strcmp(tiling, "4x4") == 0) m4 = p->m4.ok;
+    if (tiling && std::strcmp(tiling, "16x16") == 0) m4 = false;
+    if (m4) {
+      tune_m4_chunks(p->m4, g->nview);
+      p->use_m4 = true;
+      p->nchunk = p->m4.nchunk;
+    }
   }
   p->conv_precision = g->conv_precision;
   if (p->conv_precision != SPECT_CONV_FP32) {
