@@ -34,6 +34,7 @@ class Geometry:
     pz: int
     dy: float = 1.0
     angles: object = None          # None -> theta_l = 2 pi l / nview
+    rotation: str = "3pass"        # "3pass" (three 1-D shears) or "bilinear" (Sec. II-A)
     splits: list = field(init=False)
 
     def __post_init__(self):
@@ -41,7 +42,17 @@ class Geometry:
             raise ValueError("rotation about z needs nx == ny")
         if self.px % 2 == 0 or self.pz % 2 == 0:
             raise ValueError("PSF sizes must be odd")
+        if self.rotation not in rotation.METHODS:
+            raise ValueError("rotation must be '3pass' or 'bilinear'")
         self.splits = geometry.view_splits(self.nview, self.angles)
+
+
+def rotate_view(f, geom: Geometry, l: int):
+    return rotation.METHODS[geom.rotation][0](f, geom.splits[l])
+
+
+def rotate_view_T(g, geom: Geometry, l: int):
+    return rotation.METHODS[geom.rotation][1](g, geom.splits[l])
 
 
 def vol_to_paper(x):             # [nz][ny][nx] -> x[i, j, k]
@@ -58,7 +69,7 @@ def psf_view_paper(psf, l):      # [nview][ny][pz][px] -> p[a, b, j] for view l
 
 def mubar_view(mu_p, geom: Geometry, l: int):
     """Eq. (1) for view l; mu_p in paper order (nx, ny, nz)."""
-    return attenuation.mubar(rotation.rotate(mu_p, geom.splits[l]), geom.dy)
+    return attenuation.mubar(rotate_view(mu_p, geom, l), geom.dy)
 
 
 def forward(x, mu, psf, geom: Geometry, views=None, conv="direct") -> np.ndarray:
@@ -68,7 +79,7 @@ def forward(x, mu, psf, geom: Geometry, views=None, conv="direct") -> np.ndarray
     mup = vol_to_paper(mu)
     v = np.zeros((geom.nview, geom.nz, geom.nx))
     for l in (range(geom.nview) if views is None else views):
-        w = rotation.rotate(xp, geom.splits[l]) * mubar_view(mup, geom, l)
+        w = rotate_view(xp, geom, l) * mubar_view(mup, geom, l)
         p = psf_view_paper(psf, l)
         if conv == "direct":
             v2 = convolution.conv_planes(w, p).sum(axis=1)           # depth sum
@@ -92,5 +103,5 @@ def back(v, mu, psf, geom: Geometry, views=None, conv="direct") -> np.ndarray:
             u = convolution.conv_planes_T(g, p)
         else:
             u = convolution.conv_planes_T_fft(g2, p)
-        x += rotation.rotate_T(u * mubar_view(mup, geom, l), geom.splits[l])
+        x += rotate_view_T(u * mubar_view(mup, geom, l), geom, l)
     return vol_from_paper(x)

@@ -16,6 +16,8 @@ Rotation = pass3 . pass2 . pass1 . P_m.
 
 The transposes below are written as the literal adjoint of each gather
 (scatter-add of the same weights), not as a rotation by -theta.
+
+The 2-D bilinear alternative (also Sec. II-A) is at the end of the file.
 """
 from __future__ import annotations
 
@@ -123,10 +125,66 @@ def rotate_T(g: np.ndarray, split) -> np.ndarray:
     return quarter_turn_T(h, split.m)
 
 
+# ---------------------------------------------------------------- 2-D bilinear
+# Sec. II-A implements, beside the 3-pass shears, rotation by 2-D bilinear
+# interpolation with zero padding.  Reading: the same exact quarter turn P_m
+# first, then the gather out(p) = sum over the four grid neighbours q of
+# s(p) = R(phi)^-1 (p - c) + c of the bilinear weights times (P_m f)(q), with
+# (P_m f) = 0 outside the grid.  P_m is a symmetry of the grid, so this is
+# bilinear interpolation of f at R(theta)^-1 (p - c) + c.
+
+def bilinear_taps(n: int, phi: float):
+    """Source position s(p) of every output pixel p = (i, j) for the residual
+    angle phi: integer parts (qi, qj) and fractions (fi, fj), each (n, n)."""
+    c = (n - 1) / 2.0
+    u, v = np.meshgrid(np.arange(n) - c, np.arange(n) - c, indexing="ij")
+    co, sn = math.cos(phi), math.sin(phi)
+    si = c + co * u + sn * v               # R(phi)^-1 = [[cos, sin], [-sin, cos]]
+    sj = c - sn * u + co * v
+    qi, qj = np.floor(si), np.floor(sj)
+    return qi.astype(np.int64), qj.astype(np.int64), si - qi, sj - qj
+
+
+def _bilinear_corners(n: int, phi: float):
+    qi, qj, fi, fj = bilinear_taps(n, phi)
+    for di, wi in ((0, 1.0 - fi), (1, fi)):
+        for dj, wj in ((0, 1.0 - fj), (1, fj)):
+            a, b = qi + di, qj + dj
+            ok = (a >= 0) & (a < n) & (b >= 0) & (b < n)
+            yield a, b, wi * wj, ok
+
+
+def rotate_bilinear(f: np.ndarray, split) -> np.ndarray:
+    """Rotate f[i, j, ...] by theta = m*90deg + phi with bilinear interpolation."""
+    n = f.shape[0]
+    g = quarter_turn(np.asarray(f, dtype=np.float64), split.m)
+    out = np.zeros(g.shape, dtype=np.float64)
+    trail = (1,) * (g.ndim - 2)
+    for a, b, w, ok in _bilinear_corners(n, split.phi):
+        out[ok] += w[ok].reshape((-1,) + trail) * g[a[ok], b[ok]]
+    return out
+
+
+def rotate_bilinear_T(g: np.ndarray, split) -> np.ndarray:
+    """Exact transpose of rotate_bilinear: every output pixel scatters its
+    four weights back onto the samples it read, then P_m^T."""
+    n = g.shape[0]
+    g = np.asarray(g, dtype=np.float64)
+    h = np.zeros(g.shape, dtype=np.float64)
+    trail = (1,) * (g.ndim - 2)
+    for a, b, w, ok in _bilinear_corners(n, split.phi):
+        np.add.at(h, (a[ok], b[ok]), w[ok].reshape((-1,) + trail) * g[ok])
+    return quarter_turn_T(h, split.m)
+
+
+METHODS = {"3pass": (rotate, rotate_T), "bilinear": (rotate_bilinear, rotate_bilinear_T)}
+
+
 def shear_shift_rows(n: int, split):
     """(pass-1/3 shifts per j, pass-2 shifts per i); exposed for tests."""
     return _pass_shifts(n, split)
 
 
 __all__ = ["quarter_turn", "quarter_turn_T", "quarter_turn_source", "shear_lines",
-           "shear_lines_T", "rotate", "rotate_T", "shear_shift_rows", "math"]
+           "shear_lines_T", "rotate", "rotate_T", "bilinear_taps", "rotate_bilinear",
+           "rotate_bilinear_T", "METHODS", "shear_shift_rows", "math"]
