@@ -79,6 +79,12 @@ typedef enum {
 #define SPECT_CACHE_MUBAR 0x1u  /* keep the attenuation factor of Eq. (1) for all
                                    views in the workspace (nview*nx*ny*nz floats),
                                    computed once at plan creation */
+#define SPECT_ROT_BILINEAR 0x2u /* rotate activity and attenuation by 2-D bilinear
+                                   interpolation with zero padding (the alternative
+                                   Sec. II-A names beside the 3-pass shears): after
+                                   the exact quarter turn, out(p) = bilinear sample at
+                                   R(phi)^-1 (p - c) + c; spect_back applies its exact
+                                   transpose.  Default: three 1-D shears. */
 
 /* Geometry of one plan (host struct, copied by spect_plan_create). */
 typedef struct {
@@ -89,7 +95,8 @@ typedef struct {
   const double* angles;   /* host array of nview angles in radians, or NULL for
                              theta_l = 2 pi l / nview (Sec. II-A); read only
                              during spect_plan_create */
-  uint32_t flags;         /* SPECT_CACHE_MUBAR or 0 */
+  uint32_t flags;         /* SPECT_CACHE_MUBAR | SPECT_ROT_BILINEAR, or 0; other
+                             bits give SPECT_ERR_VALUE */
   int32_t view_batch;     /* views processed per internal batch; 0 = all.
                              Smaller batches need less workspace. */
   int32_t conv_precision; /* SPECT_CONV_FP32 (0), SPECT_CONV_BF16, SPECT_CONV_FP16 or

@@ -78,15 +78,25 @@ struct LpShape {
 //   off[l][1][i], w[l][1][i]: pass 2 (along j, one entry per column i)
 // A pass computes out[q] = w.x * in[q + off] + w.y * in[q + off + 1], zero
 // outside [0, n); w.x = 1 - f and w.y = f of the fractional shift.
+// Per-view rotation tables in the workspace.  Each of the 2n entries of a
+// view holds two integers (off) and two floats (w):
+//   3-pass shears: (offset, 0) and the two tap weights of a row (entries
+//     [0, n), passes 1 and 3) or column (entries [n, 2n), pass 2);
+//   bilinear: integer parts and fractions of the sample position's terms,
+//     s = (c + cos (i - c) + sin (j - c), c - sin (i - c) + cos (j - c)),
+//     split as a row term in j (entries [0, n)) plus a column term in i
+//     (entries [n, 2n)).
+// rot[l] = (cos phi, sin phi) of the residual angle.
 struct Tables {
   const int32_t* quarter;
-  const int32_t* off;
-  const float2* w;
+  const int32_t* off;     // nview x 2n x 2
+  const float2* w;        // nview x 2n
+  const float2* rot;      // nview
 };
 
 // Workspace layout (byte offsets from the workspace base, 256-B aligned).
 struct Layout {
-  size_t tables_quarter, tables_off, tables_w;
+  size_t tables_quarter, tables_off, tables_w, tables_rot;
   size_t vol_batch;     // view_batch * N floats: W (forward) / U (back)
   size_t fwd_partial;   // nchunk * view_batch * nz * nx floats
   size_t back_partial;  // kBackGroups * N floats
@@ -127,6 +137,7 @@ struct Plan {
   float* mubar_batch;   // per-batch attenuation factors when not cached
   float* rot_scratch;   // rotation working slices (nx > kMaxLdsN), else nullptr
   bool use_mfma;        // MFMA convolution path (else the direct kernels)
+  bool bilinear;         // SPECT_ROT_BILINEAR
   ConvShape conv;
   M4Shape m4;           // FP32 convolution on 4x4 blocks, used when use_m4
   bool use_m4;
@@ -137,6 +148,7 @@ struct Plan {
   int32_t* h_quarter;
   int32_t* h_off;
   float2* h_w;
+  float2* h_rot;
 };
 
 // Run `launch` (which enqueues one kernel on s), bracketed by profiling

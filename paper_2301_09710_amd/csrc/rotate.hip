@@ -13,6 +13,11 @@
 // the forward kernels stage their input once per workgroup whatever the view;
 // the transpose applies P_m^T last, on the way into the accumulators.
 //
+// With SPECT_ROT_BILINEAR the three passes are replaced by one 2-D bilinear
+// gather per pixel after the same quarter turn (forward and attenuation), and
+// the transpose gathers, for each pixel, the output pixels whose samples used
+// it (see bil_adj_px).
+//
 // The attenuation and transpose kernels run the passes one after another in
 // LDS, on slices of odd row stride n + 1 (row passes, column passes and
 // quarter-turned reads are then free of bank conflicts), with each wave
@@ -77,13 +82,14 @@ __device__ __forceinline__ ViewTab carve_tab(float* after, int n) {
 __host__ __device__ __forceinline__ int round4(int floats) { return (floats + 3) & ~3; }
 
 __device__ __forceinline__ void load_tab(const Tables& tab, int l, int n, const ViewTab& t) {
-  const int32_t* off = tab.off + (size_t)l * 2 * n;
+  const int2* off = reinterpret_cast<const int2*>(tab.off) + (size_t)l * 2 * n;
   const float2* w = tab.w + (size_t)l * 2 * n;
   for (int e = threadIdx.x; e < 2 * n; e += NT) {
-    TabEntry te;                       // e13 and e2 are contiguous: [0, n) passes 1/3, [n, 2n) pass 2
+    TabEntry te;                       // e13 and e2 are contiguous: [0, n) rows, [n, 2n) columns
+    const int2 o = off[e];
     te.w = w[e];
-    te.o = off[e];
-    te.pad = 0;
+    te.o = o.x;
+    te.pad = o.y;
     t.e13[e] = te;
   }
 }
@@ -138,6 +144,71 @@ __device__ __forceinline__ float col_px(const float* Y, int n, int S, const View
   return w.x * a + w.y * b;
 }
 
+// ---------------------------------------------------------------- bilinear
+// 2-D bilinear rotation, the alternative to the 3-pass shears: output pixel
+// p = (i, j) samples the quarter-turned slice at s(p) = R(phi)^-1 (p - c) + c
+// with zero padding.  The tables hold the terms of s as integer part plus
+// fraction, a column term in i (t.e2) and a row term in j (t.e13), so a
+// sample position costs two integer and two float additions.
+struct BilPos { int qi, qj; float fi, fj; };
+__device__ __forceinline__ BilPos bil_pos(const ViewTab& t, int i, int j) {
+  const TabEntry a = t.e2[i], b = t.e13[j];
+  BilPos p;
+  p.qi = a.o + b.o;
+  p.qj = a.pad + b.pad;
+  p.fi = a.w.x + b.w.x;
+  p.fj = a.w.y + b.w.y;
+  if (p.fi >= 1.0f) { p.fi -= 1.0f; ++p.qi; }
+  if (p.fj >= 1.0f) { p.fj -= 1.0f; ++p.qj; }
+  return p;
+}
+
+// (B P_m x)(i, j) from the unrotated slice X, read through the quarter turn.
+__device__ __forceinline__ float bil_px(const float* X, int n, const QAddr& qa, const ViewTab& t,
+                                        int i, int j) {
+  const BilPos p = bil_pos(t, i, j);
+  float v = 0.0f;
+#pragma unroll
+  for (int dj = 0; dj < 2; ++dj) {
+    const int jj = p.qj + dj;
+    if (!inside(jj, n)) continue;
+    const int row = qa.base + __mul24(qa.cj, jj);
+    const int ia = p.qi, ib = ia + 1;
+    const float a = inside(ia, n) ? X[row + __mul24(qa.ci, ia)] : 0.0f;
+    const float b = inside(ib, n) ? X[row + __mul24(qa.ci, ib)] : 0.0f;
+    v += (dj ? p.fj : 1.0f - p.fj) * ((1.0f - p.fi) * a + p.fi * b);
+  }
+  return v;
+}
+
+// (B^T Y)(qi, qj): the sum over the output pixels p whose sample uses
+// (qi, qj), i.e. |s(p) - q| < 1 on both axes.  Those p lie within sqrt(2) of
+// R(phi)(q - c) + c for |phi| <= pi/4, so the 3 x 3 pixels around its
+// rounding cover them; each weight is recomputed from the tables exactly as
+// the forward computes it.  cs = (cos phi, sin phi), c = (n - 1) / 2.
+__device__ __forceinline__ float bil_adj_px(const float* Y, int n, int S, const ViewTab& t,
+                                            float2 cs, float c, int qi, int qj) {
+  const float u = (float)qi - c, v = (float)qj - c;
+  const int pi0 = __float2int_rn(c + cs.x * u - cs.y * v);
+  const int pj0 = __float2int_rn(c + cs.y * u + cs.x * v);
+  float acc = 0.0f;
+#pragma unroll
+  for (int dj = -1; dj <= 1; ++dj) {
+    const int pj = pj0 + dj;
+    if (!inside(pj, n)) continue;
+#pragma unroll
+    for (int di = -1; di <= 1; ++di) {
+      const int pi = pi0 + di;
+      if (!inside(pi, n)) continue;
+      const BilPos p = bil_pos(t, pi, pj);
+      const float wi = qi == p.qi ? 1.0f - p.fi : (qi == p.qi + 1 ? p.fi : 0.0f);
+      const float wj = qj == p.qj ? 1.0f - p.fj : (qj == p.qj + 1 ? p.fj : 0.0f);
+      acc += wj * (wi * Y[pj * S + pi]);
+    }
+  }
+  return acc;
+}
+
 // In-place pass over the lines a wave owns: each line is read completely
 // (every lane's taps) before any lane writes it, so no workgroup barrier is
 // needed inside the pass; EPL values per lane are held in registers.
@@ -182,6 +253,21 @@ __device__ __forceinline__ void rotate_into(float* Y, const float* X, int n, int
   }
 }
 
+// Bilinear R_l X into Y.  Ends with Y complete (barrier).
+template <int EPL>
+__device__ __forceinline__ void bil_into(float* Y, const float* X, int n, int S, int SX, int m,
+                                         const ViewTab& t) {
+  const QAddr qa = quarter_addr(m, n, SX);
+  const int lane = lane_id();
+  for (int j = wave_id(); j < n; j += NW)
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      const int i = lane + 64 * e;
+      if (i < n) Y[j * S + i] = bil_px(X, n, qa, t, i, j);
+    }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------- Eq. (1)
 // Column suffix scan of a rotated attenuation slice in Y (detector beyond
 // j = n-1): kScanSeg threads per column each own a run of rows; run sums in
@@ -214,7 +300,7 @@ __device__ void mubar_scan(float* Y, double* seg, int n, int S, double dy) {
 // kGlobal (slices larger than LDS allows): the source slice is read in place
 // from mu and the working slice Y is the workgroup's own slice of `scratch`
 // (L2-resident); the scan segments and tables stay in LDS.
-template <int EPL, bool kGlobal>
+template <int EPL, bool kGlobal, bool kBil>
 __global__ __launch_bounds__(NT) void mubar_kernel(const float* __restrict__ mu,
                                                    float* __restrict__ out, int n, int nz,
                                                    int view0, int nviews, int VG, int out_view0,
@@ -247,7 +333,8 @@ __global__ __launch_bounds__(NT) void mubar_kernel(const float* __restrict__ mu,
     __syncthreads();                                   // X staged / previous view written out
     load_tab(tab, l, n, t);
     __syncthreads();
-    rotate_into<true, EPL>(Y, X, n, S, SX, tab.quarter[l], t);
+    if (kBil) bil_into<EPL>(Y, X, n, S, SX, tab.quarter[l], t);
+    else rotate_into<true, EPL>(Y, X, n, S, SX, tab.quarter[l], t);
     mubar_scan(Y, seg, n, S, dy);
     float* dst = out + ((size_t)(l - out_view0) * nz + k) * nn;
     for (int p = threadIdx.x; p < n * n; p += NT) {
@@ -318,7 +405,7 @@ __device__ __forceinline__ float rotated_pixel(const float* X, int n, const QAdd
 // tiles per wave, visited kCh at a time.
 constexpr int kCh = 4;
 // kGlobal: the slice is gathered in place from x (L2-resident), no staging.
-template <int RM, bool kGlobal>
+template <int RM, bool kGlobal, bool kBil>
 __global__ __launch_bounds__(NT) void rot_fwd_kernel(const float* __restrict__ x,
                                                      const float* __restrict__ mb, int mb_off,
                                                      float* __restrict__ W, int n, int nz,
@@ -368,7 +455,8 @@ __global__ __launch_bounds__(NT) void rot_fwd_kernel(const float* __restrict__ x
       for (int c = 0; c < kCh; ++c) {
         int i, j;
         if (r0 + c < RM && tile_pixel(n, tpr, rtpr, r0 + c, i, j))
-          dst[j * n + i] = rotated_pixel(X, n, qa, t, i, j) * att[c];
+          dst[j * n + i] =
+              (kBil ? bil_px(X, n, qa, t, i, j) : rotated_pixel(X, n, qa, t, i, j)) * att[c];
       }
 #pragma unroll
       for (int c = 0; c < kCh; ++c) att[c] = nxt[c];
@@ -382,7 +470,7 @@ __global__ __launch_bounds__(NT) void rot_fwd_kernel(const float* __restrict__ x
 // Output pixel (i, j) accumulates in wave j mod NW, lane i mod 64.
 // kGlobal: the working slice Y is the workgroup's own slice of `scratch`.
 constexpr int kStageRows = 4;
-template <int EPL, int LPW, bool kGlobal>
+template <int EPL, int LPW, bool kGlobal, bool kBil>
 __global__ __launch_bounds__(NT) void rot_back_kernel(const float* __restrict__ U,
                                                       const float* __restrict__ mb, int mb_off,
                                                       float* __restrict__ partial, int n, int nz,
@@ -429,10 +517,14 @@ __global__ __launch_bounds__(NT) void rot_back_kernel(const float* __restrict__ 
       }
     }
     __syncthreads();
-    line_pass<-1, true, EPL>(Y, n, S, t);              // pass 3 transpose
-    __syncthreads();
-    line_pass<-1, false, EPL>(Y, n, S, t);             // pass 2 transpose
-    __syncthreads();
+    if (!kBil) {
+      line_pass<-1, true, EPL>(Y, n, S, t);            // pass 3 transpose
+      __syncthreads();
+      line_pass<-1, false, EPL>(Y, n, S, t);           // pass 2 transpose
+      __syncthreads();
+    }
+    const float2 cs = tab.rot[l];
+    const float cc = 0.5f * (float)(n - 1);
     if (kGlobal) {
       // large slices: accumulate in this workgroup's own slice of `partial`
       // (each pixel has one owner lane, so the order of additions is fixed)
@@ -447,7 +539,8 @@ __global__ __launch_bounds__(NT) void rot_back_kernel(const float* __restrict__ 
           if (j < n && i < n) {
             int di, dj;
             quarter_dst(m, n, i, j, di, dj);
-            const float val = row_px<-1>(Y, n, S, t, di, dj);
+            const float val = kBil ? bil_adj_px(Y, n, S, t, cs, cc, di, dj)
+                                   : row_px<-1>(Y, n, S, t, di, dj);
             const float prev = (first && !accumulate) ? 0.0f : dst[j * n + i];
             dst[j * n + i] = prev + val;
           }
@@ -464,7 +557,8 @@ __global__ __launch_bounds__(NT) void rot_back_kernel(const float* __restrict__ 
         if (j < n && i < n) {
           int di, dj;
           quarter_dst(m, n, i, j, di, dj);             // x(i, j) = h(P_m position)
-          acc[r][e] += row_px<-1>(Y, n, S, t, di, dj);
+          acc[r][e] += kBil ? bil_adj_px(Y, n, S, t, cs, cc, di, dj)
+                            : row_px<-1>(Y, n, S, t, di, dj);
         }
       }
     }
@@ -542,11 +636,15 @@ hipError_t launch_mubar(const Plan& p, float* out, int view0, int nviews, int ou
   const int VG = kRotViewsPerGroup;
   dim3 grid(p.g.nz, (nviews + VG - 1) / VG);
   return with_shape(n, [&](auto E, auto, auto G) {
-    hipError_t e = set_smem((const void*)mubar_kernel<E.value, G.value>, sm);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((mubar_kernel<E.value, G.value>), grid, dim3(NT), sm, s, p.mu, out, n,
-                       p.g.nz, view0, nviews, VG, out_view0, p.tab, p.g.dy, p.rot_scratch);
-    return hipGetLastError();
+    auto go = [&](auto B) {
+      hipError_t e = set_smem((const void*)mubar_kernel<E.value, G.value, B.value>, sm);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((mubar_kernel<E.value, G.value, B.value>), grid, dim3(NT), sm, s, p.mu,
+                         out, n, p.g.nz, view0, nviews, VG, out_view0, p.tab, p.g.dy,
+                         p.rot_scratch);
+      return hipGetLastError();
+    };
+    return p.bilinear ? go(std::true_type()) : go(std::false_type());
   });
 }
 
@@ -558,11 +656,14 @@ hipError_t launch_rot_fwd(const Plan& p, const float* x, const float* mb, int mb
   const int VG = kRotViewsPerGroup;
   dim3 grid(p.g.nz, (nvb + VG - 1) / VG);
   auto go = [&](auto RM, auto G) {
-    hipError_t e = set_smem((const void*)rot_fwd_kernel<RM.value, G.value>, sm);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((rot_fwd_kernel<RM.value, G.value>), grid, dim3(NT), sm, s, x, mb, mb_off, W,
-                       n, p.g.nz, view0, nvb, VG, p.tab);
-    return hipGetLastError();
+    auto run = [&](auto B) {
+      hipError_t e = set_smem((const void*)rot_fwd_kernel<RM.value, G.value, B.value>, sm);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((rot_fwd_kernel<RM.value, G.value, B.value>), grid, dim3(NT), sm, s, x,
+                         mb, mb_off, W, n, p.g.nz, view0, nvb, VG, p.tab);
+      return hipGetLastError();
+    };
+    return p.bilinear ? run(std::true_type()) : run(std::false_type());
   };
   // 8x8 tiles per wave: ceil(ceil(n/8)^2 / NW)
   using std::integral_constant;
@@ -579,12 +680,15 @@ hipError_t launch_rot_back(const Plan& p, const float* U, const float* mb, int m
   const bool glob = n > kMaxLdsN;
   const size_t sm = glob ? tab_bytes(n) : (size_t)round4(n * slice_stride(n)) * 4 + tab_bytes(n);
   return with_shape(n, [&](auto E, auto L, auto G) {
-    hipError_t e = set_smem((const void*)rot_back_kernel<E.value, L.value, G.value>, sm);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((rot_back_kernel<E.value, L.value, G.value>), dim3(p.g.nz, kBackGroups),
-                       dim3(NT), sm, s, U, mb, mb_off, partial, n, p.g.nz, view0, nvb, kBackGroups,
-                       accumulate ? 1 : 0, p.tab, p.rot_scratch);
-    return hipGetLastError();
+    auto go = [&](auto B) {
+      hipError_t e = set_smem((const void*)rot_back_kernel<E.value, L.value, G.value, B.value>, sm);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((rot_back_kernel<E.value, L.value, G.value, B.value>),
+                         dim3(p.g.nz, kBackGroups), dim3(NT), sm, s, U, mb, mb_off, partial, n,
+                         p.g.nz, view0, nvb, kBackGroups, accumulate ? 1 : 0, p.tab, p.rot_scratch);
+      return hipGetLastError();
+    };
+    return p.bilinear ? go(std::true_type()) : go(std::false_type());
   });
 }
 

@@ -18,7 +18,7 @@ static spect_status validate(const spect_geom* g) {
   if (g->nx != g->ny) return SPECT_ERR_SHAPE;              // rotation about z needs a square slice
   if ((g->px & 1) == 0 || (g->pz & 1) == 0) return SPECT_ERR_SHAPE;  // centred odd kernels
   if (!(std::isfinite(g->dy) && g->dy > 0.0)) return SPECT_ERR_VALUE;
-  if (g->flags & ~SPECT_CACHE_MUBAR) return SPECT_ERR_VALUE;
+  if (g->flags & ~(SPECT_CACHE_MUBAR | SPECT_ROT_BILINEAR)) return SPECT_ERR_VALUE;
   if (g->view_batch < 0) return SPECT_ERR_VALUE;
   if (g->conv_precision != SPECT_CONV_FP32 && g->conv_precision != SPECT_CONV_BF16 &&
       g->conv_precision != SPECT_CONV_FP16 && g->conv_precision != SPECT_CONV_BF16X3)
@@ -47,8 +47,9 @@ spect_status compute_layout(const spect_geom& g, Layout* lay, int* view_batch, i
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t at = off; off += align256(bytes); return at; };
   lay->tables_quarter = take((size_t)g.nview * sizeof(int32_t));
-  lay->tables_off = take((size_t)g.nview * 2 * n * sizeof(int32_t));
+  lay->tables_off = take((size_t)g.nview * 2 * n * 2 * sizeof(int32_t));
   lay->tables_w = take((size_t)g.nview * 2 * n * sizeof(float2));
+  lay->tables_rot = take((size_t)g.nview * sizeof(float2));
   lay->vol_batch = take((size_t)vb * N * sizeof(float));
   const int maxc = nc > kMaxChunks ? nc : kMaxChunks;
   lay->fwd_partial = take((size_t)maxc * vb * g.nz * g.nx * sizeof(float));
@@ -82,24 +83,47 @@ static void split_view(const spect_geom& g, int l, int* m, double* phi) {
   *m = (int)(((M % 4) + 4) % 4);
 }
 
-static void fill_tables(const spect_geom& g, int32_t* q, int32_t* off, float2* w) {
+// Integer part and fraction of v, the fraction in [0, 1) after rounding to float.
+static void split_pos(double v, int32_t* ip, float* frac) {
+  double fl = std::floor(v);
+  float f = (float)(v - fl);
+  if (f >= 1.0f) { f = 0.0f; fl += 1.0; }
+  *ip = (int32_t)fl;
+  *frac = f;
+}
+
+static void fill_tables(const spect_geom& g, int32_t* q, int32_t* off, float2* w, float2* rot) {
   const int n = g.nx;
   const double c = (n - 1) / 2.0;
+  const bool bil = (g.flags & SPECT_ROT_BILINEAR) != 0;
   for (int l = 0; l < g.nview; ++l) {
     int m;
     double phi;
     split_view(g, l, &m, &phi);
     q[l] = m;
-    const double t = std::tan(phi / 2.0), s = std::sin(phi);
+    rot[l] = make_float2((float)std::cos(phi), (float)std::sin(phi));
+    const double t = std::tan(phi / 2.0), s = std::sin(phi), co = std::cos(phi);
     for (int r = 0; r < n; ++r) {
-      const double d13 = t * ((double)r - c);    // passes 1, 3: shift along i for row j = r
-      const double d2 = -s * ((double)r - c);    // pass 2: shift along j for column i = r
-      const double ds[2] = {d13, d2};
+      const double u = (double)r - c;
       for (int ps = 0; ps < 2; ++ps) {
-        const double fl = std::floor(ds[ps]);
-        const double f = ds[ps] - fl;
-        off[((size_t)l * 2 + ps) * n + r] = (int32_t)fl;
-        w[((size_t)l * 2 + ps) * n + r] = make_float2((float)(1.0 - f), (float)f);
+        const size_t e = ((size_t)l * 2 + ps) * n + r;
+        if (bil) {
+          // ps 0: row term (index j = r), ps 1: column term (index i = r)
+          const double ti = ps == 0 ? s * u : c + co * u;
+          const double tj = ps == 0 ? c + co * u : -s * u;
+          float fi, fj;
+          split_pos(ti, &off[2 * e], &fi);
+          split_pos(tj, &off[2 * e + 1], &fj);
+          w[e] = make_float2(fi, fj);
+        } else {
+          // passes 1, 3: shift along i for row j = r; pass 2: shift along j for column i = r
+          const double d = ps == 0 ? t * u : -s * u;
+          const double fl = std::floor(d);
+          const double f = d - fl;
+          off[2 * e] = (int32_t)fl;
+          off[2 * e + 1] = 0;
+          w[e] = make_float2((float)(1.0 - f), (float)f);
+        }
       }
     }
   }
@@ -181,23 +205,29 @@ spect_status spect_plan_create(spect_plan* out, const spect_geom* g, const float
   p->lay = lay;
   const size_t n = (size_t)g->nx;
   p->h_quarter = static_cast<int32_t*>(std::malloc(g->nview * sizeof(int32_t)));
-  p->h_off = static_cast<int32_t*>(std::malloc(g->nview * 2 * n * sizeof(int32_t)));
+  p->h_off = static_cast<int32_t*>(std::malloc(g->nview * 2 * n * 2 * sizeof(int32_t)));
   p->h_w = static_cast<float2*>(std::malloc(g->nview * 2 * n * sizeof(float2)));
-  if (!p->h_quarter || !p->h_off || !p->h_w) {
+  p->h_rot = static_cast<float2*>(std::malloc(g->nview * sizeof(float2)));
+  if (!p->h_quarter || !p->h_off || !p->h_w || !p->h_rot) {
     spect_plan_destroy(reinterpret_cast<spect_plan>(p));
     return SPECT_ERR_HIP;
   }
-  fill_tables(*g, p->h_quarter, p->h_off, p->h_w);
+  p->bilinear = (g->flags & SPECT_ROT_BILINEAR) != 0;
+  fill_tables(*g, p->h_quarter, p->h_off, p->h_w, p->h_rot);
   p->tab.quarter = reinterpret_cast<const int32_t*>(p->ws + lay.tables_quarter);
   p->tab.off = reinterpret_cast<const int32_t*>(p->ws + lay.tables_off);
   p->tab.w = reinterpret_cast<const float2*>(p->ws + lay.tables_w);
+  p->tab.rot = reinterpret_cast<const float2*>(p->ws + lay.tables_rot);
   hipError_t e = hipMemcpyAsync(p->ws + lay.tables_quarter, p->h_quarter,
                                 g->nview * sizeof(int32_t), hipMemcpyHostToDevice, stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(p->ws + lay.tables_off, p->h_off, g->nview * 2 * n * sizeof(int32_t),
+    e = hipMemcpyAsync(p->ws + lay.tables_off, p->h_off, g->nview * 2 * n * 2 * sizeof(int32_t),
                        hipMemcpyHostToDevice, stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(p->ws + lay.tables_w, p->h_w, g->nview * 2 * n * sizeof(float2),
+                       hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->ws + lay.tables_rot, p->h_rot, g->nview * sizeof(float2),
                        hipMemcpyHostToDevice, stream);
   p->mubar = nullptr;
   p->mubar_batch = nullptr;
@@ -252,6 +282,7 @@ spect_status spect_plan_destroy(spect_plan plan) {
   std::free(p->h_quarter);
   std::free(p->h_off);
   std::free(p->h_w);
+  std::free(p->h_rot);
   delete p;
   return SPECT_OK;
 }

@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libspect.so")
 
 SPECT_OK = 0
 SPECT_CACHE_MUBAR = 0x1
+SPECT_ROT_BILINEAR = 0x2
+ROTATIONS = {"3pass": 0, "bilinear": SPECT_ROT_BILINEAR}
 SPECT_CONV_FP32, SPECT_CONV_BF16, SPECT_CONV_FP16, SPECT_CONV_BF16X3 = 0, 1, 2, 3
 PRECISIONS = {"fp32": SPECT_CONV_FP32, "bf16": SPECT_CONV_BF16, "fp16": SPECT_CONV_FP16,
               "bf16x3": SPECT_CONV_BF16X3}
@@ -210,7 +212,7 @@ class Plan:
     """
 
     def __init__(self, mu, psf, dy, angles=None, cache_mubar=False, view_batch=0,
-                 precision="fp32"):
+                 precision="fp32", rotation="3pass"):
         import torch
         self.device = mu.device
         if self.device.type != "cuda":
@@ -223,7 +225,10 @@ class Plan:
         _check(psf, (nview, ny, pz, px), "psf", self.device)
         self.shape = (nx, ny, nz, nview, px, pz)
         self.nx, self.ny, self.nz, self.nview, self.px, self.pz = self.shape
-        flags = SPECT_CACHE_MUBAR if cache_mubar else 0
+        if rotation not in ROTATIONS:
+            raise ValueError(f"rotation must be one of {sorted(ROTATIONS)}")
+        self.rotation = rotation
+        flags = (SPECT_CACHE_MUBAR if cache_mubar else 0) | ROTATIONS[rotation]
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
         self.precision = precision

@@ -45,6 +45,7 @@ def test_status_strings():
     (dict(dy=0.0), 3),
     (dict(dy=float("nan")), 3),
     (dict(flags=0x10), 3),
+    (dict(flags=0x4), 3),
     (dict(view_batch=-1), 3),
     (dict(nx=300, ny=300), 5),        # in-plane size above the largest supported (256)
 ])
@@ -55,6 +56,14 @@ def test_workspace_bytes_validation(kw, status):
     with pytest.raises(spect.SpectError) as e:
         spect.spect_workspace_bytes(g)
     assert e.value.status == status
+
+
+def test_rotation_flag_accepted_with_the_same_workspace():
+    """SPECT_ROT_BILINEAR only changes the rotation tables' meaning: the
+    workspace is the same size, alone and with the attenuation cache."""
+    ws = lambda f: spect.spect_workspace_bytes(spect.make_geom(32, 32, 20, 16, 7, 7, 1.0, flags=f)[0])
+    assert ws(spect.SPECT_ROT_BILINEAR) == ws(0)
+    assert ws(spect.SPECT_ROT_BILINEAR | spect.SPECT_CACHE_MUBAR) == ws(spect.SPECT_CACHE_MUBAR)
 
 
 def test_nonfinite_angle_rejected():
