@@ -189,20 +189,30 @@ __device__ __forceinline__ float bil_px(const float* X, int n, const QAddr& qa, 
 __device__ __forceinline__ float bil_adj_px(const float* Y, int n, int S, const ViewTab& t,
                                             float2 cs, float c, int qi, int qj) {
   const float u = (float)qi - c, v = (float)qj - c;
-  const int pi0 = __float2int_rn(c + cs.x * u - cs.y * v);
-  const int pj0 = __float2int_rn(c + cs.y * u + cs.x * v);
+  const int pi0 = __float2int_rn(c + cs.x * u - cs.y * v) - 1;
+  const int pj0 = __float2int_rn(c + cs.y * u + cs.x * v) - 1;
+  // the three column and three row terms of the candidates, loaded once;
+  // outside the grid a candidate gets an entry that can never hit q
+  TabEntry ca[3], rb[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int pi = pi0 + d, pj = pj0 + d;
+    ca[d] = inside(pi, n) ? t.e2[pi] : TabEntry{make_float2(0.0f, 0.0f), -4 * n, 0};
+    rb[d] = inside(pj, n) ? t.e13[pj] : TabEntry{make_float2(0.0f, 0.0f), 0, -4 * n};
+  }
   float acc = 0.0f;
 #pragma unroll
-  for (int dj = -1; dj <= 1; ++dj) {
-    const int pj = pj0 + dj;
-    if (!inside(pj, n)) continue;
+  for (int dj = 0; dj < 3; ++dj) {
+    const int pj = min(max(pj0 + dj, 0), n - 1);          // address only; weight 0 outside
 #pragma unroll
-    for (int di = -1; di <= 1; ++di) {
-      const int pi = pi0 + di;
-      if (!inside(pi, n)) continue;
-      const BilPos p = bil_pos(t, pi, pj);
-      const float wi = qi == p.qi ? 1.0f - p.fi : (qi == p.qi + 1 ? p.fi : 0.0f);
-      const float wj = qj == p.qj ? 1.0f - p.fj : (qj == p.qj + 1 ? p.fj : 0.0f);
+    for (int di = 0; di < 3; ++di) {
+      const int pi = min(max(pi0 + di, 0), n - 1);
+      int ri = ca[di].o + rb[dj].o, rj = ca[di].pad + rb[dj].pad;
+      float fi = ca[di].w.x + rb[dj].w.x, fj = ca[di].w.y + rb[dj].w.y;
+      if (fi >= 1.0f) { fi -= 1.0f; ++ri; }
+      if (fj >= 1.0f) { fj -= 1.0f; ++rj; }
+      const float wi = qi == ri ? 1.0f - fi : (qi == ri + 1 ? fi : 0.0f);
+      const float wj = qj == rj ? 1.0f - fj : (qj == rj + 1 ? fj : 0.0f);
       acc += wj * (wi * Y[pj * S + pi]);
     }
   }
