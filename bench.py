@@ -39,15 +39,17 @@ def parse():
                     help="1: keep the Eq. (1) attenuation factor of all views in HBM (plan flag)")
     ap.add_argument("--em-recons", type=int, default=5, help="EM reconstructions timed for latency")
     ap.add_argument("--em-iters", type=int, default=8, help="EM iterations per reconstruction")
-    ap.add_argument("--cpu-views", type=int, default=24,
+    ap.add_argument("--cpu-views", type=int, default=128,
                     help="views in the bounded oracle sample (0 disables the CPU baseline)")
     ap.add_argument("--grad-iters", type=int, default=10,
                     help="unrolled EM iterations differentiated end to end (0 disables)")
     ap.add_argument("--precision-steps", type=int, default=10,
                     help="pairs timed for each reduced-precision (BF16, FP16) convolution plan (0 disables)")
+    ap.add_argument("--bilinear-steps", type=int, default=10,
+                    help="timed pairs of the FP32 pair with 2-D bilinear rotation (0: skip)")
     ap.add_argument("--large-steps", type=int, default=3,
                     help="pairs timed per precision on the 256x256x160 precision workload (0 disables)")
-    ap.add_argument("--serve-requests", type=int, default=48,
+    ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests in the continuous-batching serving trace (0 disables)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="mean arrivals per second")
     ap.add_argument("--serve-slots", type=int, default=4, help="concurrent requests at most")
@@ -118,11 +120,19 @@ def cpu_baseline(x, mu, psf, dy, nviews_sample, seed):
     oracle.back(y, mu, psf, g, views=views, conv="fft")
     dt = time.perf_counter() - t0
     sec_per_pair = dt * nview / len(views)
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": 1.0 / sec_per_pair, "unit": "pairs/s", "cores": cores, "kind": "oracle",
             "sample": f"FP64 oracle (numpy + scipy.fft, FFT convolution) forward+back of "
                       f"{len(views)} of {nview} views at {nx}x{ny}x{nz}, {px}x{pz} PSF, "
-                      f"{dt:.1f} s, scaled to a full pair",
-            "seconds_per_pair": sec_per_pair}
+                      f"{dt:.1f} s" + (", scaled to a full pair" if len(views) < nview else ""),
+            "seconds_per_pair": sec_per_pair, "cpu_model": model}
 
 
 def main():
@@ -262,6 +272,37 @@ def main():
             }
             pl.close()
             del pl, v2, b2
+
+    # The same FP32 pair with 2-D bilinear rotation (SPECT_ROT_BILINEAR), the
+    # alternative rotation the paper implements and times (not part of
+    # `value`; a different operator, so its distance from the 3-pass pair is
+    # the difference between the two interpolations, not an error).
+    bil = None
+    if args.bilinear_steps > 0:
+        pl = spect.Plan(mud, psfd, dy, cache_mubar=bool(args.cache_mubar), rotation="bilinear")
+        v2 = torch.empty_like(vd)
+        b2 = torch.empty_like(bd)
+        for _ in range(args.warmup):
+            pl.forward(xd, out=v2)
+            pl.back(v2, out=b2)
+        torch.cuda.synchronize()
+        pl.profile_start(max_launches=64 * args.bilinear_steps + 64)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.bilinear_steps):
+            pl.forward(xd, out=v2)
+            pl.back(v2, out=b2)
+        b.record()
+        torch.cuda.synchronize()
+        kt = pl.profile_stop()
+        ms = a.elapsed_time(b) / args.bilinear_steps
+        pl.forward(xd, out=v2)
+        torch.cuda.synchronize()
+        bil = {"pairs_per_s": 1000.0 / ms, "ms_per_pair": ms,
+               "rel_l2_forward_vs_3pass": float((v2.double() - vd.double()).norm() / vd.double().norm()),
+               "kernels_ms_per_launch": {k: v["total_ms"] / v["launches"] for k, v in kt.items()}}
+        pl.close()
+        del pl, v2, b2
 
     # The precision workload: 256x256x160, 128 views, 37x37 PSFs, the pair and
     # a 10-iteration EM image in FP32, BF16 and FP16 (not part of `value`).
@@ -403,6 +444,7 @@ def main():
         "em_recon_latency": em,
         "unrolled_em_grad": grad,
         "reduced_precision": lp,
+        "bilinear_rotation": bil,
         "large_precision": large,
         "serving": serving,
         "kernels_ms_per_launch": avg_ms,
