@@ -85,6 +85,13 @@ typedef enum {
                                    the exact quarter turn, out(p) = bilinear sample at
                                    R(phi)^-1 (p - c) + c; spect_back applies its exact
                                    transpose.  Default: three 1-D shears. */
+#define SPECT_PSF_SEPARABLE 0x4u /* the PSFs are separable (rank 1), p[b][a] = fz[b] fx[a]
+                                    (an axis-aligned 2-D Gaussian fit is): d_psf then holds
+                                    the factors, [nview][ny][pz + px] with the pz values of
+                                    fz first, and the convolution runs as two 1-D passes
+                                    (2 (px + pz) instead of 2 px pz FLOP per voxel).  FP32
+                                    only: with another conv_precision, or a strip that does
+                                    not fit the kernel's LDS, SPECT_ERR_UNSUPPORTED. */
 
 /* Geometry of one plan (host struct, copied by spect_plan_create). */
 typedef struct {
@@ -95,8 +102,8 @@ typedef struct {
   const double* angles;   /* host array of nview angles in radians, or NULL for
                              theta_l = 2 pi l / nview (Sec. II-A); read only
                              during spect_plan_create */
-  uint32_t flags;         /* SPECT_CACHE_MUBAR | SPECT_ROT_BILINEAR, or 0; other
-                             bits give SPECT_ERR_VALUE */
+  uint32_t flags;         /* SPECT_CACHE_MUBAR | SPECT_ROT_BILINEAR | SPECT_PSF_SEPARABLE,
+                             or 0; other bits give SPECT_ERR_VALUE */
   int32_t view_batch;     /* views processed per internal batch; 0 = all.
                              Smaller batches need less workspace. */
   int32_t conv_precision; /* SPECT_CONV_FP32 (0), SPECT_CONV_BF16, SPECT_CONV_FP16 or
@@ -109,7 +116,8 @@ typedef struct {
 spect_status spect_workspace_bytes(const spect_geom* g, size_t* bytes);
 
 /* Create a plan.  d_mu: [nz][ny][nx] attenuation map (units of 1/dy),
- * d_psf: [nview][ny][pz][px], d_workspace: device memory of ws_bytes
+ * d_psf: [nview][ny][pz][px] (with SPECT_PSF_SEPARABLE: [nview][ny][pz + px],
+ * the z factor then the x factor), d_workspace: device memory of ws_bytes
  * (>= spect_workspace_bytes, 256-byte aligned).  All three are borrowed.
  * Enqueues the upload of the per-view shear tables (and, with
  * SPECT_CACHE_MUBAR, the attenuation-factor precomputation) on `stream`. */

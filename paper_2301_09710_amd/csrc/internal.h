@@ -59,6 +59,16 @@ struct M4Shape {
   bool ok;              // the tiling fits the kernels' register and LDS budgets
 };
 
+// Tiling of the separable (rank-1) PSF convolution (see conv_sep.hip).
+struct SepShape {
+  int nx, ny, nz, px, pz, ha, hb;
+  int NBx, NBz;         // tap counts rounded up to 4
+  int nx4;              // nx rounded up to 4
+  int ZS, nstrip;       // output rows (z) per workgroup strip, strips per plane
+  int nchunk, nchunk_back;
+  bool ok;              // the strips fit LDS and the forward's register-held outputs
+};
+
 // Tiling of the BF16 / FP16 convolution (see conv_lp.hip).
 constexpr int kLpMaxWaves = 8;   // M-blocks (16 z each) per workgroup tile at most
 struct LpShape {
@@ -141,6 +151,8 @@ struct Plan {
   ConvShape conv;
   M4Shape m4;           // FP32 convolution on 4x4 blocks, used when use_m4
   bool use_m4;
+  bool separable;       // SPECT_PSF_SEPARABLE: psf holds the two 1-D factors per plane
+  SepShape sep;
   int conv_precision;   // SPECT_CONV_FP32 / _BF16 / _FP16
   LpShape lp;           // tiling of the reduced-precision convolution
   Profiler* prof;       // non-null while spect_profile_start is active
@@ -179,6 +191,9 @@ M4Shape make_m4_shape(const spect_geom& g);
 // Whether the 4x4-block tiling issues fewer matrix-core cycles than the 16x16 one.
 bool m4_preferred(const M4Shape& s, const ConvShape& cs);
 void tune_m4_chunks(M4Shape& s, int views);
+SepShape make_sep_shape(const spect_geom& g);
+size_t sep_lds_bytes(const SepShape& s, bool back);
+void tune_sep_chunks(SepShape& s, int views);
 LpShape make_lp_shape(const spect_geom& g);
 size_t lp_lds_bytes(const LpShape& s, bool split);
 bool lp_supported(const spect_geom& g);
@@ -197,6 +212,8 @@ hipError_t launch_conv_back_mfma(const Plan& p, const float* v, float* U, int vi
                                  hipStream_t s);
 hipError_t launch_conv_m4(const Plan& p, bool back, const float* in, float* out, int view0,
                           int nvb, hipStream_t s);
+hipError_t launch_conv_sep(const Plan& p, bool back, const float* in, float* out, int view0,
+                           int nvb, hipStream_t s);
 hipError_t launch_conv_back_edges(const Plan& p, const float* v, float* U, int view0, int nvb,
                                   hipStream_t s);
 hipError_t launch_conv_fwd(const Plan& p, const float* W, float* partial, int view0, int nvb,

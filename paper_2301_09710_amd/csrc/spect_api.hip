@@ -18,7 +18,8 @@ static spect_status validate(const spect_geom* g) {
   if (g->nx != g->ny) return SPECT_ERR_SHAPE;              // rotation about z needs a square slice
   if ((g->px & 1) == 0 || (g->pz & 1) == 0) return SPECT_ERR_SHAPE;  // centred odd kernels
   if (!(std::isfinite(g->dy) && g->dy > 0.0)) return SPECT_ERR_VALUE;
-  if (g->flags & ~(SPECT_CACHE_MUBAR | SPECT_ROT_BILINEAR)) return SPECT_ERR_VALUE;
+  if (g->flags & ~(SPECT_CACHE_MUBAR | SPECT_ROT_BILINEAR | SPECT_PSF_SEPARABLE))
+    return SPECT_ERR_VALUE;
   if (g->view_batch < 0) return SPECT_ERR_VALUE;
   if (g->conv_precision != SPECT_CONV_FP32 && g->conv_precision != SPECT_CONV_BF16 &&
       g->conv_precision != SPECT_CONV_FP16 && g->conv_precision != SPECT_CONV_BF16X3)
@@ -30,9 +31,14 @@ static spect_status validate(const spect_geom* g) {
   // index arithmetic inside a plane / slice uses 32-bit ints
   if ((int64_t)g->nx * g->nz > (1 << 30) || (int64_t)g->px * g->pz > (1 << 20))
     return SPECT_ERR_UNSUPPORTED;
-  // the reduced-precision convolution needs its LDS tiles and the FP32 edge fold
-  if (g->conv_precision != SPECT_CONV_FP32 && !(lp_supported(*g) && conv_mfma_supported(*g)))
+  if (g->flags & SPECT_PSF_SEPARABLE) {
+    // separable PSFs: FP32 1-D passes only
+    if (g->conv_precision != SPECT_CONV_FP32 || !make_sep_shape(*g).ok) return SPECT_ERR_UNSUPPORTED;
+  } else if (g->conv_precision != SPECT_CONV_FP32 &&
+             !(lp_supported(*g) && conv_mfma_supported(*g))) {
+    // the reduced-precision convolution needs its LDS tiles and the FP32 edge fold
     return SPECT_ERR_UNSUPPORTED;
+  }
   return SPECT_OK;
 }
 
@@ -236,7 +242,13 @@ spect_status spect_plan_create(spect_plan* out, const spect_geom* g, const float
   p->conv = make_conv_shape(*g, kFwdJChunk, kBackJChunk);
   p->m4 = make_m4_shape(*g);
   p->use_m4 = false;
-  if (p->use_mfma) {
+  p->separable = (g->flags & SPECT_PSF_SEPARABLE) != 0;
+  if (p->separable) {
+    p->use_mfma = false;
+    p->sep = make_sep_shape(*g);
+    tune_sep_chunks(p->sep, g->nview);
+    p->nchunk = p->sep.nchunk;
+  } else if (p->use_mfma) {
     tune_conv_chunks(p->conv, g->nview);   // independent of view_batch: same sums
     p->nchunk = p->conv.nchunk;          // forward partial sums per view
     // SPECT_FP32_TILING = "4x4" or "16x16" overrides the cost model ("auto")
@@ -317,6 +329,7 @@ static spect_status forward_impl(const Plan& p, const float* x, float* v, hipStr
         p.conv_precision != SPECT_CONV_FP32
             ? timed(p, K_CONV_FWD_LP, s, [&] { return launch_conv_fwd_lp(p, W, part, v0, nvb, s); })
             : timed(p, K_CONV_FWD, s, [&] {
+                if (p.separable) return launch_conv_sep(p, false, W, part, v0, nvb, s);
                 return p.use_mfma ? launch_conv_fwd_mfma(p, W, part, v0, nvb, s)
                                   : launch_conv_fwd(p, W, part, v0, nvb, s);
               });
@@ -337,6 +350,7 @@ static spect_status back_impl(const Plan& p, const float* v, float* x, hipStream
         p.conv_precision != SPECT_CONV_FP32
             ? timed(p, K_CONV_BACK_LP, s, [&] { return launch_conv_back_lp(p, v, U, v0, nvb, s); })
             : timed(p, K_CONV_BACK, s, [&] {
+                if (p.separable) return launch_conv_sep(p, true, v, U, v0, nvb, s);  // folds included
                 return p.use_mfma ? launch_conv_back_mfma(p, v, U, v0, nvb, s)
                                   : launch_conv_back(p, v, U, v0, nvb, s);
               });

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libspect.so")
 SPECT_OK = 0
 SPECT_CACHE_MUBAR = 0x1
 SPECT_ROT_BILINEAR = 0x2
+SPECT_PSF_SEPARABLE = 0x4
 ROTATIONS = {"3pass": 0, "bilinear": SPECT_ROT_BILINEAR}
 SPECT_CONV_FP32, SPECT_CONV_BF16, SPECT_CONV_FP16, SPECT_CONV_BF16X3 = 0, 1, 2, 3
 PRECISIONS = {"fp32": SPECT_CONV_FP32, "bf16": SPECT_CONV_BF16, "fp16": SPECT_CONV_FP16,
@@ -208,7 +209,10 @@ def _check(t, shape, name, device):
 class Plan:
     """A projector plan over torch tensors (borrowed mu / psf, owned workspace).
 
-    x: [nz][ny][nx], v: [nview][nz][nx], mu: [nz][ny][nx], psf: [nview][ny][pz][px].
+    x: [nz][ny][nx], v: [nview][nz][nx], mu: [nz][ny][nx], psf: [nview][ny][pz][px],
+    or for separable PSFs p[b][a] = fz[b] fx[a] the pair (fz, fx) with
+    fz: [nview][ny][pz] and fx: [nview][ny][px] (packed here into the
+    [nview][ny][pz + px] layout of SPECT_PSF_SEPARABLE).
     """
 
     def __init__(self, mu, psf, dy, angles=None, cache_mubar=False, view_batch=0,
@@ -218,17 +222,30 @@ class Plan:
         if self.device.type != "cuda":
             raise ValueError("mu must live on a GPU")
         nz, ny, nx = mu.shape
-        nview, ny2, pz, px = psf.shape
-        if ny2 != ny:
-            raise ValueError("psf depth does not match mu")
+        sep = isinstance(psf, (tuple, list))
+        if sep:
+            fz, fx = psf
+            nview, ny2, pz = fz.shape
+            px = fx.shape[2]
+            if ny2 != ny:
+                raise ValueError("psf depth does not match mu")
+            _check(fz, (nview, ny, pz), "fz", self.device)
+            _check(fx, (nview, ny, px), "fx", self.device)
+            psf = torch.cat([fz, fx], dim=2).contiguous()      # owned by the plan
+        else:
+            nview, ny2, pz, px = psf.shape
+            if ny2 != ny:
+                raise ValueError("psf depth does not match mu")
+            _check(psf, (nview, ny, pz, px), "psf", self.device)
         _check(mu, (nz, ny, nx), "mu", self.device)
-        _check(psf, (nview, ny, pz, px), "psf", self.device)
+        self.separable = sep
         self.shape = (nx, ny, nz, nview, px, pz)
         self.nx, self.ny, self.nz, self.nview, self.px, self.pz = self.shape
         if rotation not in ROTATIONS:
             raise ValueError(f"rotation must be one of {sorted(ROTATIONS)}")
         self.rotation = rotation
-        flags = (SPECT_CACHE_MUBAR if cache_mubar else 0) | ROTATIONS[rotation]
+        flags = ((SPECT_CACHE_MUBAR if cache_mubar else 0) | ROTATIONS[rotation] |
+                 (SPECT_PSF_SEPARABLE if sep else 0))
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
         self.precision = precision

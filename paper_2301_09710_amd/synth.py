@@ -126,6 +126,27 @@ def gaussian_psf(px, pz, ny, nview, sigma_min, sigma_max, view_wobble=0.0):
     return out.astype(np.float32)
 
 
+def gaussian_psf_factors(px, pz, ny, nview, sigma_min, sigma_max, view_wobble=0.0):
+    """The 1-D factors of ``gaussian_psf``: fz [nview][ny][pz] and fx
+    [nview][ny][px], each exp(-t^2 / (2 sigma^2)) normalised to sum 1, so that
+    their outer product fz[b] fx[a] is the normalised 2-D Gaussian."""
+    ha, hb = (px - 1) // 2, (pz - 1) // 2
+    a = np.arange(px) - ha
+    b = np.arange(pz) - hb
+    fz = np.empty((nview, ny, pz), dtype=np.float64)
+    fx = np.empty((nview, ny, px), dtype=np.float64)
+    for l in range(nview):
+        f = 1.0 + view_wobble * np.sin(2 * np.pi * l / nview)
+        for jj in range(ny):
+            t = (ny - 1 - jj) / (ny - 1) if ny > 1 else 0.0
+            s = (sigma_min + (sigma_max - sigma_min) * t) * f
+            gz = np.exp(-(b ** 2) / (2 * s * s))
+            gx = np.exp(-(a ** 2) / (2 * s * s))
+            fz[l, jj] = gz / gz.sum()
+            fx[l, jj] = gx / gx.sum()
+    return fz.astype(np.float32), fx.astype(np.float32)
+
+
 def random_psf(px, pz, ny, nview, seed=0, symmetric=True):
     """Random nonnegative PSFs normalised to sum 1.  ``symmetric`` makes each
     kernel symmetric in both a and b (the paper's adjoint test uses random

@@ -45,7 +45,8 @@ def test_status_strings():
     (dict(dy=0.0), 3),
     (dict(dy=float("nan")), 3),
     (dict(flags=0x10), 3),
-    (dict(flags=0x4), 3),
+    (dict(flags=0x8), 3),
+    (dict(flags=0x4, conv_precision=1), 5),   # separable PSFs: FP32 only
     (dict(view_batch=-1), 3),
     (dict(nx=300, ny=300), 5),        # in-plane size above the largest supported (256)
 ])
