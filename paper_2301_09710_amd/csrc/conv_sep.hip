@@ -15,64 +15,73 @@
 // (only the h + 1 samples nearest the edge contribute) and g[0] = y[0] sum f
 // for n = 1.
 //
-// Both passes use one register-blocked 1-D kernel: a thread computes four
+// Both passes use one register-blocked 1-D kernel: a thread computes eight
 // consecutive outputs out[d] = sum_b g[b] src(r0 + d - b) with the taps in
-// groups of four, reading one new source sample per tap (the four-sample
-// window slides down the source), so every LDS read feeds four FMAs.  Taps
+// groups of four, reading one new source sample per tap (the eight-sample
+// window slides down the source), so every LDS read feeds eight FMAs.  Taps
 // are zero-padded to a multiple of four; the adjoint uses the reversed taps.
 //
 // Work split: a workgroup (512 threads) owns a strip of ZS output rows (z) of
 // one view and a chunk of depth planes.  Forward: per plane, stage the input
-// rows the strip needs (clamped), run the z pass into a column-padded strip,
-// then the x pass, accumulating the depth sum in registers; partial sums per
-// chunk are reduced in a fixed order afterwards.  Adjoint: the projection
-// rows the strip needs are staged once (zero outside); per plane the x pass
-// (and its edge fold) fills an intermediate strip, and the z pass (and its
-// edge fold) writes the plane's output rows.
+// rows the strip needs (clamped; the next plane's rows are loaded into
+// registers meanwhile), run the z pass on the real columns and copy the edge
+// columns into the halo, then the x pass, accumulating the depth sum in
+// registers; partial sums per chunk are reduced in a fixed order afterwards.
+// Adjoint: the projection rows the strip needs are staged once (zero
+// outside); per plane the x pass (and its edge fold) fills an intermediate
+// strip on the rows inside the volume (the others stay zero), and the z pass
+// (and its edge fold) writes the plane's output rows.
 #include "internal.h"
 
 namespace spect {
 namespace {
 
 constexpr int kSepThreads = 512;
-constexpr int kSepQuads = 8;        // output quads per thread held across planes (forward)
+constexpr int kSepOcts = 4;         // output octets per thread held across planes (forward)
 
 __device__ __forceinline__ int clampi(int q, int lo, int hi) { return q < lo ? lo : (q > hi ? hi : q); }
 
-// out[d] += sum_{b < nb4} g[b] * src[(r0 + d - b) * st], d = 0..3; g is in LDS,
-// 16-byte aligned, zero from the real tap count up to nb4 (a multiple of 4).
-// Reads rows r0 - nb4 .. r0 + 3 of src.
-__device__ __forceinline__ void conv4(const float* __restrict__ src, int st, int r0,
-                                      const float* __restrict__ g, int nb4, float (&out)[4]) {
+// out[d] += sum_{b < nb4} g[b] * src[(r0 + d - b) * st], d = 0..D-1; g is in
+// LDS, 16-byte aligned, zero from the real tap count up to nb4 (a multiple of
+// 4).  The window of D source samples slides down by four per tap group, so
+// each group reads four new samples for 4 D FMAs.  Reads rows r0 - nb4 ..
+// r0 + D - 1 of src.
+template <int D>
+__device__ __forceinline__ void convD(const float* __restrict__ src, int st, int r0,
+                                      const float* __restrict__ g, int nb4, float (&out)[D]) {
   const float* s = src + r0 * st;
-  float w0 = s[0], w1 = s[st], w2 = s[2 * st], w3 = s[3 * st];
+  float w[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) w[d] = s[d * st];
+  // the next group's samples and taps are read while this group's FMAs run
+  float nn[4];
+  float4 tn = *reinterpret_cast<const float4*>(g);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) nn[m] = s[-(m + 1) * st];
   for (int b = 0; b < nb4; b += 4) {
-    const float4 t = *reinterpret_cast<const float4*>(g + b);
-    const float* sb = s - b * st;
-    const float n1 = sb[-st], n2 = sb[-2 * st], n3 = sb[-3 * st], n4 = sb[-4 * st];
-    // tap b: rows r0 - b + d = w_d
-    out[0] = fmaf(t.x, w0, out[0]);
-    out[1] = fmaf(t.x, w1, out[1]);
-    out[2] = fmaf(t.x, w2, out[2]);
-    out[3] = fmaf(t.x, w3, out[3]);
-    // tap b + 1: n1, w0, w1, w2
-    out[0] = fmaf(t.y, n1, out[0]);
-    out[1] = fmaf(t.y, w0, out[1]);
-    out[2] = fmaf(t.y, w1, out[2]);
-    out[3] = fmaf(t.y, w2, out[3]);
-    // tap b + 2: n2, n1, w0, w1
-    out[0] = fmaf(t.z, n2, out[0]);
-    out[1] = fmaf(t.z, n1, out[1]);
-    out[2] = fmaf(t.z, w0, out[2]);
-    out[3] = fmaf(t.z, w1, out[3]);
-    // tap b + 3: n3, n2, n1, w0
-    out[0] = fmaf(t.w, n3, out[0]);
-    out[1] = fmaf(t.w, n2, out[1]);
-    out[2] = fmaf(t.w, n1, out[2]);
-    out[3] = fmaf(t.w, w0, out[3]);
-    w0 = n4; w1 = n3; w2 = n2; w3 = n1;
+    const float4 t = tn;
+    float n[4];                                   // rows r0 - b - 1 .. r0 - b - 4
+#pragma unroll
+    for (int m = 0; m < 4; ++m) n[m] = nn[m];
+    if (b + 4 < nb4) {                            // uniform: the last group loads nothing
+      const float* sb = s - (b + 4) * st;
+      tn = *reinterpret_cast<const float4*>(g + b + 4);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) nn[m] = sb[-(m + 1) * st];
+    }
+    const float tv[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt)                // tap b + tt reads row r0 - b - tt + d
+#pragma unroll
+      for (int d = 0; d < D; ++d) out[d] = fmaf(tv[tt], d >= tt ? w[d - tt] : n[tt - d - 1], out[d]);
+#pragma unroll
+    for (int d = D - 1; d >= 4; --d) w[d] = w[d - 4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) w[m] = n[3 - m];
   }
 }
+
+constexpr int kOct = 8;             // outputs per thread per pass
 
 __device__ __forceinline__ void strip_range(const SepShape& s, int strip, int& k0, int& k1) {
   k0 = strip * s.ZS;
@@ -133,9 +142,44 @@ __device__ __forceinline__ void load_taps(const SepShape& s, const float* __rest
 }
 
 // ---------------------------------------------------------------- forward
+// Input rows of one plane for the z pass, prefetched into registers while
+// the previous plane is computed: rows w + 8 r (w = wave of the workgroup)
+// and columns lane + 64 u.
+constexpr int kPfRows = 16;   // staged rows per wave (WR <= 8 * 16)
+constexpr int kPfCols = 4;    // 64-column sweeps (nx <= 256)
+struct SepRows {
+  float v[kPfRows][kPfCols];
+  __device__ __forceinline__ void load(const SepShape& s, const float* __restrict__ Wj,
+                                       int rbase, int WR, size_t row_stride) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int rr = 0; rr < kPfRows; ++rr) {
+      const int r = w + (kSepThreads / 64) * rr;
+      const float* src = Wj + (size_t)clampi(rbase + r, 0, s.nz - 1) * row_stride;
+#pragma unroll
+      for (int u = 0; u < kPfCols; ++u) {
+        const int x = lane + 64 * u;
+        v[rr][u] = (r < WR && x < s.nx) ? src[x] : 0.0f;
+      }
+    }
+  }
+  __device__ __forceinline__ void store(const SepShape& s, float* Ws, int WR) const {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int rr = 0; rr < kPfRows; ++rr) {
+      const int r = w + (kSepThreads / 64) * rr;
+#pragma unroll
+      for (int u = 0; u < kPfCols; ++u) {
+        const int x = lane + 64 * u;
+        if (r < WR && x < s.nx) Ws[r * s.nx + x] = v[rr][u];
+      }
+    }
+  }
+};
+
 // grid: nstrip * nchunk * nvb workgroups of 512 threads.
-// LDS: Ws (ZS + NBz) x nx input rows (clamped), T ZS x TW (z-pass output on
-// the clamped, padded column range), taps.
+// LDS: Ws (ZS + NBz) x nx input rows (clamped), T ZS x TS z-pass output on
+// the padded column range (halo columns copied from the edge columns), taps.
 __global__ __launch_bounds__(kSepThreads) void conv_fwd_sep(const float* __restrict__ W,
                                                             const float* __restrict__ psf,
                                                             float* __restrict__ partial,
@@ -147,61 +191,71 @@ __global__ __launch_bounds__(kSepThreads) void conv_fwd_sep(const float* __restr
   strip_range(s, strip, k0, k1);
   const int j0 = (int)(((long long)c * s.ny) / s.nchunk), j1 = (int)(((long long)(c + 1) * s.ny) / s.nchunk);
   const int WR = s.ZS + s.NBz;                     // staged input rows
-  const int TW = s.nx4 + s.NBx;                    // z-pass columns
+  const int TW = s.nx8 + s.NBx;                    // z-pass columns
   const int TS = TW | 1;                           // odd row stride: rows of a wave hit distinct banks
   float* Ws = sm;                                  // WR x nx
   float* T = Ws + WR * s.nx;                       // ZS x TS
   SepTaps tp = carve_taps(T + s.ZS * TS, s);
-  // staged row r <-> input row clamp(k0 + hb - NBz + r); T column tc <-> x = clamp(tc + ha - NBx)
-  const int rbase = k0 + s.hb - s.NBz, xbase = s.ha - s.NBx;
+  // staged row r <-> input row clamp(k0 + hb - NBz + r); T column tc <-> x = clamp(tc - xo)
+  const int rbase = k0 + s.hb - s.NBz, xo = s.NBx - s.ha;
   const size_t row_stride = (size_t)s.ny * s.nx;
   const float* Wl = W + (size_t)lb * s.nz * row_stride;
-  const int zq = s.ZS / 4, xq = s.nx4 / 4;
-  float acc[kSepQuads][4];
+  const int zo = s.ZS / kOct, xoct = s.nx8 / kOct;
+  float acc[kSepOcts][kOct];
 #pragma unroll
-  for (int u = 0; u < kSepQuads; ++u)
+  for (int u = 0; u < kSepOcts; ++u)
 #pragma unroll
-    for (int d = 0; d < 4; ++d) acc[u][d] = 0.0f;
+    for (int d = 0; d < kOct; ++d) acc[u][d] = 0.0f;
+  SepRows pf;
+  if (j0 < j1) pf.load(s, Wl + (size_t)j0 * s.nx, rbase, WR, row_stride);
   for (int j = j0; j < j1; ++j) {
     __syncthreads();                               // previous plane consumed
-    const float* Wj = Wl + (size_t)j * s.nx;
-    for (int e = threadIdx.x; e < WR * s.nx; e += kSepThreads) {
-      const int r = e / s.nx, x = e - r * s.nx;
-      Ws[e] = Wj[(size_t)clampi(rbase + r, 0, s.nz - 1) * row_stride + x];
-    }
+    pf.store(s, Ws, WR);
     load_taps(s, psf + ((size_t)l * s.ny + j) * (s.pz + s.px), tp, false);
     __syncthreads();
-    // z pass: T[kk][tc] = sum_b fz[b] w[clamp(k + hb - b)][x(tc)], k = k0 + kk;
-    // output kk = 4 q + d reads staged row kk + NBz - b
-    for (int e = threadIdx.x; e < zq * TW; e += kSepThreads) {
-      const int q = e / TW, tc = e - q * TW;
-      const int x = clampi(xbase + tc, 0, s.nx - 1);
-      float o[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-      conv4(Ws + x, s.nx, 4 * q + s.NBz, tp.gz, s.NBz, o);
+    if (j + 1 < j1) pf.load(s, Wl + (size_t)(j + 1) * s.nx, rbase, WR, row_stride);
+    // z pass on the real columns: T[kk][x + xo] = sum_b fz[b] w[clamp(k + hb - b)][x],
+    // output kk = 8 q + d reads staged row kk + NBz - b; the edge columns also
+    // fill the halo columns (clamped x)
+    for (int e = threadIdx.x; e < zo * s.nx; e += kSepThreads) {
+      const int q = e / s.nx, x = e - q * s.nx;
+      float o[kOct];
 #pragma unroll
-      for (int d = 0; d < 4; ++d) T[(4 * q + d) * TS + tc] = o[d];
+      for (int d = 0; d < kOct; ++d) o[d] = 0.0f;
+      convD<kOct>(Ws + x, s.nx, kOct * q + s.NBz, tp.gz, s.NBz, o);
+#pragma unroll
+      for (int d = 0; d < kOct; ++d) T[(kOct * q + d) * TS + x + xo] = o[d];
+    }
+    __syncthreads();
+    // halo columns: copies of the edge columns (x clamped)
+    const int nh = TW - s.nx;
+    for (int e = threadIdx.x; e < s.ZS * nh; e += kSepThreads) {
+      const int kk = e / nh, h = e - kk * nh;
+      float* row = T + kk * TS;
+      const int tc = h < xo ? h : s.nx + h;       // h >= xo: right halo column nx + h
+      row[tc] = row[h < xo ? xo : xo + s.nx - 1];
     }
     __syncthreads();
     // x pass: out[kk][i] += sum_a fx[a] T[kk][i + NBx - a] (lanes along kk)
 #pragma unroll
-    for (int u = 0; u < kSepQuads; ++u) {
+    for (int u = 0; u < kSepOcts; ++u) {
       const int e = threadIdx.x + kSepThreads * u;
-      if (e < s.ZS * xq) {
-        const int iq = e / s.ZS, kk = e - iq * s.ZS;
-        conv4(T + kk * TS, 1, 4 * iq + s.NBx, tp.gx, s.NBx, acc[u]);
+      if (e < s.ZS * xoct) {
+        const int io = e / s.ZS, kk = e - io * s.ZS;
+        convD<kOct>(T + kk * TS, 1, kOct * io + s.NBx, tp.gx, s.NBx, acc[u]);
       }
     }
   }
   float* out = partial + ((size_t)c * nvb + lb) * s.nz * s.nx;
 #pragma unroll
-  for (int u = 0; u < kSepQuads; ++u) {
+  for (int u = 0; u < kSepOcts; ++u) {
     const int e = threadIdx.x + kSepThreads * u;
-    if (e < s.ZS * xq) {
-      const int iq = e / s.ZS, kk = e - iq * s.ZS;
+    if (e < s.ZS * xoct) {
+      const int io = e / s.ZS, kk = e - io * s.ZS;
       const int k = k0 + kk;
 #pragma unroll
-      for (int d = 0; d < 4; ++d) {
-        const int i = 4 * iq + d;
+      for (int d = 0; d < kOct; ++d) {
+        const int i = kOct * io + d;
         if (k < k1 && i < s.nx) out[(size_t)k * s.nx + i] = acc[u][d];
       }
     }
@@ -210,7 +264,7 @@ __global__ __launch_bounds__(kSepThreads) void conv_fwd_sep(const float* __restr
 
 // ---------------------------------------------------------------- adjoint
 // grid: nstrip * nchunk_back * nvb workgroups.
-// LDS: Vs GR x VW projection rows (zero outside), G GR x nx4 x-pass output,
+// LDS: Vs GR x VS projection rows (zero outside), G GR x GS x-pass output,
 // taps.  Staged / intermediate row r <-> z = k0 + hb - NBz + r.
 __global__ __launch_bounds__(kSepThreads) void conv_back_sep(const float* __restrict__ v,
                                                              const float* __restrict__ psf,
@@ -224,36 +278,44 @@ __global__ __launch_bounds__(kSepThreads) void conv_back_sep(const float* __rest
   const int j0 = (int)(((long long)c * s.ny) / s.nchunk_back);
   const int j1 = (int)(((long long)(c + 1) * s.ny) / s.nchunk_back);
   const int GR = s.ZS + s.NBz;
-  const int VW = s.nx4 + s.NBx;                    // column vc <-> x = vc + ha - NBx
-  const int VS = VW | 1, GS = s.nx4 | 1;           // odd row strides (rows of a wave: distinct banks)
+  const int VW = s.nx8 + s.NBx;                    // column vc <-> x = vc + ha - NBx
+  const int VS = VW | 1, GS = s.nx8 | 1;           // odd row strides (rows of a wave: distinct banks)
   float* Vs = sm;                                  // GR x VS
   float* G = Vs + GR * VS;                         // GR x GS
   SepTaps tp = carve_taps(G + GR * GS, s);
   const int rbase = k0 + s.hb - s.NBz, xbase = s.ha - s.NBx;
+  const int r_lo = max(0, -rbase), r_hi = min(GR, s.nz - rbase);   // rows inside the volume
   const float* vl = v + (size_t)l * s.nz * s.nx;
   for (int e = threadIdx.x; e < GR * VW; e += kSepThreads) {
     const int r = e / VW, vc = e - r * VW;
     const int z = rbase + r, x = xbase + vc;
     Vs[r * VS + vc] = (z >= 0 && z < s.nz && x >= 0 && x < s.nx) ? vl[(size_t)z * s.nx + x] : 0.0f;
   }
-  const int xq = s.nx4 / 4, zq = s.ZS / 4;
+  // rows outside the volume are the zero padding of the z pass, for every plane
+  for (int e = threadIdx.x; e < GR * GS; e += kSepThreads) {
+    const int r = e / GS;
+    if (r < r_lo || r >= r_hi) G[e] = 0.0f;
+  }
+  const int nr = r_hi - r_lo, xoct = s.nx8 / kOct, zo = s.ZS / kOct;
   for (int j = j0; j < j1; ++j) {
     __syncthreads();                               // projection staged / previous plane consumed
     load_taps(s, psf + ((size_t)l * s.ny + j) * (s.pz + s.px), tp, true);
     __syncthreads();
     // x pass (zero-padded correlation): G[r][i] = sum_a fx[a] v[z][i - ha + a]
-    //   = sum_b gx[b] Vs[r][i + NBx - b], gx reversed; rows outside [0, nz) stay 0
-    for (int e = threadIdx.x; e < GR * xq; e += kSepThreads) {
-      const int iq = e / GR, r = e - iq * GR;      // lanes along r
-      float o[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-      conv4(Vs + r * VS, 1, 4 * iq + s.NBx, tp.gx, s.NBx, o);
+    //   = sum_b gx[b] Vs[r][i + NBx - b], gx reversed (lanes along r)
+    for (int e = threadIdx.x; e < nr * xoct; e += kSepThreads) {
+      const int io = e / nr, r = r_lo + (e - io * nr);
+      float o[kOct];
 #pragma unroll
-      for (int d = 0; d < 4; ++d) G[r * GS + 4 * iq + d] = o[d];
+      for (int d = 0; d < kOct; ++d) o[d] = 0.0f;
+      convD<kOct>(Vs + r * VS, 1, kOct * io + s.NBx, tp.gx, s.NBx, o);
+#pragma unroll
+      for (int d = 0; d < kOct; ++d) G[r * GS + kOct * io + d] = o[d];
     }
     __syncthreads();
     // x edges: the fold of replicate padding onto x = 0 and x = nx - 1
-    for (int e = threadIdx.x; e < 2 * GR; e += kSepThreads) {
-      const int r = e >> 1, side = e & 1;
+    for (int e = threadIdx.x; e < 2 * nr; e += kSepThreads) {
+      const int r = r_lo + (e >> 1), side = e & 1;
       const float* row = Vs + r * VS - xbase;      // row[x] = v[z][x]
       float a = 0.0f;
       if (s.nx == 1) {
@@ -270,13 +332,15 @@ __global__ __launch_bounds__(kSepThreads) void conv_back_sep(const float* __rest
     //   = sum_b gz[b] G[kk + NBz - b][i], kk = k - k0; edge rows come next
     float* Uj = U + (size_t)lb * s.nz * s.ny * s.nx + (size_t)j * s.nx;
     const size_t kst = (size_t)s.ny * s.nx;
-    for (int e = threadIdx.x; e < zq * s.nx; e += kSepThreads) {
+    for (int e = threadIdx.x; e < zo * s.nx; e += kSepThreads) {
       const int q = e / s.nx, i = e - q * s.nx;
-      float o[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-      conv4(G + i, GS, 4 * q + s.NBz, tp.gz, s.NBz, o);
+      float o[kOct];
 #pragma unroll
-      for (int d = 0; d < 4; ++d) {
-        const int k = k0 + 4 * q + d;
+      for (int d = 0; d < kOct; ++d) o[d] = 0.0f;
+      convD<kOct>(G + i, GS, kOct * q + s.NBz, tp.gz, s.NBz, o);
+#pragma unroll
+      for (int d = 0; d < kOct; ++d) {
+        const int k = k0 + kOct * q + d;
         const bool edge = (k == 0 || k == s.nz - 1);
         if (k < k1 && !edge) Uj[(size_t)k * kst + i] = o[d];
       }
@@ -323,8 +387,8 @@ int sep_pick_chunks(int ny, long long units, long long slots) {
 size_t sep_lds_bytes(const SepShape& s, bool back) {
   const size_t taps = (size_t)sep_taps_floats(s);
   const size_t rows = (size_t)s.ZS + s.NBz;
-  if (back) return (rows * ((s.nx4 + s.NBx) | 1) + rows * (s.nx4 | 1) + taps) * sizeof(float);
-  return (rows * s.nx + (size_t)s.ZS * ((s.nx4 + s.NBx) | 1) + taps) * sizeof(float);
+  if (back) return (rows * ((s.nx8 + s.NBx) | 1) + rows * (s.nx8 | 1) + taps) * sizeof(float);
+  return (rows * s.nx + (size_t)s.ZS * ((s.nx8 + s.NBx) | 1) + taps) * sizeof(float);
 }
 
 SepShape make_sep_shape(const spect_geom& g) {
@@ -333,20 +397,22 @@ SepShape make_sep_shape(const spect_geom& g) {
   s.ha = (g.px - 1) / 2; s.hb = (g.pz - 1) / 2;
   s.NBx = (g.px + 3) / 4 * 4;
   s.NBz = (g.pz + 3) / 4 * 4;
-  s.nx4 = (g.nx + 3) / 4 * 4;
+  s.nx8 = (g.nx + kOct - 1) / kOct * kOct;
   s.ok = false;
-  // largest strip (multiple of 4 rows) that fits LDS and the forward's
-  // register-held quads, then balanced over the strips it takes
-  int zs = (g.nz + 3) / 4 * 4;
-  for (; zs >= 4; zs -= 4) {
+  // largest strip (multiple of 8 rows) that fits LDS, the forward's
+  // register-held outputs and its prefetched rows, then balanced over the
+  // strips it takes
+  int zs = (g.nz + kOct - 1) / kOct * kOct;
+  for (; zs >= kOct; zs -= kOct) {
     s.ZS = zs;
     if (sep_lds_bytes(s, false) <= kLdsBytes && sep_lds_bytes(s, true) <= kLdsBytes &&
-        zs * (s.nx4 / 4) <= kSepThreads * kSepQuads)
+        zs * (s.nx8 / kOct) <= kSepThreads * (kSepOcts) &&
+        zs + s.NBz <= (kSepThreads / 64) * kPfRows && g.nx <= 64 * kPfCols)
       break;
   }
-  if (zs < 4) return s;
+  if (zs < kOct) return s;
   s.nstrip = (g.nz + zs - 1) / zs;
-  s.ZS = ((g.nz + s.nstrip - 1) / s.nstrip + 3) / 4 * 4;
+  s.ZS = ((g.nz + s.nstrip - 1) / s.nstrip + kOct - 1) / kOct * kOct;
   s.nchunk = 1;
   s.nchunk_back = 1;
   s.ok = true;

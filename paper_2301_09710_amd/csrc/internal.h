@@ -63,7 +63,7 @@ struct M4Shape {
 struct SepShape {
   int nx, ny, nz, px, pz, ha, hb;
   int NBx, NBz;         // tap counts rounded up to 4
-  int nx4;              // nx rounded up to 4
+  int nx8;              // nx rounded up to 8
   int ZS, nstrip;       // output rows (z) per workgroup strip, strips per plane
   int nchunk, nchunk_back;
   bool ok;              // the strips fit LDS and the forward's register-held outputs
