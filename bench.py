@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 FP32_PEAK_TFLOPS = 157.3          # MI355X published FP32 matrix (MFMA) peak, dense
 LP_PEAK_TFLOPS = 2500.0           # MI355X published dense BF16 / FP16 matrix peak
 HBM_PEAK_GBS = 8000.0
+FP32_VALU_TFLOPS = 157.3          # MI355X published FP32 vector peak (with packed FP32, unused here)
 
 
 def parse():
@@ -47,6 +48,8 @@ def parse():
                     help="pairs timed for each reduced-precision (BF16, FP16) convolution plan (0 disables)")
     ap.add_argument("--bilinear-steps", type=int, default=10,
                     help="timed pairs of the FP32 pair with 2-D bilinear rotation (0: skip)")
+    ap.add_argument("--separable-steps", type=int, default=10,
+                    help="timed pairs with the PSFs given as their 1-D factors (0: skip)")
     ap.add_argument("--large-steps", type=int, default=3,
                     help="pairs timed per precision on the 256x256x160 precision workload (0 disables)")
     ap.add_argument("--serve-requests", type=int, default=200,
@@ -304,6 +307,46 @@ def main():
         pl.close()
         del pl, v2, b2
 
+    # The same pair with the Gaussian PSFs given as their 1-D factors
+    # (SPECT_PSF_SEPARABLE): the same operator up to the rounding of the
+    # factors, two 1-D passes per plane (not part of `value`).
+    sep = None
+    if args.separable_steps > 0:
+        cfg = synth.CONFIGS["paper"]
+        fz, fx = synth.gaussian_psf_factors(px, pz, ny, nview, *cfg["sigma"])
+        pl = spect.Plan(mud, (torch.from_numpy(fz).to(dev), torch.from_numpy(fx).to(dev)), dy,
+                        cache_mubar=bool(args.cache_mubar))
+        v2 = torch.empty_like(vd)
+        b2 = torch.empty_like(bd)
+        for _ in range(args.warmup):
+            pl.forward(xd, out=v2)
+            pl.back(v2, out=b2)
+        torch.cuda.synchronize()
+        pl.profile_start(max_launches=64 * args.separable_steps + 64)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.separable_steps):
+            pl.forward(xd, out=v2)
+            pl.back(v2, out=b2)
+        b.record()
+        torch.cuda.synchronize()
+        kt = pl.profile_stop()
+        ms = a.elapsed_time(b) / args.separable_steps
+        pl.forward(xd, out=v2)
+        pl.back(vd, out=b2)
+        torch.cuda.synchronize()
+        kav = {k: v["total_ms"] / v["launches"] for k, v in kt.items()}
+        sep_flops = 2.0 * (px + pz) * nx * ny * nz * nview
+        sep = {"pairs_per_s": 1000.0 / ms, "ms_per_pair": ms,
+               "rel_l2_forward_vs_2d": float((v2.double() - vd.double()).norm() / vd.double().norm()),
+               "rel_l2_back_vs_2d": float((b2.double() - bd.double()).norm() / bd.double().norm()),
+               "kernels_ms_per_launch": kav,
+               "conv_fwd_roofline": {"bound": "valu", "achieved": sep_flops / (kav["conv_fwd"] * 1e-3) / 1e12,
+                                     "peak": FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                                     "frac": sep_flops / (kav["conv_fwd"] * 1e-3) / 1e12 / FP32_VALU_TFLOPS}}
+        pl.close()
+        del pl, v2, b2
+
     # The precision workload: 256x256x160, 128 views, 37x37 PSFs, the pair and
     # a 10-iteration EM image in FP32, BF16 and FP16 (not part of `value`).
     # Distances are to the FP32 results, which the tests hold within 1e-5 of
@@ -445,6 +488,7 @@ def main():
         "unrolled_em_grad": grad,
         "reduced_precision": lp,
         "bilinear_rotation": bil,
+        "separable_psf": sep,
         "large_precision": large,
         "serving": serving,
         "kernels_ms_per_launch": avg_ms,
