@@ -230,6 +230,34 @@ def main():
             lat.append(a.elapsed_time(b))
         em = {"iters": args.em_iters, "recons": args.em_recons, "p50_ms": pct(lat, 50),
               "p99_ms": pct(lat, 99)}
+        # method variants on the same data: one regularised EM step (Eq. (7)-(8),
+        # beta > 0, target u), and OSEM with 4 subsets x 16 iterations (the
+        # comparison reconstruction's setting), each timed from its first launch
+        ud = torch.ones(plan.vol_shape, dtype=torch.float32, device=dev)
+        xe = torch.ones(plan.vol_shape, dtype=torch.float32, device=dev)
+        plan.reg_em_step(xe, yd, sens, ud, 0.01, rd)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.em_iters):
+            plan.reg_em_step(xe, yd, sens, ud, 0.01, rd)
+        b.record()
+        torch.cuda.synchronize()
+        em["reg_em_step_ms"] = a.elapsed_time(b) / args.em_iters
+        from paper_2301_09710_amd.osem import OSEM
+        os_ = OSEM(mud, psfd, dy, 4, cache_mubar=bool(args.cache_mubar))
+        os_.sensitivities()
+        xo = torch.ones(plan.vol_shape, dtype=torch.float32, device=dev)
+        os_.run(xo, yd, rd, iters=1)
+        torch.cuda.synchronize()
+        xo.fill_(1.0)
+        a.record()
+        os_.run(xo, yd, rd, iters=16)
+        b.record()
+        torch.cuda.synchronize()
+        em["osem_4x16_ms"] = a.elapsed_time(b)
+        os_.close()
+        del os_
 
     # Reduced-precision convolution (not part of `value`): the same pair with
     # BF16 / FP16 matrix-core operands, and with split-BF16 operands (three
