@@ -192,3 +192,17 @@ def test_large_config_all_precisions_sampled_views():
         plan.close()
         del plan
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_lp_with_bilinear_rotation(tiny, prec):
+    """The reduced-precision convolution with the bilinear rotation: within 2u
+    of the FP64 oracle's bilinear projector."""
+    g = Geometry(32, 32, 20, 16, 7, 7, tiny["dy"], rotation="bilinear")
+    plan = spect.Plan(to_dev(tiny["mu"]), to_dev(tiny["psf"]), tiny["dy"], precision=prec,
+                      rotation="bilinear")
+    ef = rel_l2(host(plan.forward(to_dev(tiny["x"]))), oracle.forward(tiny["x"], tiny["mu"], tiny["psf"], g))
+    eb = rel_l2(host(plan.back(to_dev(tiny["y"]))), oracle.back(tiny["y"], tiny["mu"], tiny["psf"], g))
+    u = precision.unit_roundoff(prec)
+    say(f"{prec} bilinear tiny: forward {ef:.2e}, back {eb:.2e} (2u = {2 * u:.2e})")
+    assert ef <= 2 * u and eb <= 2 * u

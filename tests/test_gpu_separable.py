@@ -155,3 +155,19 @@ def test_separable_gaussian_sampled_views(size, views):
     gap = abs(lhs - rhs) / abs(lhs)
     say(f"  forward {ef:.2e}, back {eb:.2e}, adjoint gap {gap:.2e}")
     assert ef <= TOL and eb <= TOL and gap <= TOL
+
+
+def test_separable_with_bilinear_rotation():
+    """Both plan options at once: separable PSFs and bilinear rotation."""
+    nx, nz, nview, px, pz = 24, 11, 6, 9, 7
+    x = synth.random_volume(nx, nx, nz, seed=41)
+    mu = synth.random_volume(nx, nx, nz, seed=42, high=0.05)
+    fz, fx = random_factors(px, pz, nx, nview, 43)
+    g = Geometry(nx, nx, nz, nview, px, pz, 1.1, rotation="bilinear")
+    plan = spect.Plan(to_dev(mu), (to_dev(fz), to_dev(fx)), 1.1, rotation="bilinear")
+    p = outer(fz, fx)
+    ef = rel_l2(host(plan.forward(to_dev(x))), oracle.forward(x, mu, p, g))
+    y = synth.random_volume(nx, nz, nview, seed=44)
+    eb = rel_l2(host(plan.back(to_dev(y))), oracle.back(y, mu, p, g))
+    say(f"separable + bilinear: forward {ef:.2e}, back {eb:.2e}")
+    assert ef <= TOL and eb <= TOL
