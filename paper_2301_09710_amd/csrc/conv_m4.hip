@@ -29,7 +29,7 @@
 //   - the PSF is stored as one zero-padded column per x tap, laid out so that
 //     step delta of lane q reads a fixed immediate offset from a per-tap base.
 //
-// Forward: a workgroup owns a (4 kZt BZ) x (32 BX) output tile of one view and
+// Forward: a workgroup (NW waves) owns a (4 kZt BZ) x (32 BX) output tile of one view and
 // a chunk of depth planes, stages each plane's region (replicate padding by
 // clamped source indices) and PSF, and adds the plane into the accumulators;
 // each plane's sum is folded into a second set, so FP32 chains stay one plane
@@ -46,11 +46,21 @@ namespace {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kZt = 5;       // z tiles (4 rows each) per block
-constexpr int kXt = 2;       // x tiles (4 columns each) per block
 constexpr int kLook = 2;     // steps of operands loaded ahead of their MFMAs
-constexpr int kPfRows = 32;  // region rows per wave held for the next plane (RR <= 128)
+constexpr int kMaxRR = 128;  // region rows
 constexpr int kPfCols = 3;   // 64-column sweeps of a region row (RC <= 192)
-constexpr int kPfPsf = 16;   // PSF table elements per thread (px * PL4 <= 4096)
+constexpr int kMaxPsf = 4096;  // PSF table elements (px * PL4)
+
+// A workgroup of NW waves (4 or 8) covers the same 32 BX columns either way:
+// each wave's blocks hold 8 / NW x tiles.  With 8 waves every SIMD runs two
+// of them, so one wave's LDS waits and barriers overlap the other's MFMAs.
+template <int NW>
+struct Waves {
+  static constexpr int kXt = 8 / NW;             // x tiles (4 columns each) per block
+  static constexpr int kThreads = 64 * NW;
+  static constexpr int kPfRows = kMaxRR / NW;    // region rows per wave held for the next plane
+  static constexpr int kPfPsf = kMaxPsf / kThreads;  // PSF table elements per thread
+};
 
 __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
@@ -76,7 +86,7 @@ __device__ __forceinline__ void chunk_range(int c, int nchunk, int ny, int& j0, 
 // advanced by PL4 per tap, read at offset (ND - 1 - t) forward or t adjoint
 // for step t; pb = RT + pb_lane (tap 0, x tile 0), moved by -RRS (forward) or
 // +RRS (adjoint) per tap, x tile j at +4 j RRS, input row r at +r.
-template <int ND4, bool kBack>
+template <int ND4, int kXt, bool kBack>
 __device__ __forceinline__ void m4_plane(const float* __restrict__ P, const float* __restrict__ RT,
                                          int pa_lane, int pb_lane, int PL4, int RRS, int px,
                                          floatx4 (&acc)[kZt][kXt]) {
@@ -143,12 +153,14 @@ __device__ __forceinline__ void m4_plane(const float* __restrict__ P, const floa
 
 // PSF table of one plane: P[a PL4 + t] = p[t - Z][a] (zero outside the taps),
 // Z = ND - pz forward (column reversed by the read order), 3 adjoint.
+template <int NW>
 struct PsfTable {
+  static constexpr int kPfPsf = Waves<NW>::kPfPsf;
   float v[kPfPsf];
   __device__ __forceinline__ void load(const M4Shape& s, const float* __restrict__ pj, int Z) {
 #pragma unroll
     for (int u = 0; u < kPfPsf; ++u) {
-      const int e = threadIdx.x + 256 * u;
+      const int e = threadIdx.x + Waves<NW>::kThreads * u;
       float x = 0.0f;
       if (e < s.px * s.PL4) {
         const int a = e / s.PL4, b = e - a * s.PL4 - Z;
@@ -160,21 +172,23 @@ struct PsfTable {
   __device__ __forceinline__ void store(const M4Shape& s, float* P) const {
 #pragma unroll
     for (int u = 0; u < kPfPsf; ++u) {
-      const int e = threadIdx.x + 256 * u;
+      const int e = threadIdx.x + Waves<NW>::kThreads * u;
       if (e < s.px * s.PL4) P[e] = v[u];
     }
   }
 };
 
-// Forward input region of one plane, rows w + 4 r (input k = k0 - hb + row,
+// Forward input region of one plane, rows w + NW r (input k = k0 - hb + row,
 // clamped) and columns lane + 64 u (input i = i0 - ha + column, clamped).
+template <int NW>
 struct FwdRegion {
+  static constexpr int kPfRows = Waves<NW>::kPfRows;
   float r[kPfRows][kPfCols];
   __device__ __forceinline__ void load(const M4Shape& s, const float* __restrict__ Wj, int k0,
                                        int i0, size_t row_stride, int w, int lane) {
 #pragma unroll
     for (int rr = 0; rr < kPfRows; ++rr) {
-      const int row = w + 4 * rr;
+      const int row = w + NW * rr;
       const float* src = Wj + (size_t)clampi(k0 - s.hb + row, 0, s.nz - 1) * row_stride;
 #pragma unroll
       for (int u = 0; u < kPfCols; ++u) {
@@ -186,7 +200,7 @@ struct FwdRegion {
   __device__ __forceinline__ void store(const M4Shape& s, float* RT, int w, int lane) const {
 #pragma unroll
     for (int rr = 0; rr < kPfRows; ++rr) {
-      const int row = w + 4 * rr;
+      const int row = w + NW * rr;
 #pragma unroll
       for (int u = 0; u < kPfCols; ++u) {
         const int col = lane + 64 * u;
@@ -197,8 +211,8 @@ struct FwdRegion {
 };
 
 // ---------------------------------------------------------------- forward
-template <int ND4>
-__global__ __launch_bounds__(256, 1) void conv_fwd_m4(const float* __restrict__ W,
+template <int ND4, int NW>
+__global__ __launch_bounds__(64 * NW, 1) void conv_fwd_m4(const float* __restrict__ W,
                                                       const float* __restrict__ psf,
                                                       float* __restrict__ partial, M4Shape s,
                                                       int view0, int nvb) {
@@ -213,7 +227,8 @@ __global__ __launch_bounds__(256, 1) void conv_fwd_m4(const float* __restrict__ 
   const int k0 = tk * 4 * kZt * s.BZ, i0 = ti * 32 * s.BX;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane & 3, blk = lane >> 2;
   const int bz = blk / s.BX, bx = blk - bz * s.BX;
-  const int zb = 4 * kZt * bz, xo = 8 * s.BX * w + 8 * bx;  // block origin in the tile
+  constexpr int kXt = Waves<NW>::kXt;
+  const int zb = 4 * kZt * bz, xo = 4 * kXt * (s.BX * w + bx);  // block origin in the tile
   int j0, j1;
   chunk_range(c, s.nchunk, s.ny, j0, j1);
   const size_t row_stride = (size_t)s.ny * s.nx;
@@ -231,8 +246,8 @@ __global__ __launch_bounds__(256, 1) void conv_fwd_m4(const float* __restrict__ 
   for (int i = 0; i < kZt; ++i)
 #pragma unroll
     for (int j = 0; j < kXt; ++j) tot[i][j] = {0.f, 0.f, 0.f, 0.f};
-  FwdRegion reg;
-  PsfTable tab;
+  FwdRegion<NW> reg;
+  PsfTable<NW> tab;
   if (j0 < j1) {
     reg.load(s, Wl + (size_t)j0 * s.nx, k0, i0, row_stride, w, lane);
     tab.load(s, psf_l + (size_t)j0 * s.pz * s.px, Z);
@@ -251,7 +266,7 @@ __global__ __launch_bounds__(256, 1) void conv_fwd_m4(const float* __restrict__ 
     for (int i = 0; i < kZt; ++i)
 #pragma unroll
       for (int jj = 0; jj < kXt; ++jj) acc[i][jj] = {0.f, 0.f, 0.f, 0.f};
-    m4_plane<ND4, false>(P, RT, pa_lane, pb_lane, s.PL4, s.RRS, s.px, acc);
+    m4_plane<ND4, kXt, false>(P, RT, pa_lane, pb_lane, s.PL4, s.RRS, s.px, acc);
 #pragma unroll
     for (int i = 0; i < kZt; ++i)
 #pragma unroll
@@ -275,8 +290,8 @@ __global__ __launch_bounds__(256, 1) void conv_fwd_m4(const float* __restrict__ 
 // ---------------------------------------------------------------- adjoint
 // u[k][i] = sum_{a,b} p[b][a] v[k + b - hb][i + a - ha] (v zero outside) for
 // every bin of the tile and every plane of the chunk.
-template <int ND4>
-__global__ __launch_bounds__(256, 1) void conv_back_m4(const float* __restrict__ v,
+template <int ND4, int NW>
+__global__ __launch_bounds__(64 * NW, 1) void conv_back_m4(const float* __restrict__ v,
                                                        const float* __restrict__ psf,
                                                        float* __restrict__ U, M4Shape s,
                                                        int view0, int nvb) {
@@ -291,14 +306,15 @@ __global__ __launch_bounds__(256, 1) void conv_back_m4(const float* __restrict__
   const int k0 = tk * 4 * kZt * s.BZ, i0 = ti * 32 * s.BX;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane & 3, blk = lane >> 2;
   const int bz = blk / s.BX, bx = blk - bz * s.BX;
-  const int zb = 4 * kZt * bz, xo = 8 * s.BX * w + 8 * bx;
+  constexpr int kXt = Waves<NW>::kXt;
+  const int zb = 4 * kZt * bz, xo = 4 * kXt * (s.BX * w + bx);
   int j0, j1;
   chunk_range(c, s.nchunk_back, s.ny, j0, j1);
   const float* vl = v + (size_t)l * s.nz * s.nx;
   const float* psf_l = psf + (size_t)l * s.ny * s.pz * s.px;
 
   // region row r <-> input k = k0 - hb + r, column cc <-> input i = i0 - ha + cc
-  for (int e = threadIdx.x; e < s.RR * s.RC; e += 256) {
+  for (int e = threadIdx.x; e < s.RR * s.RC; e += Waves<NW>::kThreads) {
     const int r = e / s.RC, cc = e - r * s.RC;
     const int kk = k0 - s.hb + r, ii = i0 - s.ha + cc;
     RT[cc * s.RRS + r] =
@@ -308,7 +324,7 @@ __global__ __launch_bounds__(256, 1) void conv_back_m4(const float* __restrict__
   // B (x tile j, row r) = RT[(xo + 4 j + q + a) RRS + zb + r]
   const int pa_lane = 3 - q;
   const int pb_lane = (xo + q) * s.RRS + zb;
-  PsfTable tab;
+  PsfTable<NW> tab;
   if (j0 < j1) tab.load(s, psf_l + (size_t)j0 * s.pz * s.px, 3);
   for (int j = j0; j < j1; ++j) {
     __syncthreads();                               // region staged / previous plane consumed
@@ -320,7 +336,7 @@ __global__ __launch_bounds__(256, 1) void conv_back_m4(const float* __restrict__
     for (int i = 0; i < kZt; ++i)
 #pragma unroll
       for (int jj = 0; jj < kXt; ++jj) acc[i][jj] = {0.f, 0.f, 0.f, 0.f};
-    m4_plane<ND4, true>(P, RT, pa_lane, pb_lane, s.PL4, s.RRS, s.px, acc);
+    m4_plane<ND4, kXt, true>(P, RT, pa_lane, pb_lane, s.PL4, s.RRS, s.px, acc);
     float* out = U + (size_t)lb * s.nz * s.ny * s.nx + (size_t)j * s.nx;
 #pragma unroll
     for (int i = 0; i < kZt; ++i)
@@ -343,39 +359,53 @@ size_t m4_lds_bytes(const M4Shape& s) {
   return ((size_t)s.RC * s.RRS + (size_t)s.px * s.PL4) * sizeof(float);
 }
 
-template <int ND4>
-hipError_t launch_m4(const M4Shape& s, bool back, const float* in, const float* psf, float* out,
-                     int view0, int nvb, hipStream_t st) {
+template <int ND4, int NW>
+hipError_t launch_m4_nw(const M4Shape& s, bool back, const float* in, const float* psf, float* out,
+                        int view0, int nvb, hipStream_t st) {
   const size_t sm = m4_lds_bytes(s);
-  const void* fn = back ? (const void*)conv_back_m4<ND4> : (const void*)conv_fwd_m4<ND4>;
+  const void* fn = back ? (const void*)conv_back_m4<ND4, NW> : (const void*)conv_fwd_m4<ND4, NW>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
   if (e != hipSuccess) return e;
   dim3 grid(s.tiles_k * s.tiles_i * (back ? s.nchunk_back : s.nchunk) * nvb);
+  dim3 block(Waves<NW>::kThreads);
   if (back)
-    hipLaunchKernelGGL(conv_back_m4<ND4>, grid, dim3(256), sm, st, in, psf, out, s, view0, nvb);
+    hipLaunchKernelGGL((conv_back_m4<ND4, NW>), grid, block, sm, st, in, psf, out, s, view0, nvb);
   else
-    hipLaunchKernelGGL(conv_fwd_m4<ND4>, grid, dim3(256), sm, st, in, psf, out, s, view0, nvb);
+    hipLaunchKernelGGL((conv_fwd_m4<ND4, NW>), grid, block, sm, st, in, psf, out, s, view0, nvb);
   return hipGetLastError();
 }
 
 template <int ND4>
-int m4_wgs_per_cu(const M4Shape& s, bool back) {
+hipError_t launch_m4(const M4Shape& s, bool back, const float* in, const float* psf, float* out,
+                     int view0, int nvb, hipStream_t st) {
+  return s.NW == 8 ? launch_m4_nw<ND4, 8>(s, back, in, psf, out, view0, nvb, st)
+                   : launch_m4_nw<ND4, 4>(s, back, in, psf, out, view0, nvb, st);
+}
+
+template <int ND4, int NW>
+int m4_wgs_per_cu_nw(const M4Shape& s, bool back) {
   int nb = 0;
-  const void* fn = back ? (const void*)conv_back_m4<ND4> : (const void*)conv_fwd_m4<ND4>;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, m4_lds_bytes(s)) != hipSuccess)
+  const void* fn = back ? (const void*)conv_back_m4<ND4, NW> : (const void*)conv_fwd_m4<ND4, NW>;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, Waves<NW>::kThreads, m4_lds_bytes(s)) !=
+      hipSuccess)
     nb = 0;
   return nb < 1 ? 1 : nb;
 }
 
+template <int ND4>
+int m4_wgs_per_cu(const M4Shape& s, bool back) {
+  return s.NW == 8 ? m4_wgs_per_cu_nw<ND4, 8>(s, back) : m4_wgs_per_cu_nw<ND4, 4>(s, back);
+}
+
 // Largest number of lanes of one half wave (32 lanes) that share an LDS bank
 // for the B reads of a column stride rrs (32 banks of 4 bytes).
-int m4_bank_conflicts(int rrs, int BX) {
+int m4_bank_conflicts(int rrs, int BX, int xt) {
   int worst = 0;
   for (int h = 0; h < 2; ++h) {
     int count[32] = {0};
     for (int lane = 32 * h; lane < 32 * h + 32; ++lane) {
       const int blk = lane >> 2, q = lane & 3, bz = blk / BX, bx = blk % BX;
-      const long long addr = (long long)(8 * bx + q) * rrs + 4 * kZt * bz;
+      const long long addr = (long long)(4 * xt * bx + q) * rrs + 4 * kZt * bz;
       const int bank = (int)(addr % 32);
       if (++count[bank] > worst) worst = count[bank];
     }
@@ -397,7 +427,7 @@ int m4_pick_chunks(int ny, long long tiles_views, long long slots) {
 
 }  // namespace
 
-M4Shape make_m4_shape(const spect_geom& g) {
+M4Shape make_m4_shape(const spect_geom& g, int NW) {
   M4Shape best{};
   best.ok = false;
   double best_area = 0.0;
@@ -407,6 +437,7 @@ M4Shape make_m4_shape(const spect_geom& g) {
     s.nx = g.nx; s.ny = g.ny; s.nz = g.nz; s.px = g.px; s.pz = g.pz;
     s.ha = (g.px - 1) / 2; s.hb = (g.pz - 1) / 2;
     s.ND4 = ND4;
+    s.NW = NW == 8 ? 8 : 4;
     s.BX = BX;
     s.BZ = 16 / BX;
     s.tiles_k = (g.nz + 4 * kZt * s.BZ - 1) / (4 * kZt * s.BZ);
@@ -416,15 +447,15 @@ M4Shape make_m4_shape(const spect_geom& g) {
     s.PL4 = 4 * ND4 + 3;
     int rrs = s.RR | 1, best_rrs = rrs, best_conf = 1 << 30;
     for (; rrs < s.RR + 64; rrs += 2) {
-      const int cf = m4_bank_conflicts(rrs, BX);
+      const int cf = m4_bank_conflicts(rrs, BX, 8 / s.NW);
       if (cf < best_conf) { best_conf = cf; best_rrs = rrs; }
       if (cf <= 1) break;
     }
     s.RRS = best_rrs;
     s.nchunk = 1;
     s.nchunk_back = 1;
-    s.ok = ND4 >= 1 && ND4 <= 16 && s.RR <= 4 * kPfRows && s.RC <= 64 * kPfCols &&
-           g.px * s.PL4 <= 256 * kPfPsf && m4_lds_bytes(s) <= kLdsBytes;
+    s.ok = ND4 >= 1 && ND4 <= 16 && s.RR <= kMaxRR && s.RC <= 64 * kPfCols &&
+           g.px * s.PL4 <= kMaxPsf && m4_lds_bytes(s) <= kLdsBytes;
     if (!s.ok) continue;
     const double area = (double)s.tiles_k * 4 * kZt * s.BZ * s.tiles_i * 32 * BX;
     if (!best.ok || area < best_area) { best = s; best_area = area; }

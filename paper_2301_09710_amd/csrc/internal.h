@@ -51,6 +51,7 @@ struct ConvShape {
 struct M4Shape {
   int nx, ny, nz, px, pz, ha, hb;
   int ND4;              // steps per tap / 4: ceil((pz + 3) / 4)
+  int NW;               // waves per workgroup (4 or 8)
   int BZ, BX;           // blocks of a wave along z and x (BZ * BX = 16)
   int tiles_k, tiles_i; // workgroup tiles of 20 BZ x 32 BX output bins
   int RR, RC, RRS;      // region rows (z), columns (x), column stride in LDS
@@ -187,7 +188,7 @@ ConvShape make_conv_shape(const spect_geom& g, int jc_fwd, int jc_back);
 void tune_conv_chunks(ConvShape& cs, int views);
 size_t conv_mfma_lds_bytes(const ConvShape& cs, bool back);
 size_t conv_edges_lds_bytes(const ConvShape& cs);
-M4Shape make_m4_shape(const spect_geom& g);
+M4Shape make_m4_shape(const spect_geom& g, int NW);
 // Whether the 4x4-block tiling issues fewer matrix-core cycles than the 16x16 one.
 bool m4_preferred(const M4Shape& s, const ConvShape& cs);
 void tune_m4_chunks(M4Shape& s, int views);

@@ -240,7 +240,9 @@ spect_status spect_plan_create(spect_plan* out, const spect_geom* g, const float
   p->rot_scratch = g->nx > kMaxLdsN ? reinterpret_cast<float*>(p->ws + lay.rot_scratch) : nullptr;
   p->use_mfma = conv_mfma_supported(*g);
   p->conv = make_conv_shape(*g, kFwdJChunk, kBackJChunk);
-  p->m4 = make_m4_shape(*g);
+  // SPECT_M4_WAVES = 4 or 8 selects the waves per workgroup of the 4x4-block kernels
+  const char* m4w = std::getenv("SPECT_M4_WAVES");
+  p->m4 = make_m4_shape(*g, m4w && std::atoi(m4w) == 4 ? 4 : 8);
   p->use_m4 = false;
   p->separable = (g->flags & SPECT_PSF_SEPARABLE) != 0;
   if (p->separable) {

@@ -1,6 +1,7 @@
 """The two FP32 tilings of the PSF convolution, each forced at plan creation
 through SPECT_FP32_TILING: 16x16x4 Toeplitz blocks ("16x16") and 4x4x1 blocks
-("4x4"), against the FP64 oracle.
+("4x4", with 8 or 4 waves per workgroup through SPECT_M4_WAVES), against the
+FP64 oracle.
 
 The plan picks a tiling per shape from its cost model (4x4 blocks at the
 paper's 128x128x80 / 37x37 workload, 16x16 blocks on most small shapes), so
@@ -28,7 +29,14 @@ from paper_2301_09710_amd import spect  # noqa: E402
 
 DEV = torch.device("cuda:0")
 TOL = 1e-5
-TILINGS = ["4x4", "16x16"]
+TILINGS = ["4x4", "4x4/4w", "16x16"]
+
+
+def force(monkeypatch, tiling):
+    """Select a tiling (and the 4x4 kernels' waves per workgroup) for the
+    plans created next."""
+    monkeypatch.setenv("SPECT_FP32_TILING", tiling.split("/")[0])
+    monkeypatch.setenv("SPECT_M4_WAVES", "4" if tiling.endswith("/4w") else "8")
 
 
 def say(msg):
@@ -65,7 +73,7 @@ CASES = [
 @pytest.mark.parametrize("tiling", TILINGS)
 @pytest.mark.parametrize("case", CASES)
 def test_tiling_parity(case, tiling, monkeypatch):
-    monkeypatch.setenv("SPECT_FP32_TILING", tiling)
+    force(monkeypatch, tiling)
     nx, nz, nview, px, pz, sym = case
     say(f"tiling {tiling} {case}")
     seed = 7 * nx + nz
@@ -87,7 +95,7 @@ def test_tiling_parity(case, tiling, monkeypatch):
 @pytest.mark.parametrize("tiling", TILINGS)
 def test_tiling_dense_adjoint(tiling, monkeypatch):
     """Explicit A and B on 8x8x6 / 7 views: B = A^T to 1e-6 relative."""
-    monkeypatch.setenv("SPECT_FP32_TILING", tiling)
+    force(monkeypatch, tiling)
     nx, nz, nview, px = 8, 6, 7, 3
     N, M = nx * nx * nz, nview * nz * nx
     eyeN = torch.eye(N, device=DEV).reshape(N, nz, nx, nx)
@@ -126,7 +134,7 @@ def paper():
 
 @pytest.mark.parametrize("tiling", TILINGS)
 def test_tiling_paper_sampled(paper, tiling, monkeypatch):
-    monkeypatch.setenv("SPECT_FP32_TILING", tiling)
+    force(monkeypatch, tiling)
     say(f"tiling {tiling}: paper size")
     plan = spect.Plan(to_dev(paper["mu"]), to_dev(paper["psf"]), paper["dy"], cache_mubar=True)
     xd = to_dev(paper["x"])
