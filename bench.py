@@ -46,6 +46,8 @@ def parse():
                     help="unrolled EM iterations differentiated end to end (0 disables)")
     ap.add_argument("--precision-steps", type=int, default=10,
                     help="pairs timed for each reduced-precision (BF16, FP16) convolution plan (0 disables)")
+    ap.add_argument("--all-taps-steps", type=int, default=10,
+                    help="timed pairs with mirror-image tap pairing switched off (0: skip)")
     ap.add_argument("--bilinear-steps", type=int, default=10,
                     help="timed pairs of the FP32 pair with 2-D bilinear rotation (0: skip)")
     ap.add_argument("--separable-steps", type=int, default=10,
@@ -163,6 +165,8 @@ def main():
     mud = torch.from_numpy(mu).to(dev)
     psfd = torch.from_numpy(psf).to(dev)
     plan = spect.Plan(mud, psfd, dy, cache_mubar=bool(args.cache_mubar))
+    sel = plan.describe()            # kernels chosen (the Gaussian PSF rows are symmetric in x)
+    mirror = sel.get("mirror") == "1"
     vd = torch.empty(plan.proj_shape, dtype=torch.float32, device=dev)
     bd = torch.empty(plan.vol_shape, dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
@@ -195,7 +199,11 @@ def main():
     # dominant kernel and its roofline (algorithmic FLOPs per launch / average duration)
     N = nx * ny * nz
     views_per_launch = plan.nview  # one launch covers all views (view_batch = all)
-    conv_flops = 2.0 * px * pz * N * views_per_launch
+    # the operator's products: 2 px pz FLOP per voxel per view; with mirror-image
+    # tap pairing the matrix cores take 2 (px + 1) / 2 pz (the pre-adds of the
+    # two input columns run on the vector ALUs)
+    op_flops = 2.0 * px * pz * N * views_per_launch
+    conv_flops = 2.0 * ((px + 1) // 2) * pz * N * views_per_launch if mirror else op_flops
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     avg_ms = {k: v["total_ms"] / v["launches"] for k, v in kern.items()}
     if dom in ("conv_fwd", "conv_back"):
@@ -203,7 +211,9 @@ def main():
         roof = {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
                 "traffic": traffic_for(dom, conv_flops),
-                "algorithmic_per_launch": conv_flops, "avg_launch_ms": avg_ms[dom]}
+                "algorithmic_per_launch": conv_flops, "avg_launch_ms": avg_ms[dom],
+                "form": "mirror-paired taps" if mirror else "all taps",
+                "operator_flop_per_launch": op_flops}
     else:
         byts = 3.0 * 4 * N * views_per_launch
         achieved = byts / (avg_ms[dom] * 1e-3) / 1e9
@@ -258,6 +268,44 @@ def main():
         em["osem_4x16_ms"] = a.elapsed_time(b)
         os_.close()
         del os_
+
+    # The same pair with every PSF tap taken separately (SPECT_PSF_MIRROR=0):
+    # the path for PSFs that are not symmetric in x (not part of `value`).
+    all_taps = None
+    if args.all_taps_steps > 0 and mirror:
+        os.environ["SPECT_PSF_MIRROR"] = "0"
+        try:
+            pl = spect.Plan(mud, psfd, dy, cache_mubar=bool(args.cache_mubar))
+        finally:
+            del os.environ["SPECT_PSF_MIRROR"]
+        v2 = torch.empty_like(vd)
+        b2 = torch.empty_like(bd)
+        for _ in range(args.warmup):
+            pl.forward(xd, out=v2)
+            pl.back(v2, out=b2)
+        torch.cuda.synchronize()
+        pl.profile_start(max_launches=64 * args.all_taps_steps + 64)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.all_taps_steps):
+            pl.forward(xd, out=v2)
+            pl.back(v2, out=b2)
+        b.record()
+        torch.cuda.synchronize()
+        kt = pl.profile_stop()
+        ms = a.elapsed_time(b) / args.all_taps_steps
+        pl.forward(xd, out=v2)
+        pl.back(vd, out=b2)
+        torch.cuda.synchronize()
+        kav = {k: v["total_ms"] / v["launches"] for k, v in kt.items()}
+        all_taps = {"pairs_per_s": 1000.0 / ms, "ms_per_pair": ms, "plan": pl.describe(),
+                    "rel_l2_forward_vs_paired": float((v2.double() - vd.double()).norm() / vd.double().norm()),
+                    "rel_l2_back_vs_paired": float((b2.double() - bd.double()).norm() / bd.double().norm()),
+                    "kernels_ms_per_launch": kav,
+                    "conv_fwd_tflops": op_flops / (kav["conv_fwd"] * 1e-3) / 1e12,
+                    "conv_back_tflops": op_flops / (kav["conv_back"] * 1e-3) / 1e12}
+        pl.close()
+        del pl, v2, b2
 
     # Reduced-precision convolution (not part of `value`): the same pair with
     # BF16 / FP16 matrix-core operands, and with split-BF16 operands (three
@@ -508,13 +556,14 @@ def main():
         "config": {"workload": "paper-scale FP32 projector pair: 128x128x80 volume (4.8 mm), "
                                "128 views over 360 deg, 37x37 depth/view-dependent Gaussian PSF",
                    "nx": nx, "ny": ny, "nz": nz, "nview": nview, "px": px, "pz": pz,
-                   "cache_mubar": bool(args.cache_mubar)},
+                   "cache_mubar": bool(args.cache_mubar), "plan": sel},
         "pair_latency_ms": {"p50": pct(step_ms, 50), "p99": pct(step_ms, 99),
                             "p10": pct(step_ms, 10), "p90": pct(step_ms, 90)},
         "wall_s_timed": wall,
         "em_recon_latency": em,
         "unrolled_em_grad": grad,
         "reduced_precision": lp,
+        "all_taps": all_taps,
         "bilinear_rotation": bil,
         "separable_psf": sep,
         "large_precision": large,

@@ -120,7 +120,14 @@ spect_status spect_workspace_bytes(const spect_geom* g, size_t* bytes);
  * the z factor then the x factor), d_workspace: device memory of ws_bytes
  * (>= spect_workspace_bytes, 256-byte aligned).  All three are borrowed.
  * Enqueues the upload of the per-view shear tables (and, with
- * SPECT_CACHE_MUBAR, the attenuation-factor precomputation) on `stream`. */
+ * SPECT_CACHE_MUBAR, the attenuation-factor precomputation) on `stream`.
+ * When the FP32 convolution runs on 4x4 blocks, it also checks on the device
+ * whether every PSF row is its own mirror image in x (p[b][a] == p[b][px-1-a]
+ * exactly, as for a centred Gaussian or any circularly symmetric response);
+ * if so the convolution pairs taps a and px-1-a, adding the two input columns
+ * before one product ((px + 1) / 2 products per row instead of px, the same
+ * operator up to FP32 rounding).  That check waits for `stream`.  Setting the
+ * environment variable SPECT_PSF_MIRROR=0 skips it and keeps every tap. */
 spect_status spect_plan_create(spect_plan* out, const spect_geom* g,
                                const float* d_mu, const float* d_psf,
                                void* d_workspace, size_t ws_bytes,
@@ -208,6 +215,13 @@ spect_status spect_profile_stop(spect_plan plan, spect_kernel_time* out, int32_t
 
 /* Library version string. */
 const char* spect_version(void);
+
+/* The kernels a plan selected, as one line of key=value pairs written to buf
+ * (NUL-terminated, truncated to len bytes): conv = fp32-4x4 | fp32-16x16 |
+ * separable | bf16 | fp16 | bf16x3, mirror = 1 when the FP32 4x4-block
+ * convolution pairs mirror-image taps (see spect_plan_create), rotation =
+ * 3pass | bilinear, view_batch, nchunk.  Host only. */
+spect_status spect_plan_describe(spect_plan plan, char* buf, size_t len);
 
 #ifdef __cplusplus
 }

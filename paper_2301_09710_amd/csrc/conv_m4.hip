@@ -38,6 +38,8 @@
 // fixed order afterwards.  Adjoint: the projection region is staged once with
 // zero padding and every depth plane of the chunk is computed from it with its
 // own PSF; the edge rows and columns are rewritten by conv_back_edges.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace spect {
@@ -53,7 +55,9 @@ constexpr int kMaxPsf = 4096;  // PSF table elements (px * PL4)
 
 // A workgroup of NW waves (4 or 8) covers the same 32 BX columns either way:
 // each wave's blocks hold 8 / NW x tiles.  With 8 waves every SIMD runs two
-// of them, so one wave's LDS waits and barriers overlap the other's MFMAs.
+// of them, so one wave's LDS waits and barriers overlap the other's MFMAs;
+// the kernels are built with 8.
+constexpr int kM4Waves = 8;
 template <int NW>
 struct Waves {
   static constexpr int kXt = 8 / NW;             // x tiles (4 columns each) per block
@@ -86,50 +90,60 @@ __device__ __forceinline__ void chunk_range(int c, int nchunk, int ny, int& j0, 
 // advanced by PL4 per tap, read at offset (ND - 1 - t) forward or t adjoint
 // for step t; pb = RT + pb_lane (tap 0, x tile 0), moved by -RRS (forward) or
 // +RRS (adjoint) per tap, x tile j at +4 j RRS, input row r at +r.
-template <int ND4, int kXt, bool kBack>
+// kMirror (PSF rows symmetric in x): tap a also stands for tap px - 1 - a,
+// whose input column pb2 = RT + pb2_lane moves the opposite way; the two
+// columns are added before the product, and ntap = ha + 1 (the centre tap's
+// PSF column is stored halved and meets its own column twice).
+template <int ND4, int kXt, bool kBack, bool kMirror>
 __device__ __forceinline__ void m4_plane(const float* __restrict__ P, const float* __restrict__ RT,
-                                         int pa_lane, int pb_lane, int PL4, int RRS, int px,
-                                         floatx4 (&acc)[kZt][kXt]) {
+                                         int pa_lane, int pb_lane, int pb2_lane, int PL4, int RRS,
+                                         int ntap, floatx4 (&acc)[kZt][kXt]) {
   constexpr int ND = 4 * ND4;                 // steps per tap
   constexpr int NR = 4 * (kZt - 1) + ND;      // input rows per tap
   float A[ND], B[NR][kXt];
   const int tstep = kBack ? RRS : -RRS;
   const int xstep = 4 * RRS;
+  auto rd = [&](const float* pb, const float* pb2, int off) {
+    return kMirror ? pb[off] + pb2[off] : pb[off];
+  };
   // operands first used at step t of a tap: its A value and the input rows
   // t + 4 i (t < 4: every tile's first row) or t + 4 (kZt - 1) (later steps)
-  auto load = [&](int t, const float* pa, const float* pb) {
+  auto load = [&](int t, const float* pa, const float* pb, const float* pb2) {
     A[t] = pa[kBack ? t : ND - 1 - t];
     if (t < 4) {
 #pragma unroll
       for (int i = 0; i < kZt; ++i)
 #pragma unroll
-        for (int j = 0; j < kXt; ++j) B[t + 4 * i][j] = pb[j * xstep + t + 4 * i];
+        for (int j = 0; j < kXt; ++j) B[t + 4 * i][j] = rd(pb, pb2, j * xstep + t + 4 * i);
     } else {
 #pragma unroll
-      for (int j = 0; j < kXt; ++j) B[t + 4 * (kZt - 1)][j] = pb[j * xstep + t + 4 * (kZt - 1)];
+      for (int j = 0; j < kXt; ++j)
+        B[t + 4 * (kZt - 1)][j] = rd(pb, pb2, j * xstep + t + 4 * (kZt - 1));
     }
   };
   const float* pa = P + pa_lane;
   const float* pb = RT + pb_lane;
+  const float* pb2 = RT + pb2_lane;
 #pragma unroll
-  for (int t = 0; t < kLook; ++t) load(t, pa, pb);
-  for (int a = 0; a < px; ++a) {
-    const int an = a + 1 < px ? a + 1 : a;    // the last tap reloads itself (values unused)
+  for (int t = 0; t < kLook; ++t) load(t, pa, pb, pb2);
+  for (int a = 0; a < ntap; ++a) {
+    const int an = a + 1 < ntap ? a + 1 : a;  // the last tap reloads itself (values unused)
     const float* pan = P + pa_lane + an * PL4;
     const float* pbn = RT + pb_lane + an * tstep;
+    const float* pb2n = RT + pb2_lane - an * tstep;
     float An[kLook], Bn[kLook][kZt][kXt];
 #pragma unroll
     for (int s = 0; s < ND; ++s) {
       const int t = s + kLook;
       if (t < ND) {
-        load(t, pa, pb);
+        load(t, pa, pb, pb2);
       } else {
         const int u = t - ND;                   // < kLook <= 4: rows u + 4 i of the next tap
         An[u] = pan[kBack ? u : ND - 1 - u];
 #pragma unroll
         for (int i = 0; i < kZt; ++i)
 #pragma unroll
-          for (int j = 0; j < kXt; ++j) Bn[u][i][j] = pbn[j * xstep + u + 4 * i];
+          for (int j = 0; j < kXt; ++j) Bn[u][i][j] = rd(pbn, pb2n, j * xstep + u + 4 * i);
       }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -148,32 +162,37 @@ __device__ __forceinline__ void m4_plane(const float* __restrict__ P, const floa
     }
     pa = pan;
     pb = pbn;
+    pb2 = pb2n;
   }
 }
 
 // PSF table of one plane: P[a PL4 + t] = p[t - Z][a] (zero outside the taps),
 // Z = ND - pz forward (column reversed by the read order), 3 adjoint.
-template <int NW>
+// kMirror: columns a = 0 .. ha only, the centre column halved (exact).
+template <int NW, bool kMirror>
 struct PsfTable {
   static constexpr int kPfPsf = Waves<NW>::kPfPsf;
   float v[kPfPsf];
   __device__ __forceinline__ void load(const M4Shape& s, const float* __restrict__ pj, int Z) {
+    const int ncol = kMirror ? s.ha + 1 : s.px;
 #pragma unroll
     for (int u = 0; u < kPfPsf; ++u) {
       const int e = threadIdx.x + Waves<NW>::kThreads * u;
       float x = 0.0f;
-      if (e < s.px * s.PL4) {
+      if (e < ncol * s.PL4) {
         const int a = e / s.PL4, b = e - a * s.PL4 - Z;
         if (b >= 0 && b < s.pz) x = pj[b * s.px + a];
+        if (kMirror && a == s.ha) x *= 0.5f;
       }
       v[u] = x;
     }
   }
   __device__ __forceinline__ void store(const M4Shape& s, float* P) const {
+    const int ncol = kMirror ? s.ha + 1 : s.px;
 #pragma unroll
     for (int u = 0; u < kPfPsf; ++u) {
       const int e = threadIdx.x + Waves<NW>::kThreads * u;
-      if (e < s.px * s.PL4) P[e] = v[u];
+      if (e < ncol * s.PL4) P[e] = v[u];
     }
   }
 };
@@ -211,7 +230,7 @@ struct FwdRegion {
 };
 
 // ---------------------------------------------------------------- forward
-template <int ND4, int NW>
+template <int ND4, int NW, bool kMirror>
 __global__ __launch_bounds__(64 * NW, 1) void conv_fwd_m4(const float* __restrict__ W,
                                                       const float* __restrict__ psf,
                                                       float* __restrict__ partial, M4Shape s,
@@ -240,6 +259,8 @@ __global__ __launch_bounds__(64 * NW, 1) void conv_fwd_m4(const float* __restric
   // B (x tile j, row r) = RT[(xo + 4 j + q + 2 ha - a) RRS + zb + r]
   const int pa_lane = q;
   const int pb_lane = (xo + q + 2 * s.ha) * s.RRS + zb;
+  const int pb2_lane = (xo + q) * s.RRS + zb;            // mirror tap px - 1 - a
+  const int ntap = kMirror ? s.ha + 1 : s.px;
 
   floatx4 tot[kZt][kXt];
 #pragma unroll
@@ -247,7 +268,7 @@ __global__ __launch_bounds__(64 * NW, 1) void conv_fwd_m4(const float* __restric
 #pragma unroll
     for (int j = 0; j < kXt; ++j) tot[i][j] = {0.f, 0.f, 0.f, 0.f};
   FwdRegion<NW> reg;
-  PsfTable<NW> tab;
+  PsfTable<NW, kMirror> tab;
   if (j0 < j1) {
     reg.load(s, Wl + (size_t)j0 * s.nx, k0, i0, row_stride, w, lane);
     tab.load(s, psf_l + (size_t)j0 * s.pz * s.px, Z);
@@ -266,7 +287,7 @@ __global__ __launch_bounds__(64 * NW, 1) void conv_fwd_m4(const float* __restric
     for (int i = 0; i < kZt; ++i)
 #pragma unroll
       for (int jj = 0; jj < kXt; ++jj) acc[i][jj] = {0.f, 0.f, 0.f, 0.f};
-    m4_plane<ND4, kXt, false>(P, RT, pa_lane, pb_lane, s.PL4, s.RRS, s.px, acc);
+    m4_plane<ND4, kXt, false, kMirror>(P, RT, pa_lane, pb_lane, pb2_lane, s.PL4, s.RRS, ntap, acc);
 #pragma unroll
     for (int i = 0; i < kZt; ++i)
 #pragma unroll
@@ -290,7 +311,7 @@ __global__ __launch_bounds__(64 * NW, 1) void conv_fwd_m4(const float* __restric
 // ---------------------------------------------------------------- adjoint
 // u[k][i] = sum_{a,b} p[b][a] v[k + b - hb][i + a - ha] (v zero outside) for
 // every bin of the tile and every plane of the chunk.
-template <int ND4, int NW>
+template <int ND4, int NW, bool kMirror>
 __global__ __launch_bounds__(64 * NW, 1) void conv_back_m4(const float* __restrict__ v,
                                                        const float* __restrict__ psf,
                                                        float* __restrict__ U, M4Shape s,
@@ -324,7 +345,9 @@ __global__ __launch_bounds__(64 * NW, 1) void conv_back_m4(const float* __restri
   // B (x tile j, row r) = RT[(xo + 4 j + q + a) RRS + zb + r]
   const int pa_lane = 3 - q;
   const int pb_lane = (xo + q) * s.RRS + zb;
-  PsfTable<NW> tab;
+  const int pb2_lane = (xo + q + 2 * s.ha) * s.RRS + zb;  // mirror tap px - 1 - a
+  const int ntap = kMirror ? s.ha + 1 : s.px;
+  PsfTable<NW, kMirror> tab;
   if (j0 < j1) tab.load(s, psf_l + (size_t)j0 * s.pz * s.px, 3);
   for (int j = j0; j < j1; ++j) {
     __syncthreads();                               // region staged / previous plane consumed
@@ -336,7 +359,7 @@ __global__ __launch_bounds__(64 * NW, 1) void conv_back_m4(const float* __restri
     for (int i = 0; i < kZt; ++i)
 #pragma unroll
       for (int jj = 0; jj < kXt; ++jj) acc[i][jj] = {0.f, 0.f, 0.f, 0.f};
-    m4_plane<ND4, kXt, true>(P, RT, pa_lane, pb_lane, s.PL4, s.RRS, s.px, acc);
+    m4_plane<ND4, kXt, true, kMirror>(P, RT, pa_lane, pb_lane, pb2_lane, s.PL4, s.RRS, ntap, acc);
     float* out = U + (size_t)lb * s.nz * s.ny * s.nx + (size_t)j * s.nx;
 #pragma unroll
     for (int i = 0; i < kZt; ++i)
@@ -352,6 +375,24 @@ __global__ __launch_bounds__(64 * NW, 1) void conv_back_m4(const float* __restri
   }
 }
 
+// ---------------------------------------------------------------- PSF symmetry
+// flag = 1, then 0 if any PSF row differs from its mirror image in x
+// (exact comparison; a NaN counts as a difference).
+__global__ void psf_mirror_flag_init(int* flag) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 1;
+}
+
+__global__ void psf_mirror_check(const float* __restrict__ psf, long long pairs, int px, int ha,
+                                 int* flag) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < pairs; e += stride) {
+    const long long r = e / ha;
+    const int a = (int)(e - r * ha);
+    const float* row = psf + r * px;
+    if (!(row[a] == row[px - 1 - a])) *flag = 0;
+  }
+}
+
 #define SPECT_M4_CASES(X) \
   X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 
@@ -359,42 +400,42 @@ size_t m4_lds_bytes(const M4Shape& s) {
   return ((size_t)s.RC * s.RRS + (size_t)s.px * s.PL4) * sizeof(float);
 }
 
-template <int ND4, int NW>
+template <int ND4, int NW, bool kMirror>
 hipError_t launch_m4_nw(const M4Shape& s, bool back, const float* in, const float* psf, float* out,
                         int view0, int nvb, hipStream_t st) {
   const size_t sm = m4_lds_bytes(s);
-  const void* fn = back ? (const void*)conv_back_m4<ND4, NW> : (const void*)conv_fwd_m4<ND4, NW>;
+  const void* fn = back ? (const void*)conv_back_m4<ND4, NW, kMirror>
+                        : (const void*)conv_fwd_m4<ND4, NW, kMirror>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
   if (e != hipSuccess) return e;
   dim3 grid(s.tiles_k * s.tiles_i * (back ? s.nchunk_back : s.nchunk) * nvb);
   dim3 block(Waves<NW>::kThreads);
   if (back)
-    hipLaunchKernelGGL((conv_back_m4<ND4, NW>), grid, block, sm, st, in, psf, out, s, view0, nvb);
+    hipLaunchKernelGGL((conv_back_m4<ND4, NW, kMirror>), grid, block, sm, st, in, psf, out, s, view0,
+                       nvb);
   else
-    hipLaunchKernelGGL((conv_fwd_m4<ND4, NW>), grid, block, sm, st, in, psf, out, s, view0, nvb);
+    hipLaunchKernelGGL((conv_fwd_m4<ND4, NW, kMirror>), grid, block, sm, st, in, psf, out, s, view0,
+                       nvb);
   return hipGetLastError();
 }
 
 template <int ND4>
 hipError_t launch_m4(const M4Shape& s, bool back, const float* in, const float* psf, float* out,
                      int view0, int nvb, hipStream_t st) {
-  return s.NW == 8 ? launch_m4_nw<ND4, 8>(s, back, in, psf, out, view0, nvb, st)
-                   : launch_m4_nw<ND4, 4>(s, back, in, psf, out, view0, nvb, st);
+  return s.mirror ? launch_m4_nw<ND4, kM4Waves, true>(s, back, in, psf, out, view0, nvb, st)
+                  : launch_m4_nw<ND4, kM4Waves, false>(s, back, in, psf, out, view0, nvb, st);
 }
 
-template <int ND4, int NW>
-int m4_wgs_per_cu_nw(const M4Shape& s, bool back) {
-  int nb = 0;
-  const void* fn = back ? (const void*)conv_back_m4<ND4, NW> : (const void*)conv_fwd_m4<ND4, NW>;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, Waves<NW>::kThreads, m4_lds_bytes(s)) !=
-      hipSuccess)
-    nb = 0;
-  return nb < 1 ? 1 : nb;
-}
-
+// Workgroups per CU (the same for the paired-tap form: same LDS, fewer registers).
 template <int ND4>
 int m4_wgs_per_cu(const M4Shape& s, bool back) {
-  return s.NW == 8 ? m4_wgs_per_cu_nw<ND4, 8>(s, back) : m4_wgs_per_cu_nw<ND4, 4>(s, back);
+  int nb = 0;
+  const void* fn = back ? (const void*)conv_back_m4<ND4, kM4Waves, false>
+                        : (const void*)conv_fwd_m4<ND4, kM4Waves, false>;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, Waves<kM4Waves>::kThreads,
+                                                   m4_lds_bytes(s)) != hipSuccess)
+    nb = 0;
+  return nb < 1 ? 1 : nb;
 }
 
 // Largest number of lanes of one half wave (32 lanes) that share an LDS bank
@@ -427,7 +468,7 @@ int m4_pick_chunks(int ny, long long tiles_views, long long slots) {
 
 }  // namespace
 
-M4Shape make_m4_shape(const spect_geom& g, int NW) {
+M4Shape make_m4_shape(const spect_geom& g) {
   M4Shape best{};
   best.ok = false;
   double best_area = 0.0;
@@ -437,7 +478,7 @@ M4Shape make_m4_shape(const spect_geom& g, int NW) {
     s.nx = g.nx; s.ny = g.ny; s.nz = g.nz; s.px = g.px; s.pz = g.pz;
     s.ha = (g.px - 1) / 2; s.hb = (g.pz - 1) / 2;
     s.ND4 = ND4;
-    s.NW = NW == 8 ? 8 : 4;
+    s.mirror = false;
     s.BX = BX;
     s.BZ = 16 / BX;
     s.tiles_k = (g.nz + 4 * kZt * s.BZ - 1) / (4 * kZt * s.BZ);
@@ -447,7 +488,7 @@ M4Shape make_m4_shape(const spect_geom& g, int NW) {
     s.PL4 = 4 * ND4 + 3;
     int rrs = s.RR | 1, best_rrs = rrs, best_conf = 1 << 30;
     for (; rrs < s.RR + 64; rrs += 2) {
-      const int cf = m4_bank_conflicts(rrs, BX, 8 / s.NW);
+      const int cf = m4_bank_conflicts(rrs, BX, Waves<kM4Waves>::kXt);
       if (cf < best_conf) { best_conf = cf; best_rrs = rrs; }
       if (cf <= 1) break;
     }
@@ -490,6 +531,24 @@ void tune_m4_chunks(M4Shape& s, int views) {
   const long long tv = (long long)s.tiles_k * s.tiles_i * views;
   s.nchunk = m4_pick_chunks(s.ny, tv, (long long)cus * fw);
   s.nchunk_back = m4_pick_chunks(s.ny, tv, (long long)cus * bw);
+}
+
+hipError_t detect_m4_mirror(Plan& p, int* d_flag, hipStream_t st) {
+  p.m4.mirror = false;
+  const long long pairs = (long long)p.g.nview * p.g.ny * p.g.pz * p.m4.ha;
+  hipLaunchKernelGGL(psf_mirror_flag_init, dim3(1), dim3(64), 0, st, d_flag);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && pairs > 0) {
+    const long long blocks = std::min<long long>((pairs + 255) / 256, 4096);
+    hipLaunchKernelGGL(psf_mirror_check, dim3((unsigned)blocks), dim3(256), 0, st, p.psf, pairs,
+                       p.g.px, p.m4.ha, d_flag);
+    e = hipGetLastError();
+  }
+  int h = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&h, d_flag, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess) p.m4.mirror = h == 1;
+  return e;
 }
 
 hipError_t launch_conv_m4(const Plan& p, bool back, const float* in, float* out, int view0,

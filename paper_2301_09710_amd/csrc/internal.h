@@ -51,7 +51,7 @@ struct ConvShape {
 struct M4Shape {
   int nx, ny, nz, px, pz, ha, hb;
   int ND4;              // steps per tap / 4: ceil((pz + 3) / 4)
-  int NW;               // waves per workgroup (4 or 8)
+  bool mirror;          // PSF rows symmetric in x: taps a and px-1-a share one product
   int BZ, BX;           // blocks of a wave along z and x (BZ * BX = 16)
   int tiles_k, tiles_i; // workgroup tiles of 20 BZ x 32 BX output bins
   int RR, RC, RRS;      // region rows (z), columns (x), column stride in LDS
@@ -188,10 +188,13 @@ ConvShape make_conv_shape(const spect_geom& g, int jc_fwd, int jc_back);
 void tune_conv_chunks(ConvShape& cs, int views);
 size_t conv_mfma_lds_bytes(const ConvShape& cs, bool back);
 size_t conv_edges_lds_bytes(const ConvShape& cs);
-M4Shape make_m4_shape(const spect_geom& g, int NW);
+M4Shape make_m4_shape(const spect_geom& g);
 // Whether the 4x4-block tiling issues fewer matrix-core cycles than the 16x16 one.
 bool m4_preferred(const M4Shape& s, const ConvShape& cs);
 void tune_m4_chunks(M4Shape& s, int views);
+// Sets p.m4.mirror: whether every PSF row equals its mirror image in x
+// (checked on the device with the 4-byte scratch d_flag; waits for st).
+hipError_t detect_m4_mirror(Plan& p, int* d_flag, hipStream_t st);
 SepShape make_sep_shape(const spect_geom& g);
 size_t sep_lds_bytes(const SepShape& s, bool back);
 void tune_sep_chunks(SepShape& s, int views);

@@ -1,6 +1,7 @@
 // C ABI of libspect: plan creation (host FP64 geometry tables, workspace
 // layout, argument validation) and the entry points that chain the kernels.
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -161,6 +162,21 @@ extern "C" {
 
 const char* spect_version(void) { return "libspect 0.1 (gfx950)"; }
 
+spect_status spect_plan_describe(spect_plan plan, char* buf, size_t len) {
+  if (!plan || !buf) return SPECT_ERR_NULL;
+  if (len == 0) return SPECT_ERR_VALUE;
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  static const char* const kLp[] = {"fp32", "bf16", "fp16", "bf16x3"};
+  const char* conv = p->separable ? "separable"
+                     : p->conv_precision != SPECT_CONV_FP32 ? kLp[p->conv_precision & 3]
+                     : p->use_m4 ? "fp32-4x4"
+                                 : "fp32-16x16";
+  const bool mirror = p->use_m4 && p->conv_precision == SPECT_CONV_FP32 && p->m4.mirror;
+  std::snprintf(buf, len, "conv=%s mirror=%d rotation=%s view_batch=%d nchunk=%d", conv,
+                mirror ? 1 : 0, p->bilinear ? "bilinear" : "3pass", p->view_batch, p->nchunk);
+  return SPECT_OK;
+}
+
 const char* spect_status_string(spect_status s) {
   switch (s) {
     case SPECT_OK: return "ok";
@@ -240,9 +256,7 @@ spect_status spect_plan_create(spect_plan* out, const spect_geom* g, const float
   p->rot_scratch = g->nx > kMaxLdsN ? reinterpret_cast<float*>(p->ws + lay.rot_scratch) : nullptr;
   p->use_mfma = conv_mfma_supported(*g);
   p->conv = make_conv_shape(*g, kFwdJChunk, kBackJChunk);
-  // SPECT_M4_WAVES = 4 or 8 selects the waves per workgroup of the 4x4-block kernels
-  const char* m4w = std::getenv("SPECT_M4_WAVES");
-  p->m4 = make_m4_shape(*g, m4w && std::atoi(m4w) == 4 ? 4 : 8);
+  p->m4 = make_m4_shape(*g);
   p->use_m4 = false;
   p->separable = (g->flags & SPECT_PSF_SEPARABLE) != 0;
   if (p->separable) {
@@ -269,6 +283,14 @@ spect_status spect_plan_create(spect_plan* out, const spect_geom* g, const float
     p->lp = make_lp_shape(*g);
     tune_lp_chunks(p->lp, g->nview, p->conv_precision);
     p->nchunk = p->lp.nchunk;
+  }
+  // PSF rows symmetric in x (a centred Gaussian, any circularly symmetric
+  // response): the 4x4-block kernels pair taps a and px-1-a.  Checked exactly
+  // on the device; SPECT_PSF_MIRROR=0 keeps every tap.
+  if (e == hipSuccess && p->use_m4 && p->conv_precision == SPECT_CONV_FP32) {
+    const char* mirror = std::getenv("SPECT_PSF_MIRROR");
+    if (!(mirror && std::strcmp(mirror, "0") == 0))
+      e = detect_m4_mirror(*p, reinterpret_cast<int*>(p->ws + lay.em_vol), stream);
   }
   if (g->flags & SPECT_CACHE_MUBAR) {
     float* cache = reinterpret_cast<float*>(p->ws + lay.mubar_cache);

@@ -31,7 +31,7 @@ STATUS_NAMES = {
 }
 EXPORTED = ("spect_workspace_bytes", "spect_plan_create", "spect_forward", "spect_back",
             "spect_em_step", "spect_reg_em_step", "spect_em_step_vjp", "spect_plan_destroy", "spect_status_string", "spect_dot_f64",
-            "spect_profile_start", "spect_profile_stop", "spect_version")
+            "spect_profile_start", "spect_profile_stop", "spect_version", "spect_plan_describe")
 
 
 class SpectError(RuntimeError):
@@ -84,6 +84,8 @@ def _lib():
         lib.spect_status_string.restype = c_char_p
         lib.spect_version.argtypes = []
         lib.spect_version.restype = c_char_p
+        lib.spect_plan_describe.argtypes = [c_void_p, ctypes.c_char_p, c_size_t]
+        lib.spect_plan_describe.restype = c_int
         _LIB = lib
     return _LIB
 
@@ -190,6 +192,15 @@ def spect_version() -> str:
     return _lib().spect_version().decode()
 
 
+def spect_plan_describe(plan: int) -> dict:
+    """The plan's kernel selection as a dict of strings (host only)."""
+    buf = ctypes.create_string_buffer(256)
+    st = _lib().spect_plan_describe(plan, buf, len(buf))
+    if st != 0:
+        raise SpectError(st, "spect_plan_describe")
+    return dict(kv.split("=", 1) for kv in buf.value.decode().split())
+
+
 # ---------------------------------------------------------------- torch wrapper
 
 def _stream(torch, device):
@@ -257,6 +268,10 @@ class Plan:
         self._plan = spect_plan_create(self._geom, mu.data_ptr(), psf.data_ptr(),
                                        self._ws.data_ptr(), self.ws_bytes,
                                        _stream(torch, self.device))
+
+    def describe(self) -> dict:
+        """Kernels this plan selected (conv, mirror, rotation, view_batch, nchunk)."""
+        return spect_plan_describe(self._plan)
 
     @property
     def vol_shape(self):

@@ -29,6 +29,13 @@ def test_library_exports_every_declared_symbol():
     assert "gfx950" in spect.spect_version()
 
 
+def test_plan_describe_rejects_null():
+    lib = spect.load()
+    buf = ctypes.create_string_buffer(64)
+    assert lib.spect_plan_describe(None, buf, 64) == 1
+    assert lib.spect_plan_describe(ctypes.c_void_p(1), None, 64) == 1
+
+
 def test_status_strings():
     lib = spect.load()
     for s in range(8):

@@ -1,6 +1,7 @@
 """The two FP32 tilings of the PSF convolution, each forced at plan creation
 through SPECT_FP32_TILING: 16x16x4 Toeplitz blocks ("16x16") and 4x4x1 blocks
-("4x4", with 8 or 4 waves per workgroup through SPECT_M4_WAVES), against the
+("4x4", which pairs mirror-image taps when the PSF rows are symmetric in x;
+"4x4/all-taps" turns the pairing off through SPECT_PSF_MIRROR=0), against the
 FP64 oracle.
 
 The plan picks a tiling per shape from its cost model (4x4 blocks at the
@@ -29,14 +30,20 @@ from paper_2301_09710_amd import spect  # noqa: E402
 
 DEV = torch.device("cuda:0")
 TOL = 1e-5
-TILINGS = ["4x4", "4x4/4w", "16x16"]
+TILINGS = ["4x4", "4x4/all-taps", "16x16"]
 
 
 def force(monkeypatch, tiling):
-    """Select a tiling (and the 4x4 kernels' waves per workgroup) for the
-    plans created next."""
+    """Select a tiling (and whether the 4x4 kernels may pair mirror-image
+    taps) for the plans created next."""
     monkeypatch.setenv("SPECT_FP32_TILING", tiling.split("/")[0])
-    monkeypatch.setenv("SPECT_M4_WAVES", "4" if tiling.endswith("/4w") else "8")
+    monkeypatch.setenv("SPECT_PSF_MIRROR", "0" if tiling.endswith("/all-taps") else "1")
+
+
+def check_selection(plan, tiling, symmetric):
+    d = plan.describe()
+    assert d["conv"] == ("fp32-16x16" if tiling == "16x16" else "fp32-4x4"), d
+    assert d["mirror"] == ("1" if tiling == "4x4" and symmetric else "0"), d
 
 
 def say(msg):
@@ -83,6 +90,7 @@ def test_tiling_parity(case, tiling, monkeypatch):
     dy = 1.5
     g = Geometry(nx, nx, nz, nview, px, pz, dy)
     plan = spect.Plan(to_dev(mu), to_dev(psf), dy)
+    check_selection(plan, tiling, sym)
     v = host(plan.forward(to_dev(x)))
     ef = rel_l2(v, oracle.forward(x, mu, psf, g))
     y = synth.random_volume(nx, nz, nview, seed=seed + 3)
@@ -137,6 +145,7 @@ def test_tiling_paper_sampled(paper, tiling, monkeypatch):
     force(monkeypatch, tiling)
     say(f"tiling {tiling}: paper size")
     plan = spect.Plan(to_dev(paper["mu"]), to_dev(paper["psf"]), paper["dy"], cache_mubar=True)
+    check_selection(plan, tiling, True)
     xd = to_dev(paper["x"])
     v = host(plan.forward(xd))
     ef = max(rel_l2(v[l], paper["v_ref"][l]) for l in paper["views"])

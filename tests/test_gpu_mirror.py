@@ -1,0 +1,160 @@
+"""Mirror-image tap pairing of the FP32 4x4-block convolution: when every PSF
+row is symmetric in x (p[b][a] == p[b][px-1-a], as for the paper's Gaussian
+responses), taps a and px-1-a share one matrix product on the sum of their
+two input columns.  The plan detects the symmetry exactly on the device.
+
+Checks: the selection itself (symmetric PSFs pair, a PSF one ulp away from
+symmetric does not, SPECT_PSF_MIRROR=0 turns pairing off); parity with the
+FP64 oracle at 1e-5 relative L2 on ragged tiles, a one-tap row, a kernel
+wider than the plane, a z-only kernel and several z tiles; the explicit
+matrix adjoint B = A^T within 1e-6; and agreement with the all-taps kernels
+at the paper's 128x128x80 / 37x37 size."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.projector import Geometry
+from paper_2301_09710_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2301_09710_amd import spect  # noqa: E402
+
+DEV = torch.device("cuda:0")
+TOL = 1e-5
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.fixture(autouse=True)
+def four_by_four(monkeypatch):
+    monkeypatch.setenv("SPECT_FP32_TILING", "4x4")
+    monkeypatch.setenv("SPECT_PSF_MIRROR", "1")
+
+
+CASES = [
+    # nx, nz, nview, px, pz
+    (32, 20, 6, 7, 7),
+    (37, 13, 5, 9, 5),        # ragged x and z tiles
+    (16, 1, 3, 41, 3),        # kernel wider than the plane, one slice
+    (20, 9, 4, 1, 5),         # one tap along x: the centre column only
+    (70, 85, 3, 11, 13),      # two z tiles
+    (48, 41, 4, 19, 21),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_mirror_parity(case):
+    nx, nz, nview, px, pz = case
+    say(f"mirror {case}")
+    seed = 11 * nx + nz
+    x = synth.random_volume(nx, nx, nz, seed=seed)
+    mu = synth.random_volume(nx, nx, nz, seed=seed + 1, high=0.05)
+    psf = synth.random_psf(px, pz, nx, nview, seed=seed + 2, symmetric=True)
+    assert np.array_equal(psf, psf[..., ::-1])
+    g = Geometry(nx, nx, nz, nview, px, pz, 1.5)
+    plan = spect.Plan(to_dev(mu), to_dev(psf), 1.5)
+    assert plan.describe()["mirror"] == "1", plan.describe()
+    ef = rel_l2(host(plan.forward(to_dev(x))), oracle.forward(x, mu, psf, g))
+    y = synth.random_volume(nx, nz, nview, seed=seed + 3)
+    eb = rel_l2(host(plan.back(to_dev(y))), oracle.back(y, mu, psf, g))
+    say(f"  forward {ef:.2e}, back {eb:.2e}")
+    assert ef <= TOL and eb <= TOL
+
+
+def test_one_ulp_from_symmetric_keeps_every_tap():
+    """A single entry nudged by one ulp: the check must see it, and the
+    all-taps kernels then give the oracle's result for that PSF."""
+    nx, nz, nview, px, pz = 24, 10, 4, 9, 7
+    x = synth.random_volume(nx, nx, nz, seed=5)
+    mu = synth.random_volume(nx, nx, nz, seed=6, high=0.05)
+    psf = synth.random_psf(px, pz, nx, nview, seed=7, symmetric=True)
+    psf[3, 17, 2, 1] = np.nextafter(psf[3, 17, 2, 1], np.float32(1.0))
+    plan = spect.Plan(to_dev(mu), to_dev(psf), 1.2)
+    assert plan.describe()["mirror"] == "0", plan.describe()
+    g = Geometry(nx, nx, nz, nview, px, pz, 1.2)
+    assert rel_l2(host(plan.forward(to_dev(x))), oracle.forward(x, mu, psf, g)) <= TOL
+    # the same PSF made symmetric again pairs
+    psf[3, 17, 2, 1] = psf[3, 17, 2, px - 2]
+    assert spect.Plan(to_dev(mu), to_dev(psf), 1.2).describe()["mirror"] == "1"
+
+
+def test_switch_off(monkeypatch):
+    monkeypatch.setenv("SPECT_PSF_MIRROR", "0")
+    x, mu, psf, dy = synth.config_inputs("tiny", seed=1)
+    assert spect.Plan(to_dev(mu), to_dev(psf), dy).describe()["mirror"] == "0"
+
+
+def test_mirror_dense_adjoint():
+    """Explicit A and B on 8x8x6 / 7 views with the paired kernels (the
+    adjoint edge fold stays the all-taps kernel): B = A^T and A = the
+    oracle's matrix, both within 1e-6."""
+    nx, nz, nview, px = 8, 6, 7, 5
+    N, M = nx * nx * nz, nview * nz * nx
+    eyeN = torch.eye(N, device=DEV).reshape(N, nz, nx, nx)
+    eyeM = torch.eye(M, device=DEV).reshape(M, nview, nz, nx)
+    mu = synth.random_volume(nx, nx, nz, seed=31, high=0.3)
+    psf = synth.random_psf(px, px, nx, nview, seed=32, symmetric=True)
+    plan = spect.Plan(to_dev(mu), to_dev(psf), 1.0)
+    assert plan.describe()["mirror"] == "1"
+    At = torch.empty(N, nview, nz, nx, device=DEV)
+    B = torch.empty(M, nz, nx, nx, device=DEV)
+    for c in range(N):
+        plan.forward(eyeN[c], out=At[c])
+    for c in range(M):
+        plan.back(eyeM[c], out=B[c])
+    torch.cuda.synchronize()
+    A = At.reshape(N, M).double().T.cpu().numpy()
+    Bm = B.reshape(M, N).double().T.cpu().numpy()
+    Aref = oracle.dense.forward_matrix(mu, psf, Geometry(nx, nx, nz, nview, px, px, 1.0))
+    et = np.linalg.norm(A.T - Bm) / np.linalg.norm(A)
+    eo = np.linalg.norm(A - Aref) / np.linalg.norm(Aref)
+    say(f"mirror dense: ||A^T - B|| / ||A|| = {et:.2e}, vs oracle {eo:.2e}")
+    assert et <= 1e-6 and eo <= 1e-6
+
+
+def test_mirror_matches_all_taps_paper_size(monkeypatch):
+    """128x128x80, 128 views, 37x37 Gaussian PSFs: paired and all-taps
+    kernels agree to FP32 rounding, and the paired pair keeps the adjoint
+    identity at full size."""
+    say("mirror: paper size")
+    x, mu, psf, dy = synth.config_inputs("paper", seed=3, view_wobble=0.1)
+    xd, mud, psfd = to_dev(x), to_dev(mu), to_dev(psf)
+    yd = to_dev(np.random.default_rng(9).uniform(0.0, 1.0, (128, 80, 128)))
+    paired = spect.Plan(mud, psfd, dy, cache_mubar=True)
+    assert paired.describe()["mirror"] == "1"
+    vp, bp = host(paired.forward(xd)), host(paired.back(yd))
+    lhs = spect.dot_f64(paired.forward(xd), yd)
+    rhs = spect.dot_f64(xd, paired.back(yd))
+    monkeypatch.setenv("SPECT_PSF_MIRROR", "0")
+    full = spect.Plan(mud, psfd, dy, cache_mubar=True)
+    assert full.describe()["mirror"] == "0"
+    ev = rel_l2(vp, host(full.forward(xd)))
+    eb = rel_l2(bp, host(full.back(yd)))
+    gap = abs(lhs - rhs) / abs(lhs)
+    say(f"  forward {ev:.2e}, back {eb:.2e} against all taps; adjoint gap {gap:.2e}")
+    assert ev <= 2e-6 and eb <= 2e-6 and gap <= TOL
