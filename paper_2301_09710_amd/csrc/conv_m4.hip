@@ -39,6 +39,8 @@
 // zero padding and every depth plane of the chunk is computed from it with its
 // own PSF; the edge rows and columns are rewritten by conv_back_edges.
 #include <algorithm>
+#include <type_traits>
+#include <utility>
 
 #include "internal.h"
 
@@ -48,7 +50,7 @@ namespace {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kZt = 5;       // z tiles (4 rows each) per block
-constexpr int kLook = 2;     // steps of operands loaded ahead of their MFMAs
+constexpr int kLook = 2;     // steps of input rows loaded ahead of their MFMAs
 constexpr int kMaxRR = 128;  // region rows
 constexpr int kPfCols = 3;   // 64-column sweeps of a region row (RC <= 192)
 constexpr int kMaxPsf = 4096;  // PSF table elements (px * PL4)
@@ -66,10 +68,6 @@ struct Waves {
   static constexpr int kPfPsf = kMaxPsf / kThreads;  // PSF table elements per thread
 };
 
-__device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
-  return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
-}
-
 __device__ __forceinline__ int clampi(int q, int lo, int hi) { return q < lo ? lo : (q > hi ? hi : q); }
 
 // Workgroup id -> logical id, so that consecutive logical ids (which share
@@ -86,81 +84,118 @@ __device__ __forceinline__ void chunk_range(int c, int nchunk, int ny, int& j0, 
   j1 = (int)(((long long)(c + 1) * ny) / nchunk);
 }
 
-// All taps of one plane into acc.  Lane pointers: pa = P + pa_lane (tap 0),
-// advanced by PL4 per tap, read at offset (ND - 1 - t) forward or t adjoint
-// for step t; pb = RT + pb_lane (tap 0, x tile 0), moved by -RRS (forward) or
-// +RRS (adjoint) per tap, x tile j at +4 j RRS, input row r at +r.
+// Calls f(std::integral_constant<int, i>) for i = 0 .. N-1 (compile-time
+// step indices, so that each step's broadcast block is an immediate).
+template <class F, int... I>
+__device__ __forceinline__ void unroll_seq(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>()), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void unroll(F&& f) {
+  unroll_seq(f, std::make_integer_sequence<int, N>());
+}
+
+// All taps of one plane into acc.
+//   A: every block uses the same PSF column, so lane 4b + q holds the A row q
+//   of step 16 g + b (group g) and each MFMA broadcasts the A operand of the
+//   block that holds its step (cbsz = 4, abid = step mod 16): one LDS read
+//   per 16 steps.  Step t of tap a reads P[a PL4 + q + ND - 1 - t] forward,
+//   P[a PL4 + 3 - q + t] adjoint.
+//   B: pb = RT + pb_lane (tap 0, x tile 0), moved by -RRS (forward) or +RRS
+//   (adjoint) per tap, x tile j at +4 j RRS, input row r at +r.
 // kMirror (PSF rows symmetric in x): tap a also stands for tap px - 1 - a,
 // whose input column pb2 = RT + pb2_lane moves the opposite way; the two
 // columns are added before the product, and ntap = ha + 1 (the centre tap's
 // PSF column is stored halved and meets its own column twice).
 template <int ND4, int kXt, bool kBack, bool kMirror>
 __device__ __forceinline__ void m4_plane(const float* __restrict__ P, const float* __restrict__ RT,
-                                         int pa_lane, int pb_lane, int pb2_lane, int PL4, int RRS,
-                                         int ntap, floatx4 (&acc)[kZt][kXt]) {
+                                         int pb_lane, int pb2_lane, int PL4, int RRS, int ntap,
+                                         floatx4 (&acc)[kZt][kXt]) {
   constexpr int ND = 4 * ND4;                 // steps per tap
   constexpr int NR = 4 * (kZt - 1) + ND;      // input rows per tap
-  float A[ND], B[NR][kXt];
+  constexpr int NF = 4 * kZt;                 // rows first used in steps 0..3 (one per tile)
+  constexpr int NG = (ND + 15) / 16;          // A groups per tap
+  constexpr int NSP = ND >= 16 ? ND - 8 : ND; // steps that carry the next tap's first rows
+  const int lane = threadIdx.x & 63, q = lane & 3, blk = lane >> 2;
+  int aoff[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    const int t = min(16 * g + blk, ND - 1);  // slots past the last step repeat it (unused)
+    aoff[g] = kBack ? 3 - q + t : q + ND - 1 - t;
+  }
+  // X1 (and X2, the mirror tap's column) hold rows as loaded; B, the MFMA
+  // operand, is formed at the row's first step, so no load is waited for
+  // in the step that issues it.
+  float Ag[NG], Agn[NG];
+  float X1[NR][kXt], X2[NR][kXt], B[NR][kXt], N1[NF][kXt], N2[NF][kXt];
   const int tstep = kBack ? RRS : -RRS;
   const int xstep = 4 * RRS;
-  auto rd = [&](const float* pb, const float* pb2, int off) {
-    return kMirror ? pb[off] + pb2[off] : pb[off];
-  };
-  // operands first used at step t of a tap: its A value and the input rows
-  // t + 4 i (t < 4: every tile's first row) or t + 4 (kZt - 1) (later steps)
-  auto load = [&](int t, const float* pa, const float* pb, const float* pb2) {
-    A[t] = pa[kBack ? t : ND - 1 - t];
-    if (t < 4) {
+  auto ld = [&](float (&d1)[kXt], float (&d2)[kXt], const float* pb, const float* pb2, int off) {
 #pragma unroll
-      for (int i = 0; i < kZt; ++i)
-#pragma unroll
-        for (int j = 0; j < kXt; ++j) B[t + 4 * i][j] = rd(pb, pb2, j * xstep + t + 4 * i);
-    } else {
-#pragma unroll
-      for (int j = 0; j < kXt; ++j)
-        B[t + 4 * (kZt - 1)][j] = rd(pb, pb2, j * xstep + t + 4 * (kZt - 1));
+    for (int j = 0; j < kXt; ++j) {
+      d1[j] = pb[j * xstep + off];
+      if (kMirror) d2[j] = pb2[j * xstep + off];
     }
   };
-  const float* pa = P + pa_lane;
+  auto form = [&](int r) {
+#pragma unroll
+    for (int j = 0; j < kXt; ++j) B[r][j] = kMirror ? X1[r][j] + X2[r][j] : X1[r][j];
+  };
+  // k-th of the rows first used in steps 0..3, in order of first use:
+  // row 4 i + u (tile i, step u) for k = u kZt + i
+  auto first_row = [](int k) { return 4 * (k % kZt) + k / kZt; };
   const float* pb = RT + pb_lane;
   const float* pb2 = RT + pb2_lane;
 #pragma unroll
-  for (int t = 0; t < kLook; ++t) load(t, pa, pb, pb2);
+  for (int g = 0; g < NG; ++g) Ag[g] = P[aoff[g]];
+#pragma unroll
+  for (int k = 0; k < NF; ++k) ld(X1[first_row(k)], X2[first_row(k)], pb, pb2, first_row(k));
   for (int a = 0; a < ntap; ++a) {
     const int an = a + 1 < ntap ? a + 1 : a;  // the last tap reloads itself (values unused)
-    const float* pan = P + pa_lane + an * PL4;
+    const float* pan = P + an * PL4;
     const float* pbn = RT + pb_lane + an * tstep;
     const float* pb2n = RT + pb2_lane - an * tstep;
-    float An[kLook], Bn[kLook][kZt][kXt];
+    unroll<ND>([&](auto S) {
+      constexpr int s = decltype(S)::value;
+      // the row first used kLook steps ahead (rows of later steps are
+      // needed by the last tile only)
+      constexpr int t = s + kLook;
+      if constexpr (t >= 4 && t < ND) ld(X1[t + 4 * (kZt - 1)], X2[t + 4 * (kZt - 1)], pb, pb2,
+                                         t + 4 * (kZt - 1));
+      // the next tap's first rows, spread over the first NSP steps
+      if constexpr (s < NSP) {
 #pragma unroll
-    for (int s = 0; s < ND; ++s) {
-      const int t = s + kLook;
-      if (t < ND) {
-        load(t, pa, pb, pb2);
+        for (int k = s * NF / NSP; k < (s + 1) * NF / NSP; ++k) ld(N1[k], N2[k], pbn, pb2n, first_row(k));
+      }
+      if constexpr (s == ND / 2) {
+#pragma unroll
+        for (int g = 0; g < NG; ++g) Agn[g] = pan[aoff[g]];
+      }
+      // operands of the rows first used at this step
+      if constexpr (s < 4) {
+#pragma unroll
+        for (int i = 0; i < kZt; ++i) form(s + 4 * i);
       } else {
-        const int u = t - ND;                   // < kLook <= 4: rows u + 4 i of the next tap
-        An[u] = pan[kBack ? u : ND - 1 - u];
-#pragma unroll
-        for (int i = 0; i < kZt; ++i)
-#pragma unroll
-          for (int j = 0; j < kXt; ++j) Bn[u][i][j] = rd(pbn, pb2n, j * xstep + u + 4 * i);
+        form(s + 4 * (kZt - 1));
       }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int i = 0; i < kZt; ++i)
 #pragma unroll
-        for (int j = 0; j < kXt; ++j) acc[i][j] = mfma4(A[s], B[s + 4 * i][j], acc[i][j]);
+        for (int j = 0; j < kXt; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_4x4x1f32(Ag[s / 16], B[s + 4 * i][j], acc[i][j], 4,
+                                                         s % 16, 0);
       __builtin_amdgcn_sched_barrier(0);
-    }
+    });
 #pragma unroll
-    for (int u = 0; u < kLook; ++u) {
-      A[u] = An[u];
+    for (int g = 0; g < NG; ++g) Ag[g] = Agn[g];
 #pragma unroll
-      for (int i = 0; i < kZt; ++i)
+    for (int k = 0; k < NF; ++k)
 #pragma unroll
-        for (int j = 0; j < kXt; ++j) B[u + 4 * i][j] = Bn[u][i][j];
-    }
-    pa = pan;
+      for (int j = 0; j < kXt; ++j) {
+        X1[first_row(k)][j] = N1[k][j];
+        if (kMirror) X2[first_row(k)][j] = N2[k][j];
+      }
     pb = pbn;
     pb2 = pb2n;
   }
@@ -257,7 +292,6 @@ __global__ __launch_bounds__(64 * NW, 1) void conv_fwd_m4(const float* __restric
   const int Z = ND - s.pz;
   // step t of tap a: A = P[a PL4 + q + ND - 1 - t] = p[2 hb - t + q][a];
   // B (x tile j, row r) = RT[(xo + 4 j + q + 2 ha - a) RRS + zb + r]
-  const int pa_lane = q;
   const int pb_lane = (xo + q + 2 * s.ha) * s.RRS + zb;
   const int pb2_lane = (xo + q) * s.RRS + zb;            // mirror tap px - 1 - a
   const int ntap = kMirror ? s.ha + 1 : s.px;
@@ -287,7 +321,7 @@ __global__ __launch_bounds__(64 * NW, 1) void conv_fwd_m4(const float* __restric
     for (int i = 0; i < kZt; ++i)
 #pragma unroll
       for (int jj = 0; jj < kXt; ++jj) acc[i][jj] = {0.f, 0.f, 0.f, 0.f};
-    m4_plane<ND4, kXt, false, kMirror>(P, RT, pa_lane, pb_lane, pb2_lane, s.PL4, s.RRS, ntap, acc);
+    m4_plane<ND4, kXt, false, kMirror>(P, RT, pb_lane, pb2_lane, s.PL4, s.RRS, ntap, acc);
 #pragma unroll
     for (int i = 0; i < kZt; ++i)
 #pragma unroll
@@ -343,7 +377,6 @@ __global__ __launch_bounds__(64 * NW, 1) void conv_back_m4(const float* __restri
   }
   // step t of tap a: A = P[a PL4 + 3 - q + t] = p[t - q][a];
   // B (x tile j, row r) = RT[(xo + 4 j + q + a) RRS + zb + r]
-  const int pa_lane = 3 - q;
   const int pb_lane = (xo + q) * s.RRS + zb;
   const int pb2_lane = (xo + q + 2 * s.ha) * s.RRS + zb;  // mirror tap px - 1 - a
   const int ntap = kMirror ? s.ha + 1 : s.px;
@@ -359,7 +392,7 @@ __global__ __launch_bounds__(64 * NW, 1) void conv_back_m4(const float* __restri
     for (int i = 0; i < kZt; ++i)
 #pragma unroll
       for (int jj = 0; jj < kXt; ++jj) acc[i][jj] = {0.f, 0.f, 0.f, 0.f};
-    m4_plane<ND4, kXt, true, kMirror>(P, RT, pa_lane, pb_lane, pb2_lane, s.PL4, s.RRS, ntap, acc);
+    m4_plane<ND4, kXt, true, kMirror>(P, RT, pb_lane, pb2_lane, s.PL4, s.RRS, ntap, acc);
     float* out = U + (size_t)lb * s.nz * s.ny * s.nx + (size_t)j * s.nx;
 #pragma unroll
     for (int i = 0; i < kZt; ++i)
