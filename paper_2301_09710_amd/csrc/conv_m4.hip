@@ -18,19 +18,24 @@
 // with b(m, row) the z tap that links output row m to the input row.  For a
 // tile whose first output row lies delta rows before the input row, the A
 // column depends on delta only, so the steps of one tap run over delta: one
-// A value (one LDS read) serves every tile of the step, and each input row is
-// read from LDS once per tap and kept in registers while the tiles that need
-// it pass (rows delta, delta + 4, ..., delta + 4 (kZt - 1)).
+// A value serves every tile of the step, and each input row is read from LDS
+// once per tap and kept in registers while the tiles that need it pass (rows
+// delta, delta + 4, ..., delta + 4 (kZt - 1)).
+//
+// A wave's 16 blocks form BZ x BX (z x x) and the workgroup's waves WZ x WX,
+// so a workgroup tile is TH = 4 kZt BZ WZ by TW = 4 kXt BX WX bins.  With
+// BX >= 8 each half wave holds one row of blocks, 32 distinct columns at one
+// z offset, whose B reads fall in 32 distinct banks for any odd RRS.
 //
 // Operands come from LDS:
-//   - the input region is stored transposed (z contiguous, column stride RRS
-//     chosen so that the 32 lanes of a half wave fall in distinct banks), so
+//   - the input region is stored transposed (z contiguous, odd column stride
+//     RRS chosen on the host against bank conflicts of a half wave), so
 //     every row offset is an instruction immediate;
 //   - the PSF is stored as one zero-padded column per x tap, laid out so that
 //     step delta of lane q reads a fixed immediate offset from a per-tap base.
 //
-// Forward: a workgroup (NW waves) owns a (4 kZt BZ) x (32 BX) output tile of one view and
-// a chunk of depth planes, stages each plane's region (replicate padding by
+// Forward: a workgroup owns a TH x TW output tile of one view and a chunk of
+// depth planes, stages each plane's region (replicate padding by
 // clamped source indices) and PSF, and adds the plane into the accumulators;
 // each plane's sum is folded into a second set, so FP32 chains stay one plane
 // long.  The next plane's region and PSF are loaded into registers while the
@@ -55,10 +60,9 @@ constexpr int kMaxRR = 128;  // region rows
 constexpr int kPfCols = 3;   // 64-column sweeps of a region row (RC <= 192)
 constexpr int kMaxPsf = 4096;  // PSF table elements (px * PL4)
 
-// A workgroup of NW waves (4 or 8) covers the same 32 BX columns either way:
-// each wave's blocks hold 8 / NW x tiles.  With 8 waves every SIMD runs two
-// of them, so one wave's LDS waits and barriers overlap the other's MFMAs;
-// the kernels are built with 8.
+// Waves per workgroup: with 8, every SIMD runs two of them, so one wave's LDS
+// waits and barriers overlap the other's MFMAs (the kernels are built with
+// 8; with 4, each block would hold 2 x tiles).
 constexpr int kM4Waves = 8;
 template <int NW>
 struct Waves {
@@ -278,11 +282,12 @@ __global__ __launch_bounds__(64 * NW, 1) void conv_fwd_m4(const float* __restric
   const int tile = logical % ntile, rest = logical / ntile;
   const int tk = tile / s.tiles_i, ti = tile - tk * s.tiles_i;
   const int c = rest % s.nchunk, lb = rest / s.nchunk, l = view0 + lb;
-  const int k0 = tk * 4 * kZt * s.BZ, i0 = ti * 32 * s.BX;
+  const int k0 = tk * s.TH, i0 = ti * s.TW;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane & 3, blk = lane >> 2;
-  const int bz = blk / s.BX, bx = blk - bz * s.BX;
+  const int bz = blk / s.BX, bx = blk - bz * s.BX, wz = w / s.WX, wx = w - wz * s.WX;
   constexpr int kXt = Waves<NW>::kXt;
-  const int zb = 4 * kZt * bz, xo = 4 * kXt * (s.BX * w + bx);  // block origin in the tile
+  // block origin in the tile
+  const int zb = 4 * kZt * (s.BZ * wz + bz), xo = 4 * kXt * (s.BX * wx + bx);
   int j0, j1;
   chunk_range(c, s.nchunk, s.ny, j0, j1);
   const size_t row_stride = (size_t)s.ny * s.nx;
@@ -358,11 +363,11 @@ __global__ __launch_bounds__(64 * NW, 1) void conv_back_m4(const float* __restri
   const int tile = logical % ntile, rest = logical / ntile;
   const int tk = tile / s.tiles_i, ti = tile - tk * s.tiles_i;
   const int c = rest % s.nchunk_back, lb = rest / s.nchunk_back, l = view0 + lb;
-  const int k0 = tk * 4 * kZt * s.BZ, i0 = ti * 32 * s.BX;
+  const int k0 = tk * s.TH, i0 = ti * s.TW;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane & 3, blk = lane >> 2;
-  const int bz = blk / s.BX, bx = blk - bz * s.BX;
+  const int bz = blk / s.BX, bx = blk - bz * s.BX, wz = w / s.WX, wx = w - wz * s.WX;
   constexpr int kXt = Waves<NW>::kXt;
-  const int zb = 4 * kZt * bz, xo = 4 * kXt * (s.BX * w + bx);
+  const int zb = 4 * kZt * (s.BZ * wz + bz), xo = 4 * kXt * (s.BX * wx + bx);
   int j0, j1;
   chunk_range(c, s.nchunk_back, s.ny, j0, j1);
   const float* vl = v + (size_t)l * s.nz * s.nx;
@@ -504,36 +509,44 @@ int m4_pick_chunks(int ny, long long tiles_views, long long slots) {
 M4Shape make_m4_shape(const spect_geom& g) {
   M4Shape best{};
   best.ok = false;
-  double best_area = 0.0;
+  double best_cost = 0.0;
   const int ND4 = (g.pz + 3 + 3) / 4;
-  for (int BX = 1; BX <= 16; BX *= 2) {
-    M4Shape s{};
-    s.nx = g.nx; s.ny = g.ny; s.nz = g.nz; s.px = g.px; s.pz = g.pz;
-    s.ha = (g.px - 1) / 2; s.hb = (g.pz - 1) / 2;
-    s.ND4 = ND4;
-    s.mirror = false;
-    s.BX = BX;
-    s.BZ = 16 / BX;
-    s.tiles_k = (g.nz + 4 * kZt * s.BZ - 1) / (4 * kZt * s.BZ);
-    s.tiles_i = (g.nx + 32 * BX - 1) / (32 * BX);
-    s.RR = 4 * kZt * (s.BZ - 1) + 4 * (kZt - 1) + 4 * ND4;
-    s.RC = 32 * BX + g.px - 1;
-    s.PL4 = 4 * ND4 + 3;
-    int rrs = s.RR | 1, best_rrs = rrs, best_conf = 1 << 30;
-    for (; rrs < s.RR + 64; rrs += 2) {
-      const int cf = m4_bank_conflicts(rrs, BX, Waves<kM4Waves>::kXt);
-      if (cf < best_conf) { best_conf = cf; best_rrs = rrs; }
-      if (cf <= 1) break;
+  constexpr int kXt = Waves<kM4Waves>::kXt;
+  for (int BX = 1; BX <= 16; BX *= 2)
+    for (int WX = 1; WX <= kM4Waves; WX *= 2) {
+      M4Shape s{};
+      s.nx = g.nx; s.ny = g.ny; s.nz = g.nz; s.px = g.px; s.pz = g.pz;
+      s.ha = (g.px - 1) / 2; s.hb = (g.pz - 1) / 2;
+      s.ND4 = ND4;
+      s.mirror = false;
+      s.BX = BX;
+      s.BZ = 16 / BX;
+      s.WX = WX;
+      s.WZ = kM4Waves / WX;
+      s.TH = 4 * kZt * s.BZ * s.WZ;
+      s.TW = 4 * kXt * BX * WX;
+      s.tiles_k = (g.nz + s.TH - 1) / s.TH;
+      s.tiles_i = (g.nx + s.TW - 1) / s.TW;
+      s.RR = s.TH - 4 + 4 * ND4;
+      s.RC = s.TW + g.px - 1;
+      s.PL4 = 4 * ND4 + 3;
+      int rrs = s.RR | 1, best_rrs = rrs, best_conf = 1 << 30;
+      for (; rrs < s.RR + 64; rrs += 2) {
+        const int cf = m4_bank_conflicts(rrs, BX, kXt);
+        if (cf < best_conf) { best_conf = cf; best_rrs = rrs; }
+        if (cf <= 1) break;
+      }
+      s.RRS = best_rrs;
+      s.nchunk = 1;
+      s.nchunk_back = 1;
+      s.ok = ND4 >= 1 && ND4 <= 16 && s.RR <= kMaxRR && s.RC <= 64 * kPfCols &&
+             g.px * s.PL4 <= kMaxPsf && m4_lds_bytes(s) <= kLdsBytes;
+      if (!s.ok) continue;
+      // padded output area; an n-way conflict on the B reads costs about
+      // (n - 1) / 8 more (they are half the LDS reads, LDS about half busy)
+      const double cost = (double)s.tiles_k * s.TH * s.tiles_i * s.TW * (1.0 + 0.125 * (best_conf - 1));
+      if (!best.ok || cost < best_cost) { best = s; best_cost = cost; }
     }
-    s.RRS = best_rrs;
-    s.nchunk = 1;
-    s.nchunk_back = 1;
-    s.ok = ND4 >= 1 && ND4 <= 16 && s.RR <= kMaxRR && s.RC <= 64 * kPfCols &&
-           g.px * s.PL4 <= kMaxPsf && m4_lds_bytes(s) <= kLdsBytes;
-    if (!s.ok) continue;
-    const double area = (double)s.tiles_k * 4 * kZt * s.BZ * s.tiles_i * 32 * BX;
-    if (!best.ok || area < best_area) { best = s; best_area = area; }
-  }
   return best;
 }
 
@@ -544,7 +557,7 @@ M4Shape make_m4_shape(const spect_geom& g) {
 bool m4_preferred(const M4Shape& s, const ConvShape& cs) {
   if (!s.ok) return false;
   const double old_cost = (double)cs.tiles_k * 16 * cs.WK * cs.tiles_i * 32 * cs.WI * 4 * cs.KS;
-  const double new_cost = (double)s.tiles_k * 4 * kZt * s.BZ * s.tiles_i * 32 * s.BX * 4 * s.ND4 / 0.92;
+  const double new_cost = (double)s.tiles_k * s.TH * s.tiles_i * s.TW * 4 * s.ND4 / 0.92;
   return new_cost < old_cost;
 }
 

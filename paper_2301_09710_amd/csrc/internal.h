@@ -53,7 +53,9 @@ struct M4Shape {
   int ND4;              // steps per tap / 4: ceil((pz + 3) / 4)
   bool mirror;          // PSF rows symmetric in x: taps a and px-1-a share one product
   int BZ, BX;           // blocks of a wave along z and x (BZ * BX = 16)
-  int tiles_k, tiles_i; // workgroup tiles of 20 BZ x 32 BX output bins
+  int WZ, WX;           // waves of a workgroup along z and x (WZ * WX = 8)
+  int TH, TW;           // workgroup tile: 20 BZ WZ x 4 BX WX output bins
+  int tiles_k, tiles_i; // workgroup tiles along z and x
   int RR, RC, RRS;      // region rows (z), columns (x), column stride in LDS
   int PL4;              // PSF column length in LDS
   int nchunk, nchunk_back;
