@@ -220,7 +220,8 @@ const char* spect_version(void);
  * (NUL-terminated, truncated to len bytes): conv = fp32-4x4 | fp32-16x16 |
  * separable | bf16 | fp16 | bf16x3, mirror = 1 when the FP32 4x4-block
  * convolution pairs mirror-image taps (see spect_plan_create), rotation =
- * 3pass | bilinear, view_batch, nchunk.  Host only. */
+ * 3pass | bilinear, view_batch, nchunk, rot_views (views per workgroup of
+ * the forward rotation).  Host only. */
 spect_status spect_plan_describe(spect_plan plan, char* buf, size_t len);
 
 #ifdef __cplusplus

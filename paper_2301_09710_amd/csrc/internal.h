@@ -140,6 +140,7 @@ struct Profiler {
 struct Plan {
   spect_geom g;         // angles pointer cleared after creation
   int view_batch;
+  int rot_fwd_vg;       // views per workgroup of the line-pass forward rotation
   int nchunk;           // forward depth chunks
   const float* mu;
   const float* psf;
@@ -205,6 +206,9 @@ size_t lp_lds_bytes(const LpShape& s, bool split);
 bool lp_supported(const spect_geom& g);
 void tune_lp_chunks(LpShape& s, int views, int precision);
 size_t rotation_lds_bytes(int n);
+// Views per workgroup of the forward rotation for batches of nvb views:
+// whole rounds of the resident workgroup slots, few views per workgroup.
+int tune_rot_fwd_views(const spect_geom& g, int nvb);
 size_t rotation_scratch_bytes(int n, int nz, int nview);
 
 // ---- kernel launchers (return hipGetLastError() of the launch) ----

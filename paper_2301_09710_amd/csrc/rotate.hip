@@ -474,6 +474,127 @@ __global__ __launch_bounds__(NT) void rot_fwd_kernel(const float* __restrict__ x
   }
 }
 
+// ---------------------------------------------------------------- forward, line passes
+// The 3-pass forward on slices that fit LDS: per view the slice is staged
+// quarter-turned (P_m x) into one working buffer and the three shears run as
+// in-place line passes, the last one fused with the attenuation weight and
+// the store.  Each line's table entry is one broadcast read, and samples
+// outside [0, n) fall on zero guard cells (clamped positions) instead of
+// branches.  The source slice stays in registers across the workgroup's views;
+// a view's attenuation factors are requested before its staging and first two
+// passes, which cover their latency.
+//
+// Guarded buffer: cell (i, j), -1 <= i, j <= n, at Yd[j S + i] with
+// Yd = Y + S + 1 and S = guarded_stride(n) (odd, >= n + 2): rows and columns
+// -1 and n are zero.
+__host__ __device__ __forceinline__ int guarded_stride(int n) { return (n + 2) | 1; }
+__host__ __device__ __forceinline__ int guarded_floats(int n) { return (n + 2) * guarded_stride(n); }
+
+__device__ __forceinline__ int clamp_guard(int q, int n) { return min(max(q, -1), n); }
+
+// In-place forward shear of the lines a wave owns (rows: along i with the
+// per-row entries, kRows = false: along j with the per-column entries).
+template <bool kRows, int EPL, int LPW>
+__device__ __forceinline__ void guarded_pass(float* Yd, int n, int S, const TabEntry* lines) {
+  const int lane = lane_id(), w = wave_id();
+#pragma unroll 2
+  for (int r = 0; r < LPW; ++r) {
+    const int L = w + NW * r;
+    if (L >= n) break;                             // uniform per wave
+    const TabEntry te = lines[L];
+    float v[EPL];
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      const int q = lane + 64 * e;
+      const int qa = clamp_guard(q + te.o, n), qb = clamp_guard(q + te.o + 1, n);
+      const float a = kRows ? Yd[L * S + qa] : Yd[qa * S + L];
+      const float b = kRows ? Yd[L * S + qb] : Yd[qb * S + L];
+      v[e] = te.w.x * a + te.w.y * b;
+    }
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      const int q = lane + 64 * e;
+      if (q < n) (kRows ? Yd[L * S + q] : Yd[q * S + L]) = v[e];
+    }
+  }
+}
+
+// grid (nz, ceil(nvb / VG)): W[lb][k] = (R_l x)[k] * mubar_l[k] for the views
+// of this group.  Thread (wave w, lane) owns pixels i = lane + 64 e,
+// j = w + NW r for staging, the last pass and the store.
+template <int EPL, int LPW>
+__global__ __launch_bounds__(NT) void rot_fwd_lines_kernel(const float* __restrict__ x,
+                                                           const float* __restrict__ mb, int mb_off,
+                                                           float* __restrict__ W, int n, int nz,
+                                                           int view0, int nvb, int VG, Tables tab) {
+  extern __shared__ float smem[];
+  const int S = guarded_stride(n);
+  float* Yd = smem + S + 1;
+  ViewTab t = carve_tab(smem + round4(guarded_floats(n)), n);
+  const int k = blockIdx.x, lane = lane_id(), w = wave_id();
+  const size_t nn = (size_t)n * n, N = nn * nz;
+  for (int p = threadIdx.x; p < guarded_floats(n); p += NT) smem[p] = 0.0f;
+  const int lb0 = blockIdx.y * VG, lb1 = min(nvb, lb0 + VG);
+  // rows j = w + NW r with j < n (uniform per wave); columns i = lane + 64 e
+  float xv[LPW][EPL], mbv[LPW][EPL];
+  const int pix = w * n + lane;                   // offset of this thread's (r, e) = (0, 0) pixel
+  const float* xs = x + (size_t)k * nn;
+#pragma unroll
+  for (int r = 0; r < LPW; ++r) {
+    if (w + NW * r >= n) break;
+#pragma unroll
+    for (int e = 0; e < EPL; ++e)
+      xv[r][e] = lane + 64 * e < n ? xs[pix + NW * n * r + 64 * e] : 0.0f;
+  }
+  for (int lb = lb0; lb < lb1; ++lb) {
+    const int l = view0 + lb;
+    const int m = tab.quarter[l];
+    const float* mbs = mb + (size_t)(lb + mb_off) * N + (size_t)k * nn;
+#pragma unroll
+    for (int r = 0; r < LPW; ++r) {
+      if (w + NW * r >= n) break;
+#pragma unroll
+      for (int e = 0; e < EPL; ++e)
+        mbv[r][e] = lane + 64 * e < n ? mbs[pix + NW * n * r + 64 * e] : 0.0f;
+    }
+    // position of pixel (i, j) of x in Y = P_m x: Yd[qb + qi i + qj j]
+    int qb, qi, qj;
+    if (m == 0) { qb = 0; qi = 1; qj = S; }
+    else if (m == 1) { qb = n - 1; qi = S; qj = -1; }
+    else if (m == 2) { qb = (n - 1) * S + n - 1; qi = -1; qj = -S; }
+    else { qb = (n - 1) * S; qi = -S; qj = 1; }
+    const int sb = qb + qi * lane + qj * w;
+    __syncthreads();                               // guards zeroed / previous view's readers done
+    load_tab(tab, l, n, t);
+#pragma unroll
+    for (int r = 0; r < LPW; ++r) {
+      if (w + NW * r >= n) break;
+#pragma unroll
+      for (int e = 0; e < EPL; ++e)
+        if (lane + 64 * e < n) Yd[sb + qi * 64 * e + qj * NW * r] = xv[r][e];
+    }
+    __syncthreads();
+    guarded_pass<true, EPL, LPW>(Yd, n, S, t.e13);   // pass 1 (along i)
+    __syncthreads();
+    guarded_pass<false, EPL, LPW>(Yd, n, S, t.e2);   // pass 2 (along j)
+    __syncthreads();
+    float* dst = W + (size_t)lb * N + (size_t)k * nn;
+#pragma unroll
+    for (int r = 0; r < LPW; ++r) {                 // pass 3 (along i), weight, store
+      const int j = w + NW * r;
+      if (j >= n) break;
+      const TabEntry te = t.e13[j];
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        const int i = lane + 64 * e;
+        const int qa = clamp_guard(i + te.o, n), qb2 = clamp_guard(i + te.o + 1, n);
+        const float v = te.w.x * Yd[j * S + qa] + te.w.y * Yd[j * S + qb2];
+        if (i < n) dst[pix + NW * n * r + 64 * e] = v * mbv[r][e];
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- back
 // grid (nz, G): partial[g][k] (+)= sum over views lb = g, g+G, ... of
 //   P_m^T S1^T S2^T S3^T (U[lb][k] * mubar_l[k]).
@@ -662,6 +783,22 @@ hipError_t launch_rot_fwd(const Plan& p, const float* x, const float* mb, int mb
                           int view0, int nvb, hipStream_t s) {
   const int n = p.g.nx;
   const bool glob = n > kMaxLdsN;
+  if (!glob && !p.bilinear) {
+    const size_t sm = (size_t)round4(guarded_floats(n)) * 4 + tab_bytes(n);
+    const int VG = p.rot_fwd_vg > 0 ? p.rot_fwd_vg : kRotViewsPerGroup;
+    dim3 grid(p.g.nz, (nvb + VG - 1) / VG);
+    return with_shape(n, [&](auto E, auto L, auto G) {
+      if constexpr (G.value) {
+        return hipErrorInvalidValue;               // not reached: n <= kMaxLdsN here
+      } else {
+        hipError_t e = set_smem((const void*)rot_fwd_lines_kernel<E.value, L.value>, sm);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((rot_fwd_lines_kernel<E.value, L.value>), grid, dim3(NT), sm, s, x, mb,
+                           mb_off, W, n, p.g.nz, view0, nvb, VG, p.tab);
+        return hipGetLastError();
+      }
+    });
+  }
   const size_t sm = glob ? tab_bytes(n) : (size_t)n * gather_stride(n) * 4 + tab_bytes(n);
   const int VG = kRotViewsPerGroup;
   dim3 grid(p.g.nz, (nvb + VG - 1) / VG);
@@ -682,6 +819,38 @@ hipError_t launch_rot_fwd(const Plan& p, const float* x, const float* mb, int mb
   constexpr int tl = (kMaxLdsN + 7) / 8, tg = (kMaxN + 7) / 8;
   if (n <= kMaxLdsN) return go(integral_constant<int, (tl * tl + NW - 1) / NW>(), std::false_type());
   return go(integral_constant<int, (tg * tg + NW - 1) / NW>(), std::true_type());
+}
+
+int tune_rot_fwd_views(const spect_geom& g, int nvb) {
+  const int n = g.nx;
+  if (n > kMaxLdsN || (g.flags & SPECT_ROT_BILINEAR)) return kRotViewsPerGroup;
+  int dev = 0, cus = 0, per_cu = 0;
+  const size_t sm = (size_t)round4(guarded_floats(n)) * 4 + tab_bytes(n);
+  hipError_t e = with_shape(n, [&](auto E, auto L, auto G) {
+    if constexpr (G.value) {
+      return hipErrorInvalidValue;
+    } else {
+      hipError_t r = set_smem((const void*)rot_fwd_lines_kernel<E.value, L.value>, sm);
+      if (r != hipSuccess) return r;
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, (const void*)rot_fwd_lines_kernel<E.value, L.value>, NT, sm);
+    }
+  });
+  if (e != hipSuccess || hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1 || per_cu < 1)
+    return kRotViewsPerGroup;
+  // time ~ rounds x (views per workgroup + the per-workgroup set-up, about
+  // half a view: guard zeroing and the source slice)
+  const long long slots = (long long)cus * per_cu;
+  int best = kRotViewsPerGroup;
+  double best_cost = -1.0;
+  for (int vg = 1; vg <= 16; ++vg) {
+    const long long wgs = (long long)g.nz * ((nvb + vg - 1) / vg);
+    const double cost = (double)((wgs + slots - 1) / slots) * (vg + 0.5);
+    if (best_cost < 0 || cost < best_cost) { best_cost = cost; best = vg; }
+  }
+  return best;
 }
 
 hipError_t launch_rot_back(const Plan& p, const float* U, const float* mb, int mb_off,

@@ -172,8 +172,9 @@ spect_status spect_plan_describe(spect_plan plan, char* buf, size_t len) {
                      : p->use_m4 ? "fp32-4x4"
                                  : "fp32-16x16";
   const bool mirror = p->use_m4 && p->conv_precision == SPECT_CONV_FP32 && p->m4.mirror;
-  std::snprintf(buf, len, "conv=%s mirror=%d rotation=%s view_batch=%d nchunk=%d", conv,
-                mirror ? 1 : 0, p->bilinear ? "bilinear" : "3pass", p->view_batch, p->nchunk);
+  std::snprintf(buf, len, "conv=%s mirror=%d rotation=%s view_batch=%d nchunk=%d rot_views=%d",
+                conv, mirror ? 1 : 0, p->bilinear ? "bilinear" : "3pass", p->view_batch, p->nchunk,
+                p->rot_fwd_vg);
   return SPECT_OK;
 }
 
@@ -254,6 +255,7 @@ spect_status spect_plan_create(spect_plan* out, const spect_geom* g, const float
   p->mubar = nullptr;
   p->mubar_batch = nullptr;
   p->rot_scratch = g->nx > kMaxLdsN ? reinterpret_cast<float*>(p->ws + lay.rot_scratch) : nullptr;
+  p->rot_fwd_vg = tune_rot_fwd_views(*g, vb);
   p->use_mfma = conv_mfma_supported(*g);
   p->conv = make_conv_shape(*g, kFwdJChunk, kBackJChunk);
   p->m4 = make_m4_shape(*g);

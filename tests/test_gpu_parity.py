@@ -177,6 +177,9 @@ RAGGED = [
     (20, 9, 8, 3, 7, False, None),              # 45-degree ties
     (12, 7, 5, 5, 5, False, [0.1, -2.0, 3.9, 7.5, math.pi / 4]),
     (9, 4, 1, 1, 1, True, None),
+    (100, 5, 4, 7, 5, True, None),              # lines of 100: a partial second lane sweep
+    (136, 4, 3, 5, 5, False, None),             # the largest slice kept in LDS
+    (64, 6, 5, 3, 3, False, None),
 ]
 
 
