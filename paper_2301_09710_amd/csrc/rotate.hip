@@ -492,9 +492,20 @@ __host__ __device__ __forceinline__ int guarded_floats(int n) { return (n + 2) *
 
 __device__ __forceinline__ int clamp_guard(int q, int n) { return min(max(q, -1), n); }
 
-// In-place forward shear of the lines a wave owns (rows: along i with the
-// per-row entries, kRows = false: along j with the per-column entries).
-template <bool kRows, int EPL, int LPW>
+// Cell of pixel (i, j) under P_m (the position quarter_dst gives) in a
+// buffer of row stride S: qb + qi i + qj j.
+__device__ __forceinline__ void quarter_cell(int m, int n, int S, int& qb, int& qi, int& qj) {
+  if (m == 0) { qb = 0; qi = 1; qj = S; }
+  else if (m == 1) { qb = n - 1; qi = S; qj = -1; }
+  else if (m == 2) { qb = (n - 1) * S + n - 1; qi = -1; qj = -S; }
+  else { qb = (n - 1) * S; qi = -S; qj = 1; }
+}
+
+// In-place shear of the lines a wave owns (rows: along i with the per-row
+// entries, kRows = false: along j with the per-column entries), forward
+// (kSgn = +1: out[q] = w.x in[q + o] + w.y in[q + o + 1]) or transposed
+// (kSgn = -1: out[q] = w.x in[q - o] + w.y in[q - o - 1]).
+template <int kSgn, bool kRows, int EPL, int LPW>
 __device__ __forceinline__ void guarded_pass(float* Yd, int n, int S, const TabEntry* lines) {
   const int lane = lane_id(), w = wave_id();
 #pragma unroll 2
@@ -506,7 +517,7 @@ __device__ __forceinline__ void guarded_pass(float* Yd, int n, int S, const TabE
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
       const int q = lane + 64 * e;
-      const int qa = clamp_guard(q + te.o, n), qb = clamp_guard(q + te.o + 1, n);
+      const int qa = clamp_guard(q + kSgn * te.o, n), qb = clamp_guard(q + kSgn * (te.o + 1), n);
       const float a = kRows ? Yd[L * S + qa] : Yd[qa * S + L];
       const float b = kRows ? Yd[L * S + qb] : Yd[qb * S + L];
       v[e] = te.w.x * a + te.w.y * b;
@@ -557,12 +568,8 @@ __global__ __launch_bounds__(NT) void rot_fwd_lines_kernel(const float* __restri
       for (int e = 0; e < EPL; ++e)
         mbv[r][e] = lane + 64 * e < n ? mbs[pix + NW * n * r + 64 * e] : 0.0f;
     }
-    // position of pixel (i, j) of x in Y = P_m x: Yd[qb + qi i + qj j]
     int qb, qi, qj;
-    if (m == 0) { qb = 0; qi = 1; qj = S; }
-    else if (m == 1) { qb = n - 1; qi = S; qj = -1; }
-    else if (m == 2) { qb = (n - 1) * S + n - 1; qi = -1; qj = -S; }
-    else { qb = (n - 1) * S; qi = -S; qj = 1; }
+    quarter_cell(m, n, S, qb, qi, qj);
     const int sb = qb + qi * lane + qj * w;
     __syncthreads();                               // guards zeroed / previous view's readers done
     load_tab(tab, l, n, t);
@@ -574,9 +581,9 @@ __global__ __launch_bounds__(NT) void rot_fwd_lines_kernel(const float* __restri
         if (lane + 64 * e < n) Yd[sb + qi * 64 * e + qj * NW * r] = xv[r][e];
     }
     __syncthreads();
-    guarded_pass<true, EPL, LPW>(Yd, n, S, t.e13);   // pass 1 (along i)
+    guarded_pass<1, true, EPL, LPW>(Yd, n, S, t.e13);   // pass 1 (along i)
     __syncthreads();
-    guarded_pass<false, EPL, LPW>(Yd, n, S, t.e2);   // pass 2 (along j)
+    guarded_pass<1, false, EPL, LPW>(Yd, n, S, t.e2);   // pass 2 (along j)
     __syncthreads();
     float* dst = W + (size_t)lb * N + (size_t)k * nn;
 #pragma unroll
@@ -591,6 +598,91 @@ __global__ __launch_bounds__(NT) void rot_fwd_lines_kernel(const float* __restri
         const float v = te.w.x * Yd[j * S + qa] + te.w.y * Yd[j * S + qb2];
         if (i < n) dst[pix + NW * n * r + 64 * e] = v * mbv[r][e];
       }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- back, line passes
+// grid (nz, G) on slices that fit LDS: partial[g][k] (+)= sum over views
+// lb = g, g+G, ... of P_m^T S1^T S2^T S3^T (U[lb][k] * mubar_l[k]).  Per view
+// the weighted slice is staged into the zero-guarded buffer, the transposed
+// shears run as in-place line passes (S3^T, S2^T, S1^T), and P_m^T gathers
+// the result into the accumulators (thread (w, lane) owns pixels
+// i = lane + 64 e, j = w + NW r).  The next view's U and mubar are loaded
+// during the passes.
+template <int EPL, int LPW>
+__global__ __launch_bounds__(NT) void rot_back_lines_kernel(const float* __restrict__ U,
+                                                            const float* __restrict__ mb, int mb_off,
+                                                            float* __restrict__ partial, int n,
+                                                            int nz, int view0, int nvb, int G,
+                                                            int accumulate, Tables tab) {
+  extern __shared__ float smem[];
+  const int S = guarded_stride(n);
+  float* Yd = smem + S + 1;
+  ViewTab t = carve_tab(smem + round4(guarded_floats(n)), n);
+  const int k = blockIdx.x, g = blockIdx.y, lane = lane_id(), w = wave_id();
+  const size_t nn = (size_t)n * n, N = nn * nz;
+  for (int p = threadIdx.x; p < guarded_floats(n); p += NT) smem[p] = 0.0f;
+  const int pix = w * n + lane;
+  float acc[LPW][EPL], uv[LPW][EPL], mv[LPW][EPL];
+#pragma unroll
+  for (int r = 0; r < LPW; ++r)
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) acc[r][e] = 0.0f;
+  auto load_view = [&](int lb) {
+    const float* src = U + (size_t)lb * N + (size_t)k * nn;
+    const float* mbs = mb + (size_t)(lb + mb_off) * N + (size_t)k * nn;
+#pragma unroll
+    for (int r = 0; r < LPW; ++r) {
+      if (w + NW * r >= n) break;
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        const bool in = lane + 64 * e < n;
+        uv[r][e] = in ? src[pix + NW * n * r + 64 * e] : 0.0f;
+        mv[r][e] = in ? mbs[pix + NW * n * r + 64 * e] : 0.0f;
+      }
+    }
+  };
+  if (g < nvb) load_view(g);
+  for (int lb = g; lb < nvb; lb += G) {
+    const int l = view0 + lb;
+    const int m = tab.quarter[l];
+    __syncthreads();                               // guards zeroed / previous view's readers done
+    load_tab(tab, l, n, t);
+#pragma unroll
+    for (int r = 0; r < LPW; ++r) {                 // Y = U * mubar
+      if (w + NW * r >= n) break;
+#pragma unroll
+      for (int e = 0; e < EPL; ++e)
+        if (lane + 64 * e < n) Yd[(w + NW * r) * S + lane + 64 * e] = uv[r][e] * mv[r][e];
+    }
+    if (lb + G < nvb) load_view(lb + G);
+    __syncthreads();
+    guarded_pass<-1, true, EPL, LPW>(Yd, n, S, t.e13);    // S3^T (along i)
+    __syncthreads();
+    guarded_pass<-1, false, EPL, LPW>(Yd, n, S, t.e2);    // S2^T (along j)
+    __syncthreads();
+    guarded_pass<-1, true, EPL, LPW>(Yd, n, S, t.e13);    // S1^T (along i)
+    __syncthreads();
+    int qb, qi, qj;                                       // x(i, j) += h(P_m (i, j))
+    quarter_cell(m, n, S, qb, qi, qj);
+    const int sb = qb + qi * lane + qj * w;
+#pragma unroll
+    for (int r = 0; r < LPW; ++r) {
+      if (w + NW * r >= n) break;
+#pragma unroll
+      for (int e = 0; e < EPL; ++e)
+        if (lane + 64 * e < n) acc[r][e] += Yd[sb + qi * 64 * e + qj * NW * r];
+    }
+  }
+  float* dst = partial + (size_t)g * N + (size_t)k * nn;
+#pragma unroll
+  for (int r = 0; r < LPW; ++r) {
+    if (w + NW * r >= n) break;
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      const int p = pix + NW * n * r + 64 * e;
+      if (lane + 64 * e < n) dst[p] = accumulate ? dst[p] + acc[r][e] : acc[r][e];
     }
   }
 }
@@ -857,6 +949,22 @@ hipError_t launch_rot_back(const Plan& p, const float* U, const float* mb, int m
                            float* partial, int view0, int nvb, bool accumulate, hipStream_t s) {
   const int n = p.g.nx;
   const bool glob = n > kMaxLdsN;
+  // line passes up to 128 (two values per lane; wider lines would spill)
+  if (n <= 128 && !p.bilinear) {
+    const size_t sm = (size_t)round4(guarded_floats(n)) * 4 + tab_bytes(n);
+    return with_shape(n, [&](auto E, auto L, auto G) {
+      if constexpr (G.value || E.value > 2) {
+        return hipErrorInvalidValue;               // not reached: n <= 128 here
+      } else {
+        hipError_t e = set_smem((const void*)rot_back_lines_kernel<E.value, L.value>, sm);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((rot_back_lines_kernel<E.value, L.value>), dim3(p.g.nz, kBackGroups),
+                           dim3(NT), sm, s, U, mb, mb_off, partial, n, p.g.nz, view0, nvb,
+                           kBackGroups, accumulate ? 1 : 0, p.tab);
+        return hipGetLastError();
+      }
+    });
+  }
   const size_t sm = glob ? tab_bytes(n) : (size_t)round4(n * slice_stride(n)) * 4 + tab_bytes(n);
   return with_shape(n, [&](auto E, auto L, auto G) {
     auto go = [&](auto B) {
