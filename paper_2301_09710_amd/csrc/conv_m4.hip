@@ -117,7 +117,7 @@ __device__ __forceinline__ void m4_plane(const float* __restrict__ P, const floa
                                          floatx4 (&acc)[kZt][kXt]) {
   constexpr int ND = 4 * ND4;                 // steps per tap
   constexpr int NR = 4 * (kZt - 1) + ND;      // input rows per tap
-  constexpr int NF = 4 * kZt;                 // rows first used in steps 0..3 (one per tile)
+  constexpr int NF = 4 * kZt;                 // rows 0 .. NF-1: first used in steps 0..3
   constexpr int NG = (ND + 15) / 16;          // A groups per tap
   constexpr int NSP = ND >= 16 ? ND - 8 : ND; // steps that carry the next tap's first rows
   const int lane = threadIdx.x & 63, q = lane & 3, blk = lane >> 2;
@@ -127,11 +127,14 @@ __device__ __forceinline__ void m4_plane(const float* __restrict__ P, const floa
     const int t = min(16 * g + blk, ND - 1);  // slots past the last step repeat it (unused)
     aoff[g] = kBack ? 3 - q + t : q + ND - 1 - t;
   }
-  // X1 (and X2, the mirror tap's column) hold rows as loaded; B, the MFMA
-  // operand, is formed at the row's first step, so no load is waited for
-  // in the step that issues it.
-  float Ag[NG], Agn[NG];
-  float X1[NR][kXt], X2[NR][kXt], B[NR][kXt], N1[NF][kXt], N2[NF][kXt];
+  // Rows as loaded (X: the tap's column, Y: the mirror tap's column).  The
+  // first rows of consecutive taps alternate between the sets F0 and F1 (the
+  // tap loop is unrolled by two, so no copies are needed); rows NF .. NR-1
+  // are loaded during their own tap into R.  B, the MFMA operand, is formed at
+  // the row's first step, so no load is waited for in the step that issues it.
+  float Ag[2][NG];
+  float F0x[NF][kXt], F0y[NF][kXt], F1x[NF][kXt], F1y[NF][kXt];
+  float Rx[NR][kXt], Ry[NR][kXt], B[NR][kXt];
   const int tstep = kBack ? RRS : -RRS;
   const int xstep = 4 * RRS;
   auto ld = [&](float (&d1)[kXt], float (&d2)[kXt], const float* pb, const float* pb2, int off) {
@@ -141,68 +144,70 @@ __device__ __forceinline__ void m4_plane(const float* __restrict__ P, const floa
       if (kMirror) d2[j] = pb2[j * xstep + off];
     }
   };
-  auto form = [&](int r) {
+  auto form = [&](const float (&x)[kXt], const float (&y)[kXt], int r) {
 #pragma unroll
-    for (int j = 0; j < kXt; ++j) B[r][j] = kMirror ? X1[r][j] + X2[r][j] : X1[r][j];
+    for (int j = 0; j < kXt; ++j) B[r][j] = kMirror ? x[j] + y[j] : x[j];
   };
-  // k-th of the rows first used in steps 0..3, in order of first use:
-  // row 4 i + u (tile i, step u) for k = u kZt + i
+  // k-th first row in order of first use: row 4 i + u (tile i, step u) for
+  // k = u kZt + i; its index is first_k(r) for r < NF
   auto first_row = [](int k) { return 4 * (k % kZt) + k / kZt; };
-  const float* pb = RT + pb_lane;
-  const float* pb2 = RT + pb2_lane;
-#pragma unroll
-  for (int g = 0; g < NG; ++g) Ag[g] = P[aoff[g]];
-#pragma unroll
-  for (int k = 0; k < NF; ++k) ld(X1[first_row(k)], X2[first_row(k)], pb, pb2, first_row(k));
-  for (int a = 0; a < ntap; ++a) {
+  auto first_k = [](int r) { return (r % 4) * kZt + r / 4; };
+  // one tap: a = the tap, kOdd selects which first-row and A sets are current
+  auto tap = [&](auto Odd, int a) {
+    constexpr bool kOdd = decltype(Odd)::value;
+    auto& Fx = kOdd ? F1x : F0x;
+    auto& Fy = kOdd ? F1y : F0y;
+    auto& Nx = kOdd ? F0x : F1x;
+    auto& Ny = kOdd ? F0y : F1y;
+    const float* pb = RT + pb_lane + a * tstep;
+    const float* pb2 = RT + pb2_lane - a * tstep;
     const int an = a + 1 < ntap ? a + 1 : a;  // the last tap reloads itself (values unused)
     const float* pan = P + an * PL4;
     const float* pbn = RT + pb_lane + an * tstep;
     const float* pb2n = RT + pb2_lane - an * tstep;
     unroll<ND>([&](auto S) {
       constexpr int s = decltype(S)::value;
-      // the row first used kLook steps ahead (rows of later steps are
-      // needed by the last tile only)
+      // the row first used kLook steps ahead (rows of later steps are needed
+      // by the last tile only)
       constexpr int t = s + kLook;
-      if constexpr (t >= 4 && t < ND) ld(X1[t + 4 * (kZt - 1)], X2[t + 4 * (kZt - 1)], pb, pb2,
+      if constexpr (t >= 4 && t < ND) ld(Rx[t + 4 * (kZt - 1)], Ry[t + 4 * (kZt - 1)], pb, pb2,
                                          t + 4 * (kZt - 1));
       // the next tap's first rows, spread over the first NSP steps
       if constexpr (s < NSP) {
 #pragma unroll
-        for (int k = s * NF / NSP; k < (s + 1) * NF / NSP; ++k) ld(N1[k], N2[k], pbn, pb2n, first_row(k));
+        for (int k = s * NF / NSP; k < (s + 1) * NF / NSP; ++k) ld(Nx[k], Ny[k], pbn, pb2n, first_row(k));
       }
       if constexpr (s == ND / 2) {
 #pragma unroll
-        for (int g = 0; g < NG; ++g) Agn[g] = pan[aoff[g]];
+        for (int g = 0; g < NG; ++g) Ag[kOdd ? 0 : 1][g] = pan[aoff[g]];
       }
       // operands of the rows first used at this step
       if constexpr (s < 4) {
 #pragma unroll
-        for (int i = 0; i < kZt; ++i) form(s + 4 * i);
+        for (int i = 0; i < kZt; ++i) form(Fx[first_k(s + 4 * i)], Fy[first_k(s + 4 * i)], s + 4 * i);
       } else {
-        form(s + 4 * (kZt - 1));
+        form(Rx[s + 4 * (kZt - 1)], Ry[s + 4 * (kZt - 1)], s + 4 * (kZt - 1));
       }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int i = 0; i < kZt; ++i)
 #pragma unroll
         for (int j = 0; j < kXt; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_4x4x1f32(Ag[s / 16], B[s + 4 * i][j], acc[i][j], 4,
-                                                         s % 16, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_4x4x1f32(Ag[kOdd ? 1 : 0][s / 16], B[s + 4 * i][j],
+                                                         acc[i][j], 4, s % 16, 0);
       __builtin_amdgcn_sched_barrier(0);
     });
+  };
 #pragma unroll
-    for (int g = 0; g < NG; ++g) Ag[g] = Agn[g];
+  for (int g = 0; g < NG; ++g) Ag[0][g] = P[aoff[g]];
 #pragma unroll
-    for (int k = 0; k < NF; ++k)
-#pragma unroll
-      for (int j = 0; j < kXt; ++j) {
-        X1[first_row(k)][j] = N1[k][j];
-        if (kMirror) X2[first_row(k)][j] = N2[k][j];
-      }
-    pb = pbn;
-    pb2 = pb2n;
+  for (int k = 0; k < NF; ++k) ld(F0x[k], F0y[k], RT + pb_lane, RT + pb2_lane, first_row(k));
+  int a = 0;
+  for (; a + 1 < ntap; a += 2) {
+    tap(std::false_type(), a);
+    tap(std::true_type(), a + 1);
   }
+  if (a < ntap) tap(std::false_type(), a);
 }
 
 // PSF table of one plane: P[a PL4 + t] = p[t - Z][a] (zero outside the taps),
