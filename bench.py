@@ -570,6 +570,12 @@ def main():
         "serving": serving,
         "kernels_ms_per_launch": avg_ms,
         "roofline": roof,
+        # the direct operator's products per pair (forward and back convolution,
+        # 2 px pz FLOP per voxel per view each) over the measured pair time: the
+        # rate a direct all-taps implementation would need to match this pair
+        "operator_rate": {"flop_per_pair": 2 * op_flops,
+                          "tflops": 2 * op_flops / (ms_per_step * 1e-3) / 1e12,
+                          "frac_of_fp32_peak": 2 * op_flops / (ms_per_step * 1e-3) / 1e12 / FP32_PEAK_TFLOPS},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
