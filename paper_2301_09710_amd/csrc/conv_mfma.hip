@@ -584,11 +584,13 @@ __global__ __launch_bounds__(256) void conv_back_edges(const float* __restrict__
   }
 }
 
-// N-blocks per pass for nall blocks: fewest issued blocks, then fewest passes.
+// N-blocks per pass for nall blocks: issued blocks plus the fixed cost of a
+// pass (its PSF loads and K loop, about three blocks' worth), then fewer passes.
 int edge_pick_nb(int nall) {
   int best = kEdgeMaxNB, cost = -1;
   for (int nb = kEdgeMaxNB; nb >= 1; --nb) {
-    const int c = (nall + nb - 1) / nb * nb;
+    const int passes = (nall + nb - 1) / nb;
+    const int c = passes * nb + 3 * passes;
     if (cost < 0 || c < cost) { cost = c; best = nb; }
   }
   return best;
