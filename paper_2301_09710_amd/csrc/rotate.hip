@@ -687,6 +687,55 @@ __global__ __launch_bounds__(NT) void rot_back_lines_kernel(const float* __restr
   }
 }
 
+// ---------------------------------------------------------------- banded column pass
+// Column shear of a working slice Y in global memory (row stride S), for
+// slices too large for LDS.  Lanes along a column would touch one cache line
+// each, so the pass runs through LDS in bands of kBand columns: a band is
+// staged with coalesced row reads into B (rows -1 .. n, stride kBand + 1,
+// rows -1 and n zero: set once by the caller), each wave shears its columns
+// in place (lanes along the rows, one table read per column, sample positions
+// clamped into the zero rows), and the band is written back with coalesced
+// row writes.  Starts and ends with a workgroup barrier.
+constexpr int kBand = 64;
+constexpr int kBandStride = kBand + 1;
+__host__ __device__ __forceinline__ size_t band_floats(int n) { return (size_t)(n + 2) * kBandStride; }
+
+template <int kSgn, int EPL>
+__device__ void banded_col_pass(float* Y, int n, int S, const ViewTab& t, float* B) {
+  float* Bd = B + kBandStride;                     // row r of the band at Bd[r * kBandStride]
+  const int lane = lane_id(), w = wave_id();
+  for (int c0 = 0; c0 < n; c0 += kBand) {
+    __syncthreads();                               // Y written / previous band written back
+    for (int p = threadIdx.x; p < n * kBand; p += NT) {
+      const int r = p / kBand, c = p - r * kBand;
+      Bd[r * kBandStride + c] = c0 + c < n ? Y[r * S + c0 + c] : 0.0f;
+    }
+    __syncthreads();
+    for (int c = w; c < kBand && c0 + c < n; c += NW) {
+      const TabEntry te = t.e2[c0 + c];
+      float v[EPL];
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        const int q = lane + 64 * e;
+        const int qa = min(max(q + kSgn * te.o, -1), n);
+        const int qb = min(max(q + kSgn * (te.o + 1), -1), n);
+        v[e] = te.w.x * Bd[qa * kBandStride + c] + te.w.y * Bd[qb * kBandStride + c];
+      }
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        const int q = lane + 64 * e;
+        if (q < n) Bd[q * kBandStride + c] = v[e];
+      }
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < n * kBand; p += NT) {
+      const int r = p / kBand, c = p - r * kBand;
+      if (c0 + c < n) Y[r * S + c0 + c] = Bd[r * kBandStride + c];
+    }
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------- back
 // grid (nz, G): partial[g][k] (+)= sum over views lb = g, g+G, ... of
 //   P_m^T S1^T S2^T S3^T (U[lb][k] * mubar_l[k]).
@@ -704,6 +753,9 @@ __global__ __launch_bounds__(NT) void rot_back_kernel(const float* __restrict__ 
   const int k = blockIdx.x, g = blockIdx.y, lane = lane_id(), w = wave_id();
   float* Y = kGlobal ? scratch + ((size_t)g * nz + k) * n * S : smem;
   ViewTab t = carve_tab(kGlobal ? smem : Y + round4(n * S), n);
+  float* band = kGlobal ? smem + 8 * n : nullptr;   // after the tables (2n entries of 4 floats)
+  if (kGlobal)
+    for (int p = threadIdx.x; p < band_floats(n); p += NT) band[p] = 0.0f;   // guard rows stay zero
   const size_t nn = (size_t)n * n, N = nn * nz;
   float acc[LPW][EPL];
 #pragma unroll
@@ -743,8 +795,12 @@ __global__ __launch_bounds__(NT) void rot_back_kernel(const float* __restrict__ 
     if (!kBil) {
       line_pass<-1, true, EPL>(Y, n, S, t);            // pass 3 transpose
       __syncthreads();
-      line_pass<-1, false, EPL>(Y, n, S, t);           // pass 2 transpose
-      __syncthreads();
+      if (kGlobal) {
+        banded_col_pass<-1, EPL>(Y, n, S, t, band);    // pass 2 transpose
+      } else {
+        line_pass<-1, false, EPL>(Y, n, S, t);         // pass 2 transpose
+        __syncthreads();
+      }
     }
     const float2 cs = tab.rot[l];
     const float cc = 0.5f * (float)(n - 1);
@@ -965,7 +1021,8 @@ hipError_t launch_rot_back(const Plan& p, const float* U, const float* mb, int m
       }
     });
   }
-  const size_t sm = glob ? tab_bytes(n) : (size_t)round4(n * slice_stride(n)) * 4 + tab_bytes(n);
+  const size_t sm = glob ? tab_bytes(n) + band_floats(n) * 4
+                         : (size_t)round4(n * slice_stride(n)) * 4 + tab_bytes(n);
   return with_shape(n, [&](auto E, auto L, auto G) {
     auto go = [&](auto B) {
       hipError_t e = set_smem((const void*)rot_back_kernel<E.value, L.value, G.value, B.value>, sm);
