@@ -9,20 +9,25 @@
 //   forward   out[q] = w.x in[q + o] + w.y in[q + o + 1]
 //   transpose out[q] = w.x in[q - o] + w.y in[q - o - 1]
 // with every sample outside [0, n) equal to zero.  The quarter turn P_m is
-// an affine remapping of the LDS address of the staged, unrotated slice, so
-// the forward kernels stage their input once per workgroup whatever the view;
-// the transpose applies P_m^T last, on the way into the accumulators.
+// an affine remapping of cell addresses; the transpose applies P_m^T last,
+// on the way into the accumulators.
+//
+// Slices that fit LDS (3-pass): rot_fwd_lines_kernel stages P_m x per view
+// into a zero-guarded buffer and runs the three passes in place, each wave
+// owning whole lines, with the attenuation weight fused into the last pass;
+// rot_back_lines_kernel (n <= 128) runs the transposed passes the same way.
+// The attenuation kernel runs the passes in sequence on slices of odd row
+// stride n + 1 (row passes, column passes and quarter-turned reads are then
+// free of bank conflicts).
 //
 // With SPECT_ROT_BILINEAR the three passes are replaced by one 2-D bilinear
 // gather per pixel after the same quarter turn (forward and attenuation), and
 // the transpose gathers, for each pixel, the output pixels whose samples used
-// it (see bil_adj_px).
-//
-// The attenuation and transpose kernels run the passes one after another in
-// LDS, on slices of odd row stride n + 1 (row passes, column passes and
-// quarter-turned reads are then free of bank conflicts), with each wave
-// owning whole lines.  The forward rotation fuses the three passes into one
-// gather per pixel from a single staged slice (see rot_fwd_kernel).
+// it (see bil_adj_px).  rot_fwd_kernel (one gather per output pixel from a
+// single staged slice, the three passes fused or the bilinear sample) and
+// rot_back_kernel (the passes in sequence) serve the bilinear rotation and
+// slices above the LDS limit, whose working slices then live in global
+// scratch.
 #include <algorithm>
 #include <type_traits>
 
