@@ -246,11 +246,60 @@ __device__ __forceinline__ void line_pass(float* Y, int n, int S, const ViewTab&
   }
 }
 
+// ---------------------------------------------------------------- banded column pass
+// Column shear of a working slice Y in global memory (row stride S), for
+// slices too large for LDS.  Lanes along a column would touch one cache line
+// each, so the pass runs through LDS in bands of kBand columns: a band is
+// staged with coalesced row reads into B (rows -1 .. n, stride kBand + 1,
+// rows -1 and n zero: set once by the caller), each wave shears its columns
+// in place (lanes along the rows, one table read per column, sample positions
+// clamped into the zero rows), and the band is written back with coalesced
+// row writes.  Starts and ends with a workgroup barrier.
+constexpr int kBand = 64;
+constexpr int kBandStride = kBand + 1;
+__host__ __device__ __forceinline__ size_t band_floats(int n) { return (size_t)(n + 2) * kBandStride; }
+
+template <int kSgn, int EPL>
+__device__ void banded_col_pass(float* Y, int n, int S, const ViewTab& t, float* B) {
+  float* Bd = B + kBandStride;                     // row r of the band at Bd[r * kBandStride]
+  const int lane = lane_id(), w = wave_id();
+  for (int c0 = 0; c0 < n; c0 += kBand) {
+    __syncthreads();                               // Y written / previous band written back
+    for (int p = threadIdx.x; p < n * kBand; p += NT) {
+      const int r = p / kBand, c = p - r * kBand;
+      Bd[r * kBandStride + c] = c0 + c < n ? Y[r * S + c0 + c] : 0.0f;
+    }
+    __syncthreads();
+    for (int c = w; c < kBand && c0 + c < n; c += NW) {
+      const TabEntry te = t.e2[c0 + c];
+      float v[EPL];
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        const int q = lane + 64 * e;
+        const int qa = min(max(q + kSgn * te.o, -1), n);
+        const int qb = min(max(q + kSgn * (te.o + 1), -1), n);
+        v[e] = te.w.x * Bd[qa * kBandStride + c] + te.w.y * Bd[qb * kBandStride + c];
+      }
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        const int q = lane + 64 * e;
+        if (q < n) Bd[q * kBandStride + c] = v[e];
+      }
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < n * kBand; p += NT) {
+      const int r = p / kBand, c = p - r * kBand;
+      if (c0 + c < n) Y[r * S + c0 + c] = Bd[r * kBandStride + c];
+    }
+  }
+  __syncthreads();
+}
+
 // Passes 1 and 2 of R_l X into Y (and pass 3 when kAllThree; otherwise the
 // caller fuses pass 3 with its output).  Ends with Y complete (barrier).
 template <bool kAllThree, int EPL>
 __device__ __forceinline__ void rotate_into(float* Y, const float* X, int n, int S, int SX, int m,
-                                            const ViewTab& t) {
+                                            const ViewTab& t, float* band = nullptr) {
   const QAddr qa = quarter_addr(m, n, SX);
   const int lane = lane_id();
   for (int j = wave_id(); j < n; j += NW)
@@ -259,9 +308,13 @@ __device__ __forceinline__ void rotate_into(float* Y, const float* X, int n, int
       const int i = lane + 64 * e;
       if (i < n) Y[j * S + i] = pass1_px(X, n, qa, t, i, j);
     }
-  __syncthreads();
-  line_pass<1, false, EPL>(Y, n, S, t);
-  __syncthreads();
+  if (band) {                                          // Y in global memory
+    banded_col_pass<1, EPL>(Y, n, S, t, band);
+  } else {
+    __syncthreads();
+    line_pass<1, false, EPL>(Y, n, S, t);
+    __syncthreads();
+  }
   if (kAllThree) {
     line_pass<1, true, EPL>(Y, n, S, t);
     __syncthreads();
@@ -342,6 +395,10 @@ __global__ __launch_bounds__(NT) void mubar_kernel(const float* __restrict__ mu,
     SX = S;
   }
   ViewTab t = carve_tab(reinterpret_cast<float*>(seg + kScanSeg * n), n);
+  // global working slice: the column pass goes through LDS bands after the tables
+  float* band = kGlobal ? reinterpret_cast<float*>(seg + kScanSeg * n) + 8 * n : nullptr;
+  if (kGlobal && !kBil)
+    for (int p = threadIdx.x; p < band_floats(n); p += NT) band[p] = 0.0f;   // guard rows stay zero
   const int lb0 = blockIdx.y * VG, lb1 = min(nviews, lb0 + VG);
   for (int lb = lb0; lb < lb1; ++lb) {
     const int l = view0 + lb;
@@ -349,7 +406,7 @@ __global__ __launch_bounds__(NT) void mubar_kernel(const float* __restrict__ mu,
     load_tab(tab, l, n, t);
     __syncthreads();
     if (kBil) bil_into<EPL>(Y, X, n, S, SX, tab.quarter[l], t);
-    else rotate_into<true, EPL>(Y, X, n, S, SX, tab.quarter[l], t);
+    else rotate_into<true, EPL>(Y, X, n, S, SX, tab.quarter[l], t, band);
     mubar_scan(Y, seg, n, S, dy);
     float* dst = out + ((size_t)(l - out_view0) * nz + k) * nn;
     for (int p = threadIdx.x; p < n * n; p += NT) {
@@ -692,55 +749,6 @@ __global__ __launch_bounds__(NT) void rot_back_lines_kernel(const float* __restr
   }
 }
 
-// ---------------------------------------------------------------- banded column pass
-// Column shear of a working slice Y in global memory (row stride S), for
-// slices too large for LDS.  Lanes along a column would touch one cache line
-// each, so the pass runs through LDS in bands of kBand columns: a band is
-// staged with coalesced row reads into B (rows -1 .. n, stride kBand + 1,
-// rows -1 and n zero: set once by the caller), each wave shears its columns
-// in place (lanes along the rows, one table read per column, sample positions
-// clamped into the zero rows), and the band is written back with coalesced
-// row writes.  Starts and ends with a workgroup barrier.
-constexpr int kBand = 64;
-constexpr int kBandStride = kBand + 1;
-__host__ __device__ __forceinline__ size_t band_floats(int n) { return (size_t)(n + 2) * kBandStride; }
-
-template <int kSgn, int EPL>
-__device__ void banded_col_pass(float* Y, int n, int S, const ViewTab& t, float* B) {
-  float* Bd = B + kBandStride;                     // row r of the band at Bd[r * kBandStride]
-  const int lane = lane_id(), w = wave_id();
-  for (int c0 = 0; c0 < n; c0 += kBand) {
-    __syncthreads();                               // Y written / previous band written back
-    for (int p = threadIdx.x; p < n * kBand; p += NT) {
-      const int r = p / kBand, c = p - r * kBand;
-      Bd[r * kBandStride + c] = c0 + c < n ? Y[r * S + c0 + c] : 0.0f;
-    }
-    __syncthreads();
-    for (int c = w; c < kBand && c0 + c < n; c += NW) {
-      const TabEntry te = t.e2[c0 + c];
-      float v[EPL];
-#pragma unroll
-      for (int e = 0; e < EPL; ++e) {
-        const int q = lane + 64 * e;
-        const int qa = min(max(q + kSgn * te.o, -1), n);
-        const int qb = min(max(q + kSgn * (te.o + 1), -1), n);
-        v[e] = te.w.x * Bd[qa * kBandStride + c] + te.w.y * Bd[qb * kBandStride + c];
-      }
-#pragma unroll
-      for (int e = 0; e < EPL; ++e) {
-        const int q = lane + 64 * e;
-        if (q < n) Bd[q * kBandStride + c] = v[e];
-      }
-    }
-    __syncthreads();
-    for (int p = threadIdx.x; p < n * kBand; p += NT) {
-      const int r = p / kBand, c = p - r * kBand;
-      if (c0 + c < n) Y[r * S + c0 + c] = Bd[r * kBandStride + c];
-    }
-  }
-  __syncthreads();
-}
-
 // ---------------------------------------------------------------- back
 // grid (nz, G): partial[g][k] (+)= sum over views lb = g, g+G, ... of
 //   P_m^T S1^T S2^T S3^T (U[lb][k] * mubar_l[k]).
@@ -916,7 +924,8 @@ hipError_t launch_mubar(const Plan& p, float* out, int view0, int nviews, int ou
                         hipStream_t s) {
   const int n = p.g.nx;
   const bool glob = n > kMaxLdsN;
-  const size_t sm = glob ? (size_t)kScanSeg * n * 8 + tab_bytes(n) : rotation_lds_bytes(n);
+  const size_t sm = glob ? (size_t)kScanSeg * n * 8 + tab_bytes(n) + band_floats(n) * 4
+                         : rotation_lds_bytes(n);
   const int VG = kRotViewsPerGroup;
   dim3 grid(p.g.nz, (nviews + VG - 1) / VG);
   return with_shape(n, [&](auto E, auto, auto G) {
