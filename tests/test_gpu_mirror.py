@@ -7,8 +7,9 @@ Checks: the selection itself (symmetric PSFs pair, a PSF one ulp away from
 symmetric does not, SPECT_PSF_MIRROR=0 turns pairing off); parity with the
 FP64 oracle at 1e-5 relative L2 on ragged tiles, a one-tap row, a kernel
 wider than the plane, a z-only kernel and several z tiles; the explicit
-matrix adjoint B = A^T within 1e-6; and agreement with the all-taps kernels
-at the paper's 128x128x80 / 37x37 size."""
+matrix adjoint B = A^T within 1e-6; agreement with the all-taps kernels at
+the paper's 128x128x80 / 37x37 size; and spect_plan_describe's report of
+each plan option (precision, rotation, separable PSFs, view batch, tiling)."""
 import sys
 
 import numpy as np
@@ -158,3 +159,26 @@ def test_mirror_matches_all_taps_paper_size(monkeypatch):
     gap = abs(lhs - rhs) / abs(lhs)
     say(f"  forward {ev:.2e}, back {eb:.2e} against all taps; adjoint gap {gap:.2e}")
     assert ev <= 2e-6 and eb <= 2e-6 and gap <= TOL
+
+
+def test_describe_reports_each_path(monkeypatch):
+    """spect_plan_describe names the kernels each plan option selects; pairing
+    applies to the FP32 4x4-block convolution only."""
+    x, mu, psf, dy = synth.config_inputs("tiny", seed=4)
+    mud, psfd = to_dev(mu), to_dev(psf)
+    d = spect.Plan(mud, psfd, dy).describe()
+    assert d["conv"] == "fp32-4x4" and d["mirror"] == "1" and d["rotation"] == "3pass", d
+    assert int(d["view_batch"]) == 16 and int(d["nchunk"]) >= 1 and int(d["rot_views"]) >= 1, d
+    for prec in ("bf16", "fp16", "bf16x3"):
+        d = spect.Plan(mud, psfd, dy, precision=prec).describe()
+        assert d["conv"] == prec and d["mirror"] == "0", d
+    d = spect.Plan(mud, psfd, dy, rotation="bilinear").describe()
+    assert d["rotation"] == "bilinear" and d["mirror"] == "1", d
+    fz, fx = synth.gaussian_psf_factors(7, 7, 32, 16, 0.5, 2.0)
+    d = spect.Plan(mud, (to_dev(fz), to_dev(fx)), dy).describe()
+    assert d["conv"] == "separable" and d["mirror"] == "0", d
+    d = spect.Plan(mud, psfd, dy, view_batch=5).describe()
+    assert int(d["view_batch"]) == 5, d
+    monkeypatch.setenv("SPECT_FP32_TILING", "16x16")
+    d = spect.Plan(mud, psfd, dy).describe()
+    assert d["conv"] == "fp32-16x16" and d["mirror"] == "0", d
