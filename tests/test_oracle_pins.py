@@ -460,3 +460,93 @@ def test_osem_subset_projector_restricts_views():
         gs = Geometry(nx, nx, nz, len(views), 3, 3, 2.0, angles=ang)
         np.testing.assert_allclose(oracle.forward(x, mu, psf[views], gs), full[views], rtol=1e-13,
                                    atol=1e-13 * np.abs(full).max())
+
+
+def _osem_problem(nx=12, nz=4, nview=16, seed=5):
+    """A small problem whose activity lies inside the disk that every view's
+    rotation keeps on the grid, so each subset's sensitivity A_s'1 is positive
+    on the support.  Views and PSFs per subset come from the full arrays."""
+    x, mu = synth.body_phantom(nx, nx, nz, seed=seed)
+    c = (nx - 1) / 2.0
+    jj, ii = np.meshgrid(np.arange(nx), np.arange(nx), indexing="ij")
+    disk = ((ii - c) ** 2 + (jj - c) ** 2 <= (0.4 * nx) ** 2)[None, :, :]
+    xt = np.where(disk, x.astype(np.float64) + 0.2, 0.0)
+    psf = synth.random_psf(3, 3, nx, nview, seed=seed + 1, symmetric=False)
+    dy = 4.8 * 128 / nx
+
+    def geom(views):
+        return Geometry(nx, nx, nz, len(views), 3, 3, dy,
+                        angles=[2 * math.pi * l / nview for l in views])
+
+    return xt, disk, mu, psf, geom
+
+
+def _subset_ops(mu, psf, geom, subs, calls=None):
+    def A_sub(s, z):
+        if calls is not None:
+            calls.append((s, np.array(z, dtype=np.float64)))
+        g = geom(subs[s])
+        return oracle.forward(np.asarray(z).reshape(g.nz, g.ny, g.nx), mu, psf[subs[s]], g)
+
+    def At_sub(s, v):
+        return oracle.back(v, mu, psf[subs[s]], geom(subs[s]))
+    return A_sub, At_sub
+
+
+@pytest.mark.parametrize("nsub", [2, 4, 8])
+def test_osem_subset_fixed_point_and_count_preservation(nsub):
+    """OSEM with several subsets (Sec. III-A compares OSEM reconstructions;
+    each subset update is Eq. (7)-(8) with beta -> 0 on that subset's rows).
+    With consistent noiseless data y = A x* and r = 0, every subset update
+    maps x* to x* * A_s'1 / A_s'1 = x*, so x* is a fixed point of whole
+    iterations.  From any start, a subset update with its own sensitivity
+    A_s'1 preserves that subset's counts: 1'A_s x+ = 1'y_s (r = 0).  Both
+    facts fail if a subset divides by another sensitivity (e.g. the full
+    A'1), as the negative control below shows."""
+    nview = 16
+    xt, disk, mu, psf, geom = _osem_problem(nview=nview)
+    subs = em.osem_subsets(nview, nsub)
+    A_sub, At_sub = _subset_ops(mu, psf, geom, subs)
+    full = geom(list(range(nview)))
+    y = oracle.forward(xt, mu, psf, full)
+    support = np.broadcast_to(disk, xt.shape)
+    for s, views in enumerate(subs):
+        assert (At_sub(s, np.ones((len(views),) + y.shape[1:]))[support] > 0).all()
+    x2 = em.osem(xt, y, None, A_sub, At_sub, nview, nsub, 2)
+    np.testing.assert_allclose(x2, xt, rtol=1e-12, atol=1e-12 * xt.max())
+
+    # counts per subset from a flat start with noisy data: record the iterate
+    # handed to each subset's projector (the iterate before that subset's
+    # update); the iterate after the last update is osem's return value
+    yn = synth.poisson_counts(y * 40.0, seed=11).astype(np.float64) / 40.0
+    calls = []
+    A_rec, _ = _subset_ops(mu, psf, geom, subs, calls)
+    x_end = em.osem(np.ones_like(xt), yn, None, A_rec, At_sub, nview, nsub, 2)
+    after = [z for _, z in calls[1:]] + [x_end]
+    assert len(calls) == 2 * nsub
+    for (s, _), xp in zip(calls, after):
+        got = A_sub(s, xp).sum()
+        want = yn[subs[s]].sum()
+        assert abs(got - want) <= 1e-10 * want, (nsub, s, got, want)
+
+
+def test_osem_full_sensitivity_in_every_subset_fails():
+    """Negative control for the pin above: an OSEM that divides every subset
+    update by the full sensitivity A'1 (a plausible mistake) moves x* and
+    breaks the per-subset count identity far beyond the tolerances used."""
+    nview, nsub = 16, 4
+    xt, disk, mu, psf, geom = _osem_problem(nview=nview)
+    subs = em.osem_subsets(nview, nsub)
+    A_sub, At_sub = _subset_ops(mu, psf, geom, subs)
+    full = geom(list(range(nview)))
+    y = oracle.forward(xt, mu, psf, full)
+    sens_full = oracle.back(np.ones(y.shape), mu, psf, full)
+    x = xt.copy()
+    for s, views in enumerate(subs):
+        x = em.mlem_step(x, y[views], None, sens_full, lambda z, s=s: A_sub(s, z),
+                         lambda v, s=s: At_sub(s, v))
+    assert np.abs(x - xt).max() > 1e-3 * xt.max()
+    x0 = np.ones_like(xt)
+    x1 = em.mlem_step(x0, y[subs[0]], None, sens_full, lambda z: A_sub(0, z),
+                      lambda v: At_sub(0, v))
+    assert abs(A_sub(0, x1).sum() - y[subs[0]].sum()) > 1e-3 * y[subs[0]].sum()
