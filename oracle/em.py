@@ -55,7 +55,7 @@ def reg_em_update(x, e, sens, u, beta):
                     (-d + disc) / (2.0 * beta))
 
 
-def mlem_step_vjp(x, y, r, sens, g, A, At):
+def mlem_step_vjp(x, y, r, sens, g, A, At, ybar=None, b=None):
     """Reverse-mode derivative of ``mlem_step`` (the unrolled EM iterations of
     Sec. II-B are trained by backpropagation).  For x+ = x * b / s with
     b = At(rho), rho = y / ybar, ybar = A x + r and upstream g = dL/dx+, the
@@ -67,13 +67,18 @@ def mlem_step_vjp(x, y, r, sens, g, A, At):
       dL/dybar = -dL/drho * y / ybar^2
       dL/dx  += At(dL/dybar)            (ybar = A x + r)
 
-    Returns (dL/dx, dL/dy).  A and At are callables; FP64 throughout."""
+    Returns (dL/dx, dL/dy).  A and At are callables; FP64 throughout.
+    ``ybar`` and ``b``, when given, are the step's own A x + r and
+    At(y / ybar) (as the forward step computed them); otherwise they are
+    recomputed from x."""
     x = np.asarray(x, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
     g = np.asarray(g, dtype=np.float64)
     sens = np.asarray(sens, dtype=np.float64)
-    ybar = A(x) + (0.0 if r is None else np.asarray(r, dtype=np.float64))
-    b = At(ratio(y, ybar))
+    if ybar is None:
+        ybar = A(x) + (0.0 if r is None else np.asarray(r, dtype=np.float64))
+    if b is None:
+        b = At(ratio(y, ybar))
     okx = sens > 0
     g_b = np.zeros_like(x)
     g_b[okx] = g[okx] * x[okx] / sens[okx]
@@ -92,14 +97,26 @@ def mlem_step_vjp(x, y, r, sens, g, A, At):
 def unrolled_mlem_grad(x0, y, r, sens, A, At, iters, loss_grad):
     """x_K after ``iters`` ML-EM updates from x0, and the gradients of a loss
     L(x_K) with respect to x0 and y.  ``loss_grad(x_K)`` returns
-    (L, dL/dx_K).  Plain reverse accumulation over the stored iterates."""
+    (L, dL/dx_K).  Plain reverse accumulation over the stored iterates; each
+    step's A x + r and At(y / (A x + r)) are kept from the forward sweep, so
+    the backward sweep projects only the two new directions per step."""
+    rr = 0.0 if r is None else np.asarray(r, dtype=np.float64)
     xs = [np.asarray(x0, dtype=np.float64)]
+    saved = []
+    s64 = np.asarray(sens, dtype=np.float64)
     for _ in range(iters):
-        xs.append(mlem_step(xs[-1], y, r, sens, A, At))
+        x = xs[-1]
+        ybar = A(x) + rr
+        b = At(ratio(y, ybar))
+        out = np.zeros_like(x)
+        ok = s64 > 0
+        out[ok] = x[ok] * b[ok] / s64[ok]
+        saved.append((ybar, b))
+        xs.append(out)
     loss, g = loss_grad(xs[-1])
     gy = np.zeros_like(np.asarray(y, dtype=np.float64))
     for k in range(iters - 1, -1, -1):
-        g, gyk = mlem_step_vjp(xs[k], y, r, sens, g, A, At)
+        g, gyk = mlem_step_vjp(xs[k], y, r, sens, g, A, At, ybar=saved[k][0], b=saved[k][1])
         gy = gy + gyk
     return xs[-1], loss, g, gy
 
