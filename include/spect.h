@@ -92,6 +92,22 @@ typedef enum {
                                     (2 (px + pz) instead of 2 px pz FLOP per voxel).  FP32
                                     only: with another conv_precision, or a strip that does
                                     not fit the kernel's LDS, SPECT_ERR_UNSUPPORTED. */
+#define SPECT_PSF_ALL_TAPS 0x8u /* never pair mirror-image PSF taps (see spect_plan_create);
+                                   the plan then waits for nothing */
+#define SPECT_PSF_SYMMETRIC_X 0x10u /* the caller states that every PSF row is its own
+                                       mirror image in x, p[b][a] == p[b][px-1-a] (a centred
+                                       Gaussian is): the FP32 4x4-block convolution pairs
+                                       taps without checking on the device, and plan
+                                       creation waits for nothing.  With a PSF that is not
+                                       symmetric, the operator computed is that of the PSF
+                                       p'[b][a] = p[b][min(a, px-1-a)].  Exclusive with
+                                       SPECT_PSF_ALL_TAPS (else SPECT_ERR_VALUE). */
+#define SPECT_TILING_4X4 0x20u  /* FP32 convolution on 4x4 matrix blocks when the shape
+                                   fits them (else 16x16 blocks), instead of the plan's
+                                   cost model */
+#define SPECT_TILING_16X16 0x40u /* FP32 convolution as 16x16x4 Toeplitz blocks, instead of
+                                    the plan's cost model.  Exclusive with SPECT_TILING_4X4
+                                    (else SPECT_ERR_VALUE). */
 
 /* Geometry of one plan (host struct, copied by spect_plan_create). */
 typedef struct {
@@ -102,8 +118,9 @@ typedef struct {
   const double* angles;   /* host array of nview angles in radians, or NULL for
                              theta_l = 2 pi l / nview (Sec. II-A); read only
                              during spect_plan_create */
-  uint32_t flags;         /* SPECT_CACHE_MUBAR | SPECT_ROT_BILINEAR | SPECT_PSF_SEPARABLE,
-                             or 0; other bits give SPECT_ERR_VALUE */
+  uint32_t flags;         /* SPECT_CACHE_MUBAR | SPECT_ROT_BILINEAR | SPECT_PSF_SEPARABLE |
+                             SPECT_PSF_ALL_TAPS | SPECT_PSF_SYMMETRIC_X | SPECT_TILING_4X4 |
+                             SPECT_TILING_16X16, or 0; other bits give SPECT_ERR_VALUE */
   int32_t view_batch;     /* views processed per internal batch; 0 = all.
                              Smaller batches need less workspace. */
   int32_t conv_precision; /* SPECT_CONV_FP32 (0), SPECT_CONV_BF16, SPECT_CONV_FP16 or
@@ -121,13 +138,14 @@ spect_status spect_workspace_bytes(const spect_geom* g, size_t* bytes);
  * (>= spect_workspace_bytes, 256-byte aligned).  All three are borrowed.
  * Enqueues the upload of the per-view shear tables (and, with
  * SPECT_CACHE_MUBAR, the attenuation-factor precomputation) on `stream`.
- * When the FP32 convolution runs on 4x4 blocks, it also checks on the device
- * whether every PSF row is its own mirror image in x (p[b][a] == p[b][px-1-a]
- * exactly, as for a centred Gaussian or any circularly symmetric response);
- * if so the convolution pairs taps a and px-1-a, adding the two input columns
- * before one product ((px + 1) / 2 products per row instead of px, the same
- * operator up to FP32 rounding).  That check waits for `stream`.  Setting the
- * environment variable SPECT_PSF_MIRROR=0 skips it and keeps every tap. */
+ * When the FP32 convolution runs on 4x4 blocks and neither SPECT_PSF_ALL_TAPS
+ * nor SPECT_PSF_SYMMETRIC_X is set, it also checks on the device whether every
+ * PSF row is its own mirror image in x (p[b][a] == p[b][px-1-a] exactly, as
+ * for a centred Gaussian or any circularly symmetric response); if so the
+ * convolution pairs taps a and px-1-a, adding the two input columns before
+ * one product ((px + 1) / 2 products per row instead of px, the same operator
+ * up to FP32 rounding).  That check waits for `stream`; the two flags skip it
+ * (keep every tap, or pair on the caller's word). */
 spect_status spect_plan_create(spect_plan* out, const spect_geom* g,
                                const float* d_mu, const float* d_psf,
                                void* d_workspace, size_t ws_bytes,
@@ -218,7 +236,8 @@ const char* spect_version(void);
 
 /* The kernels a plan selected, as one line of key=value pairs written to buf
  * (NUL-terminated, truncated to len bytes): conv = fp32-4x4 | fp32-16x16 |
- * separable | bf16 | fp16 | bf16x3, mirror = 1 when the FP32 4x4-block
+ * fp32-direct (plain FP32 kernels, for PSFs taller than the matrix-core tiles
+ * hold: pz >= 67) | separable | bf16 | fp16 | bf16x3, mirror = 1 when the FP32 4x4-block
  * convolution pairs mirror-image taps (see spect_plan_create), rotation =
  * 3pass | bilinear, view_batch, nchunk, rot_views (views per workgroup of
  * the forward rotation).  Host only. */

@@ -5,9 +5,11 @@
 namespace spect {
 namespace {
 
-// rho = y / (v + r), 0 where the mean v + r <= 0.
-__global__ void em_ratio_kernel(const float* __restrict__ v, const float* __restrict__ y,
-                                const float* __restrict__ r, float* __restrict__ rho, size_t m) {
+// rho = y / (v + r), 0 where the mean v + r <= 0.  rho may be v (the EM step
+// overwrites its projection in place): each element is read before it is
+// written by the same thread, so v and rho carry no __restrict__.
+__global__ void em_ratio_kernel(const float* v, const float* __restrict__ y,
+                                const float* __restrict__ r, float* rho, size_t m) {
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= m) return;
   const float ybar = v[q] + (r ? r[q] : 0.0f);
@@ -50,10 +52,12 @@ __global__ void em_reg_update_kernel(float* __restrict__ x, const float* __restr
 // gradient.  The projections t and A'(gq) run on the projector kernels; the
 // steps below are the element-wise parts.
 
-// gb = g x / s and gx = g b / s (0 where s <= 0).
-__global__ void em_vjp_prep_kernel(const float* __restrict__ g, const float* __restrict__ x,
+// gb = g x / s and gx = g b / s (0 where s <= 0).  gx may be g (the C ABI
+// allows the gradient to be updated in place), so those two are not
+// __restrict__; each element of g is read before gx is written.
+__global__ void em_vjp_prep_kernel(const float* g, const float* __restrict__ x,
                                    const float* __restrict__ b, const float* __restrict__ sens,
-                                   float* __restrict__ gb, float* __restrict__ gx, size_t n) {
+                                   float* __restrict__ gb, float* gx, size_t n) {
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
   const float s = sens[q];

@@ -19,8 +19,12 @@ static spect_status validate(const spect_geom* g) {
   if (g->nx != g->ny) return SPECT_ERR_SHAPE;              // rotation about z needs a square slice
   if ((g->px & 1) == 0 || (g->pz & 1) == 0) return SPECT_ERR_SHAPE;  // centred odd kernels
   if (!(std::isfinite(g->dy) && g->dy > 0.0)) return SPECT_ERR_VALUE;
-  if (g->flags & ~(SPECT_CACHE_MUBAR | SPECT_ROT_BILINEAR | SPECT_PSF_SEPARABLE))
+  if (g->flags & ~(SPECT_CACHE_MUBAR | SPECT_ROT_BILINEAR | SPECT_PSF_SEPARABLE |
+                   SPECT_PSF_ALL_TAPS | SPECT_PSF_SYMMETRIC_X | SPECT_TILING_4X4 |
+                   SPECT_TILING_16X16))
     return SPECT_ERR_VALUE;
+  if ((g->flags & SPECT_PSF_ALL_TAPS) && (g->flags & SPECT_PSF_SYMMETRIC_X)) return SPECT_ERR_VALUE;
+  if ((g->flags & SPECT_TILING_4X4) && (g->flags & SPECT_TILING_16X16)) return SPECT_ERR_VALUE;
   if (g->view_batch < 0) return SPECT_ERR_VALUE;
   if (g->conv_precision != SPECT_CONV_FP32 && g->conv_precision != SPECT_CONV_BF16 &&
       g->conv_precision != SPECT_CONV_FP16 && g->conv_precision != SPECT_CONV_BF16X3)
@@ -169,8 +173,9 @@ spect_status spect_plan_describe(spect_plan plan, char* buf, size_t len) {
   static const char* const kLp[] = {"fp32", "bf16", "fp16", "bf16x3"};
   const char* conv = p->separable ? "separable"
                      : p->conv_precision != SPECT_CONV_FP32 ? kLp[p->conv_precision & 3]
-                     : p->use_m4 ? "fp32-4x4"
-                                 : "fp32-16x16";
+                     : p->use_m4    ? "fp32-4x4"
+                     : p->use_mfma  ? "fp32-16x16"
+                                    : "fp32-direct";
   const bool mirror = p->use_m4 && p->conv_precision == SPECT_CONV_FP32 && p->m4.mirror;
   std::snprintf(buf, len, "conv=%s mirror=%d rotation=%s view_batch=%d nchunk=%d rot_views=%d",
                 conv, mirror ? 1 : 0, p->bilinear ? "bilinear" : "3pass", p->view_batch, p->nchunk,
@@ -269,11 +274,10 @@ spect_status spect_plan_create(spect_plan* out, const spect_geom* g, const float
   } else if (p->use_mfma) {
     tune_conv_chunks(p->conv, g->nview);   // independent of view_batch: same sums
     p->nchunk = p->conv.nchunk;          // forward partial sums per view
-    // SPECT_FP32_TILING = "4x4" or "16x16" overrides the cost model ("auto")
-    const char* tiling = std::getenv("SPECT_FP32_TILING");
+    // SPECT_TILING_4X4 / SPECT_TILING_16X16 override the cost model
     bool m4 = m4_preferred(p->m4, p->conv);
-    if (tiling && std::strcmp(tiling, "4x4") == 0) m4 = p->m4.ok;
-    if (tiling && std::strcmp(tiling, "16x16") == 0) m4 = false;
+    if (g->flags & SPECT_TILING_4X4) m4 = p->m4.ok;
+    if (g->flags & SPECT_TILING_16X16) m4 = false;
     if (m4) {
       tune_m4_chunks(p->m4, g->nview);
       p->use_m4 = true;
@@ -288,10 +292,12 @@ spect_status spect_plan_create(spect_plan* out, const spect_geom* g, const float
   }
   // PSF rows symmetric in x (a centred Gaussian, any circularly symmetric
   // response): the 4x4-block kernels pair taps a and px-1-a.  Checked exactly
-  // on the device; SPECT_PSF_MIRROR=0 keeps every tap.
+  // on the device unless the caller states the symmetry (SPECT_PSF_SYMMETRIC_X)
+  // or asks for every tap (SPECT_PSF_ALL_TAPS).
   if (e == hipSuccess && p->use_m4 && p->conv_precision == SPECT_CONV_FP32) {
-    const char* mirror = std::getenv("SPECT_PSF_MIRROR");
-    if (!(mirror && std::strcmp(mirror, "0") == 0))
+    if (g->flags & SPECT_PSF_SYMMETRIC_X)
+      p->m4.mirror = true;
+    else if (!(g->flags & SPECT_PSF_ALL_TAPS))
       e = detect_m4_mirror(*p, reinterpret_cast<int*>(p->ws + lay.em_vol), stream);
   }
   if (g->flags & SPECT_CACHE_MUBAR) {

@@ -21,6 +21,12 @@ SPECT_OK = 0
 SPECT_CACHE_MUBAR = 0x1
 SPECT_ROT_BILINEAR = 0x2
 SPECT_PSF_SEPARABLE = 0x4
+SPECT_PSF_ALL_TAPS = 0x8
+SPECT_PSF_SYMMETRIC_X = 0x10
+SPECT_TILING_4X4 = 0x20
+SPECT_TILING_16X16 = 0x40
+MIRRORS = {"auto": 0, "off": SPECT_PSF_ALL_TAPS, "assume": SPECT_PSF_SYMMETRIC_X}
+TILINGS = {"auto": 0, "4x4": SPECT_TILING_4X4, "16x16": SPECT_TILING_16X16}
 ROTATIONS = {"3pass": 0, "bilinear": SPECT_ROT_BILINEAR}
 SPECT_CONV_FP32, SPECT_CONV_BF16, SPECT_CONV_FP16, SPECT_CONV_BF16X3 = 0, 1, 2, 3
 PRECISIONS = {"fp32": SPECT_CONV_FP32, "bf16": SPECT_CONV_BF16, "fp16": SPECT_CONV_FP16,
@@ -224,10 +230,15 @@ class Plan:
     or for separable PSFs p[b][a] = fz[b] fx[a] the pair (fz, fx) with
     fz: [nview][ny][pz] and fx: [nview][ny][px] (packed here into the
     [nview][ny][pz + px] layout of SPECT_PSF_SEPARABLE).
+
+    mirror: "auto" (pair mirror-image taps when the device check finds every
+    PSF row symmetric in x), "off" (SPECT_PSF_ALL_TAPS) or "assume"
+    (SPECT_PSF_SYMMETRIC_X: the caller states the symmetry; no check, no
+    wait).  tiling: "auto", "4x4" or "16x16" (the FP32 convolution's blocks).
     """
 
     def __init__(self, mu, psf, dy, angles=None, cache_mubar=False, view_batch=0,
-                 precision="fp32", rotation="3pass"):
+                 precision="fp32", rotation="3pass", mirror="auto", tiling="auto"):
         import torch
         self.device = mu.device
         if self.device.type != "cuda":
@@ -255,8 +266,12 @@ class Plan:
         if rotation not in ROTATIONS:
             raise ValueError(f"rotation must be one of {sorted(ROTATIONS)}")
         self.rotation = rotation
+        if mirror not in MIRRORS:
+            raise ValueError(f"mirror must be one of {sorted(MIRRORS)}")
+        if tiling not in TILINGS:
+            raise ValueError(f"tiling must be one of {sorted(TILINGS)}")
         flags = ((SPECT_CACHE_MUBAR if cache_mubar else 0) | ROTATIONS[rotation] |
-                 (SPECT_PSF_SEPARABLE if sep else 0))
+                 (SPECT_PSF_SEPARABLE if sep else 0) | MIRRORS[mirror] | TILINGS[tiling])
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
         self.precision = precision

@@ -51,8 +51,9 @@ def test_status_strings():
     (dict(nview=0), 2),
     (dict(dy=0.0), 3),
     (dict(dy=float("nan")), 3),
-    (dict(flags=0x10), 3),
-    (dict(flags=0x8), 3),
+    (dict(flags=0x80), 3),            # unknown flag bit
+    (dict(flags=0x18), 3),            # all taps and stated symmetry together
+    (dict(flags=0x60), 3),            # both FP32 tilings together
     (dict(flags=0x4, conv_precision=1), 5),   # separable PSFs: FP32 only
     (dict(view_batch=-1), 3),
     (dict(nx=300, ny=300), 5),        # in-plane size above the largest supported (256)
@@ -147,3 +148,23 @@ def test_conv_precision_validation():
         with pytest.raises(spect.SpectError) as e:
             spect.spect_workspace_bytes(g)
         assert e.value.status == 3
+
+
+def test_plan_choice_flags_keep_the_workspace():
+    """The tap-pairing and tiling flags only change kernel selection."""
+    ws = lambda f: spect.spect_workspace_bytes(spect.make_geom(32, 32, 20, 16, 7, 7, 1.0, flags=f)[0])
+    for f in (spect.SPECT_PSF_ALL_TAPS, spect.SPECT_PSF_SYMMETRIC_X, spect.SPECT_TILING_4X4,
+              spect.SPECT_TILING_16X16, spect.SPECT_PSF_SYMMETRIC_X | spect.SPECT_TILING_4X4):
+        assert ws(f) == ws(0)
+
+
+def test_direct_convolution_shape_is_accepted_in_fp32_only():
+    """PSFs taller than the matrix-core tiles hold (pz >= 67) run on the plain
+    FP32 kernels; the reduced-precision forms need the tiles."""
+    g, _ = spect.make_geom(32, 32, 80, 16, 9, 69, 1.0)
+    assert spect.spect_workspace_bytes(g) > 0
+    for prec in (1, 2, 3):
+        g, _ = spect.make_geom(32, 32, 80, 16, 9, 69, 1.0, conv_precision=prec)
+        with pytest.raises(spect.SpectError) as e:
+            spect.spect_workspace_bytes(g)
+        assert e.value.status == 5

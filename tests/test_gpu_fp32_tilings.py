@@ -1,8 +1,8 @@
 """The two FP32 tilings of the PSF convolution, each forced at plan creation
-through SPECT_FP32_TILING: 16x16x4 Toeplitz blocks ("16x16") and 4x4x1 blocks
-("4x4", which pairs mirror-image taps when the PSF rows are symmetric in x;
-"4x4/all-taps" turns the pairing off through SPECT_PSF_MIRROR=0), against the
-FP64 oracle.
+through the SPECT_TILING_* flags: 16x16x4 Toeplitz blocks ("16x16") and 4x4x1
+blocks ("4x4", which pairs mirror-image taps when the PSF rows are symmetric
+in x; "4x4/all-taps" turns the pairing off through SPECT_PSF_ALL_TAPS),
+against the FP64 oracle.
 
 The plan picks a tiling per shape from its cost model (4x4 blocks at the
 paper's 128x128x80 / 37x37 workload, 16x16 blocks on most small shapes), so
@@ -33,11 +33,11 @@ TOL = 1e-5
 TILINGS = ["4x4", "4x4/all-taps", "16x16"]
 
 
-def force(monkeypatch, tiling):
-    """Select a tiling (and whether the 4x4 kernels may pair mirror-image
-    taps) for the plans created next."""
-    monkeypatch.setenv("SPECT_FP32_TILING", tiling.split("/")[0])
-    monkeypatch.setenv("SPECT_PSF_MIRROR", "0" if tiling.endswith("/all-taps") else "1")
+def force(tiling):
+    """Plan keywords selecting a tiling (and whether the 4x4 kernels may pair
+    mirror-image taps)."""
+    return dict(tiling=tiling.split("/")[0],
+                mirror="off" if tiling.endswith("/all-taps") else "auto")
 
 
 def check_selection(plan, tiling, symmetric):
@@ -79,8 +79,7 @@ CASES = [
 
 @pytest.mark.parametrize("tiling", TILINGS)
 @pytest.mark.parametrize("case", CASES)
-def test_tiling_parity(case, tiling, monkeypatch):
-    force(monkeypatch, tiling)
+def test_tiling_parity(case, tiling):
     nx, nz, nview, px, pz, sym = case
     say(f"tiling {tiling} {case}")
     seed = 7 * nx + nz
@@ -89,7 +88,7 @@ def test_tiling_parity(case, tiling, monkeypatch):
     psf = synth.random_psf(px, pz, nx, nview, seed=seed + 2, symmetric=sym)
     dy = 1.5
     g = Geometry(nx, nx, nz, nview, px, pz, dy)
-    plan = spect.Plan(to_dev(mu), to_dev(psf), dy)
+    plan = spect.Plan(to_dev(mu), to_dev(psf), dy, **force(tiling))
     check_selection(plan, tiling, sym)
     v = host(plan.forward(to_dev(x)))
     ef = rel_l2(v, oracle.forward(x, mu, psf, g))
@@ -101,9 +100,8 @@ def test_tiling_parity(case, tiling, monkeypatch):
 
 
 @pytest.mark.parametrize("tiling", TILINGS)
-def test_tiling_dense_adjoint(tiling, monkeypatch):
+def test_tiling_dense_adjoint(tiling):
     """Explicit A and B on 8x8x6 / 7 views: B = A^T to 1e-6 relative."""
-    force(monkeypatch, tiling)
     nx, nz, nview, px = 8, 6, 7, 3
     N, M = nx * nx * nz, nview * nz * nx
     eyeN = torch.eye(N, device=DEV).reshape(N, nz, nx, nx)
@@ -112,7 +110,7 @@ def test_tiling_dense_adjoint(tiling, monkeypatch):
     for rep in range(5):
         mu = synth.random_volume(nx, nx, nz, seed=300 + rep, high=0.3)
         psf = synth.random_psf(px, px, nx, nview, seed=400 + rep, symmetric=False)
-        plan = spect.Plan(to_dev(mu), to_dev(psf), 1.0)
+        plan = spect.Plan(to_dev(mu), to_dev(psf), 1.0, **force(tiling))
         At = torch.empty(N, nview, nz, nx, device=DEV)
         B = torch.empty(M, nz, nx, nx, device=DEV)
         for c in range(N):
@@ -141,10 +139,10 @@ def paper():
 
 
 @pytest.mark.parametrize("tiling", TILINGS)
-def test_tiling_paper_sampled(paper, tiling, monkeypatch):
-    force(monkeypatch, tiling)
+def test_tiling_paper_sampled(paper, tiling):
     say(f"tiling {tiling}: paper size")
-    plan = spect.Plan(to_dev(paper["mu"]), to_dev(paper["psf"]), paper["dy"], cache_mubar=True)
+    plan = spect.Plan(to_dev(paper["mu"]), to_dev(paper["psf"]), paper["dy"], cache_mubar=True,
+                      **force(tiling))
     check_selection(plan, tiling, True)
     xd = to_dev(paper["x"])
     v = host(plan.forward(xd))

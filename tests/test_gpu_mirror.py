@@ -4,7 +4,8 @@ responses), taps a and px-1-a share one matrix product on the sum of their
 two input columns.  The plan detects the symmetry exactly on the device.
 
 Checks: the selection itself (symmetric PSFs pair, a PSF one ulp away from
-symmetric does not, SPECT_PSF_MIRROR=0 turns pairing off); parity with the
+symmetric does not, SPECT_PSF_ALL_TAPS turns pairing off, SPECT_PSF_SYMMETRIC_X
+pairs without the check); parity with the
 FP64 oracle at 1e-5 relative L2 on ragged tiles, a one-tap row, a kernel
 wider than the plane, a z-only kernel and several z tiles; the explicit
 matrix adjoint B = A^T within 1e-6; agreement with the all-taps kernels at
@@ -51,10 +52,11 @@ def host(t):
     return t.cpu().numpy()
 
 
-@pytest.fixture(autouse=True)
-def four_by_four(monkeypatch):
-    monkeypatch.setenv("SPECT_FP32_TILING", "4x4")
-    monkeypatch.setenv("SPECT_PSF_MIRROR", "1")
+def Plan(*a, **kw):
+    """A plan on the 4x4-block FP32 tiling (pairing chosen by the device check
+    unless `mirror` says otherwise)."""
+    kw.setdefault("tiling", "4x4")
+    return spect.Plan(*a, **kw)
 
 
 CASES = [
@@ -78,7 +80,7 @@ def test_mirror_parity(case):
     psf = synth.random_psf(px, pz, nx, nview, seed=seed + 2, symmetric=True)
     assert np.array_equal(psf, psf[..., ::-1])
     g = Geometry(nx, nx, nz, nview, px, pz, 1.5)
-    plan = spect.Plan(to_dev(mu), to_dev(psf), 1.5)
+    plan = Plan(to_dev(mu), to_dev(psf), 1.5)
     assert plan.describe()["mirror"] == "1", plan.describe()
     ef = rel_l2(host(plan.forward(to_dev(x))), oracle.forward(x, mu, psf, g))
     y = synth.random_volume(nx, nz, nview, seed=seed + 3)
@@ -95,19 +97,32 @@ def test_one_ulp_from_symmetric_keeps_every_tap():
     mu = synth.random_volume(nx, nx, nz, seed=6, high=0.05)
     psf = synth.random_psf(px, pz, nx, nview, seed=7, symmetric=True)
     psf[3, 17, 2, 1] = np.nextafter(psf[3, 17, 2, 1], np.float32(1.0))
-    plan = spect.Plan(to_dev(mu), to_dev(psf), 1.2)
+    plan = Plan(to_dev(mu), to_dev(psf), 1.2)
     assert plan.describe()["mirror"] == "0", plan.describe()
     g = Geometry(nx, nx, nz, nview, px, pz, 1.2)
     assert rel_l2(host(plan.forward(to_dev(x))), oracle.forward(x, mu, psf, g)) <= TOL
     # the same PSF made symmetric again pairs
     psf[3, 17, 2, 1] = psf[3, 17, 2, px - 2]
-    assert spect.Plan(to_dev(mu), to_dev(psf), 1.2).describe()["mirror"] == "1"
+    assert Plan(to_dev(mu), to_dev(psf), 1.2).describe()["mirror"] == "1"
 
 
-def test_switch_off(monkeypatch):
-    monkeypatch.setenv("SPECT_PSF_MIRROR", "0")
+def test_switch_off():
     x, mu, psf, dy = synth.config_inputs("tiny", seed=1)
-    assert spect.Plan(to_dev(mu), to_dev(psf), dy).describe()["mirror"] == "0"
+    assert Plan(to_dev(mu), to_dev(psf), dy, mirror="off").describe()["mirror"] == "0"
+
+
+def test_stated_symmetry_pairs_without_check():
+    """SPECT_PSF_SYMMETRIC_X: the caller states the symmetry, the plan pairs
+    without the device check; on symmetric PSFs the results are those of the
+    checked plan, bit for bit (the same kernels)."""
+    x, mu, psf, dy = synth.config_inputs("tiny", seed=2)
+    xd, mud, psfd = to_dev(x), to_dev(mu), to_dev(psf)
+    stated = Plan(mud, psfd, dy, mirror="assume")
+    checked = Plan(mud, psfd, dy)
+    assert stated.describe()["mirror"] == "1" and checked.describe()["mirror"] == "1"
+    assert np.array_equal(host(stated.forward(xd)), host(checked.forward(xd)))
+    y = to_dev(synth.random_volume(32, 20, 16, seed=3))
+    assert np.array_equal(host(stated.back(y)), host(checked.back(y)))
 
 
 def test_mirror_dense_adjoint():
@@ -120,7 +135,7 @@ def test_mirror_dense_adjoint():
     eyeM = torch.eye(M, device=DEV).reshape(M, nview, nz, nx)
     mu = synth.random_volume(nx, nx, nz, seed=31, high=0.3)
     psf = synth.random_psf(px, px, nx, nview, seed=32, symmetric=True)
-    plan = spect.Plan(to_dev(mu), to_dev(psf), 1.0)
+    plan = Plan(to_dev(mu), to_dev(psf), 1.0)
     assert plan.describe()["mirror"] == "1"
     At = torch.empty(N, nview, nz, nx, device=DEV)
     B = torch.empty(M, nz, nx, nx, device=DEV)
@@ -138,7 +153,7 @@ def test_mirror_dense_adjoint():
     assert et <= 1e-6 and eo <= 1e-6
 
 
-def test_mirror_matches_all_taps_paper_size(monkeypatch):
+def test_mirror_matches_all_taps_paper_size():
     """128x128x80, 128 views, 37x37 Gaussian PSFs: paired and all-taps
     kernels agree to FP32 rounding, and the paired pair keeps the adjoint
     identity at full size."""
@@ -146,13 +161,12 @@ def test_mirror_matches_all_taps_paper_size(monkeypatch):
     x, mu, psf, dy = synth.config_inputs("paper", seed=3, view_wobble=0.1)
     xd, mud, psfd = to_dev(x), to_dev(mu), to_dev(psf)
     yd = to_dev(np.random.default_rng(9).uniform(0.0, 1.0, (128, 80, 128)))
-    paired = spect.Plan(mud, psfd, dy, cache_mubar=True)
+    paired = Plan(mud, psfd, dy, cache_mubar=True)
     assert paired.describe()["mirror"] == "1"
     vp, bp = host(paired.forward(xd)), host(paired.back(yd))
     lhs = spect.dot_f64(paired.forward(xd), yd)
     rhs = spect.dot_f64(xd, paired.back(yd))
-    monkeypatch.setenv("SPECT_PSF_MIRROR", "0")
-    full = spect.Plan(mud, psfd, dy, cache_mubar=True)
+    full = Plan(mud, psfd, dy, cache_mubar=True, mirror="off")
     assert full.describe()["mirror"] == "0"
     ev = rel_l2(vp, host(full.forward(xd)))
     eb = rel_l2(bp, host(full.back(yd)))
@@ -161,24 +175,23 @@ def test_mirror_matches_all_taps_paper_size(monkeypatch):
     assert ev <= 2e-6 and eb <= 2e-6 and gap <= TOL
 
 
-def test_describe_reports_each_path(monkeypatch):
+def test_describe_reports_each_path():
     """spect_plan_describe names the kernels each plan option selects; pairing
     applies to the FP32 4x4-block convolution only."""
     x, mu, psf, dy = synth.config_inputs("tiny", seed=4)
     mud, psfd = to_dev(mu), to_dev(psf)
-    d = spect.Plan(mud, psfd, dy).describe()
+    d = Plan(mud, psfd, dy).describe()
     assert d["conv"] == "fp32-4x4" and d["mirror"] == "1" and d["rotation"] == "3pass", d
     assert int(d["view_batch"]) == 16 and int(d["nchunk"]) >= 1 and int(d["rot_views"]) >= 1, d
     for prec in ("bf16", "fp16", "bf16x3"):
-        d = spect.Plan(mud, psfd, dy, precision=prec).describe()
+        d = Plan(mud, psfd, dy, precision=prec).describe()
         assert d["conv"] == prec and d["mirror"] == "0", d
-    d = spect.Plan(mud, psfd, dy, rotation="bilinear").describe()
+    d = Plan(mud, psfd, dy, rotation="bilinear").describe()
     assert d["rotation"] == "bilinear" and d["mirror"] == "1", d
     fz, fx = synth.gaussian_psf_factors(7, 7, 32, 16, 0.5, 2.0)
-    d = spect.Plan(mud, (to_dev(fz), to_dev(fx)), dy).describe()
+    d = Plan(mud, (to_dev(fz), to_dev(fx)), dy).describe()
     assert d["conv"] == "separable" and d["mirror"] == "0", d
-    d = spect.Plan(mud, psfd, dy, view_batch=5).describe()
+    d = Plan(mud, psfd, dy, view_batch=5).describe()
     assert int(d["view_batch"]) == 5, d
-    monkeypatch.setenv("SPECT_FP32_TILING", "16x16")
-    d = spect.Plan(mud, psfd, dy).describe()
+    d = Plan(mud, psfd, dy, tiling="16x16").describe()
     assert d["conv"] == "fp32-16x16" and d["mirror"] == "0", d
