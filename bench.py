@@ -28,7 +28,10 @@ sys.path.insert(0, ROOT)
 FP32_PEAK_TFLOPS = 157.3          # MI355X published FP32 matrix (MFMA) peak, dense
 LP_PEAK_TFLOPS = 2500.0           # MI355X published dense BF16 / FP16 matrix peak
 HBM_PEAK_GBS = 8000.0
-FP32_VALU_TFLOPS = 157.3          # MI355X published FP32 vector peak (with packed FP32, unused here)
+# MI355X FP32 vector peak without packed FP32 instructions (which this build
+# disables): 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP (FMA) x 2.4 GHz = 78.6 TFLOP/s
+# (the published 157.3 TFLOP/s counts packed FP32, two FMAs per lane and cycle)
+FP32_VALU_TFLOPS = 78.6
 
 
 def parse():
@@ -58,8 +61,12 @@ def parse():
                     help="requests in the continuous-batching serving trace (0 disables)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="mean arrivals per second")
     ap.add_argument("--serve-slots", type=int, default=4, help="concurrent requests at most")
-    ap.add_argument("--serve-precision", default="bf16", choices=["fp32", "bf16", "fp16"],
-                    help="convolution precision of the served reconstructions")
+    ap.add_argument("--serve-precisions", default="fp32,bf16",
+                    help="comma-separated convolution precisions of the served reconstructions "
+                         "(one serving run per precision, on the same trace)")
+    ap.add_argument("--uncached-steps", type=int, default=10,
+                    help="timed pairs with the attenuation factor recomputed per call "
+                         "(no SPECT_CACHE_MUBAR), the paper's memory-saving order (0: skip)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB device-to-device: a plain "
@@ -81,10 +88,12 @@ def source_sha(path):
     return hashlib.sha256(open(path, "rb").read()).hexdigest()
 
 
-def traffic_for(kernel, launches_flops):
+def traffic_for(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE / WRITE_SIZE scaled by a copy-kernel calibration),
-    or None if absent or taken on a different kernel source."""
+    or None if absent or taken on different kernel sources (every file the
+    record names -- the kernel's source and the headers it includes -- must
+    still hash to the recorded SHA-256)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -92,9 +101,9 @@ def traffic_for(kernel, launches_flops):
         rec = json.load(open(path)).get(kernel)
         if not rec:
             return None
-        src = os.path.join(ROOT, rec["source"])
-        if source_sha(src) != rec["source_sha256"]:
-            return None
+        for src, sha in rec["sources"].items():
+            if source_sha(os.path.join(ROOT, src)) != sha:
+                return None
         return rec["hbm_bytes_per_launch"]
     except Exception:
         return None
@@ -102,28 +111,28 @@ def traffic_for(kernel, launches_flops):
 
 def cpu_baseline(x, mu, psf, dy, nviews_sample, seed):
     """The FP64 oracle as it stands (FFT convolution path), forward + back of
-    `nviews_sample` views, scaled to whole pairs."""
+    `nviews_sample` views over a process pool of views on the host cores this
+    process may use (its CPU affinity, at most 16: the host share of one GPU
+    on the benchmark machines), scaled to whole pairs."""
     import numpy as np
-    import oracle
-    from oracle import convolution
+    from oracle.pool import OraclePool, host_cores
     from oracle.projector import Geometry
 
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except Exception:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
-    convolution.FFT_WORKERS = cores
+    cores = host_cores(cap=16)
     nz, ny, nx = x.shape
     nview, _, pz, px = psf.shape
-    g = Geometry(nx, ny, nz, nview, px, pz, dy)
     step = max(1, nview // nviews_sample)
     views = list(range(0, nview, step))[:nviews_sample]
-    y = np.random.default_rng(seed + 7).uniform(0.5, 1.5, size=(nview, nz, nx))
-    t0 = time.perf_counter()
-    oracle.forward(x, mu, psf, g, views=views, conv="fft")
-    oracle.back(y, mu, psf, g, views=views, conv="fft")
-    dt = time.perf_counter() - t0
+    g = Geometry(nx, ny, nz, len(views), px, pz, dy,
+                 angles=[2 * np.pi * l / nview for l in views])
+    y = np.random.default_rng(seed + 7).uniform(0.5, 1.5, size=(len(views), nz, nx))
+    with OraclePool(mu, psf[views], g, workers=cores, conv="fft") as pool:
+        pool.forward(np.zeros_like(x))          # workers started and warm
+        t0 = time.perf_counter()
+        pool.forward(x)
+        pool.back(y)
+        dt = time.perf_counter() - t0
+        workers = pool.workers
     sec_per_pair = dt * nview / len(views)
     model = None
     try:
@@ -133,11 +142,13 @@ def cpu_baseline(x, mu, psf, dy, nviews_sample, seed):
                 break
     except OSError:
         pass
-    return {"value": 1.0 / sec_per_pair, "unit": "pairs/s", "cores": cores, "kind": "oracle",
+    return {"value": 1.0 / sec_per_pair, "unit": "pairs/s", "cores": workers, "kind": "oracle",
             "sample": f"FP64 oracle (numpy + scipy.fft, FFT convolution) forward+back of "
                       f"{len(views)} of {nview} views at {nx}x{ny}x{nz}, {px}x{pz} PSF, "
-                      f"{dt:.1f} s" + (", scaled to a full pair" if len(views) < nview else ""),
-            "seconds_per_pair": sec_per_pair, "cpu_model": model}
+                      f"{workers} worker processes over views, {dt:.1f} s"
+                      + (", scaled to a full pair" if len(views) < nview else ""),
+            "seconds_per_pair": sec_per_pair, "cpu_model": model,
+            "os_cpu_count": os.cpu_count(), "affinity_cores": host_cores(cap=1 << 20)}
 
 
 def main():
@@ -210,7 +221,7 @@ def main():
         achieved = conv_flops / (avg_ms[dom] * 1e-3) / 1e12
         roof = {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
-                "traffic": traffic_for(dom, conv_flops),
+                "traffic": traffic_for(dom),
                 "algorithmic_per_launch": conv_flops, "avg_launch_ms": avg_ms[dom],
                 "form": "mirror-paired taps" if mirror else "all taps",
                 "operator_flop_per_launch": op_flops}
@@ -218,7 +229,7 @@ def main():
         byts = 3.0 * 4 * N * views_per_launch
         achieved = byts / (avg_ms[dom] * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(dom, byts),
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(dom),
                 "algorithmic_per_launch": byts, "avg_launch_ms": avg_ms[dom]}
 
     # EM reconstruction latency (not part of `value`)
@@ -269,15 +280,11 @@ def main():
         os_.close()
         del os_
 
-    # The same pair with every PSF tap taken separately (SPECT_PSF_MIRROR=0):
+    # The same pair with every PSF tap taken separately (SPECT_PSF_ALL_TAPS):
     # the path for PSFs that are not symmetric in x (not part of `value`).
     all_taps = None
     if args.all_taps_steps > 0 and mirror:
-        os.environ["SPECT_PSF_MIRROR"] = "0"
-        try:
-            pl = spect.Plan(mud, psfd, dy, cache_mubar=bool(args.cache_mubar))
-        finally:
-            del os.environ["SPECT_PSF_MIRROR"]
+        pl = spect.Plan(mud, psfd, dy, cache_mubar=bool(args.cache_mubar), mirror="off")
         v2 = torch.empty_like(vd)
         b2 = torch.empty_like(bd)
         for _ in range(args.warmup):
@@ -304,6 +311,36 @@ def main():
                     "kernels_ms_per_launch": kav,
                     "conv_fwd_tflops": op_flops / (kav["conv_fwd"] * 1e-3) / 1e12,
                     "conv_back_tflops": op_flops / (kav["conv_back"] * 1e-3) / 1e12}
+        pl.close()
+        del pl, v2, b2
+
+    # The same pair without the attenuation cache (not part of `value`): the
+    # Eq. (1) factor is recomputed from mu for every view in every call, as in
+    # the paper's memory-saving design, and the workspace shrinks by the cache.
+    uncached = None
+    if args.uncached_steps > 0:
+        pl = spect.Plan(mud, psfd, dy, cache_mubar=False)
+        v2 = torch.empty_like(vd)
+        b2 = torch.empty_like(bd)
+        for _ in range(args.warmup):
+            pl.forward(xd, out=v2)
+            pl.back(v2, out=b2)
+        torch.cuda.synchronize()
+        pl.profile_start(max_launches=64 * args.uncached_steps + 64)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.uncached_steps):
+            pl.forward(xd, out=v2)
+            pl.back(v2, out=b2)
+        b.record()
+        torch.cuda.synchronize()
+        kt = pl.profile_stop()
+        ms = a.elapsed_time(b) / args.uncached_steps
+        pl.forward(xd, out=v2)
+        torch.cuda.synchronize()
+        uncached = {"pairs_per_s": 1000.0 / ms, "ms_per_pair": ms, "workspace_bytes": pl.ws_bytes,
+                    "forward_bitwise_equal_to_cached": bool(torch.equal(v2, vd)),
+                    "kernels_ms_per_launch": {k: v["total_ms"] / v["launches"] for k, v in kt.items()}}
         pl.close()
         del pl, v2, b2
 
@@ -338,16 +375,24 @@ def main():
             pl.forward(xd, out=v2)
             torch.cuda.synchronize()
             kav = {k: v["total_ms"] / v["launches"] for k, v in kt.items()}
-            fwd_ms = kav.get("conv_fwd_lp")
+            # the LP kernels take every tap (no mirror pairing); split BF16
+            # issues three BF16 products per FP32 product
+            lp_flops = op_flops * (3 if prec == "bf16x3" else 1)
+
+            def lp_roof(ms_, flops_=lp_flops):
+                if not ms_:
+                    return None
+                a_ = flops_ / (ms_ * 1e-3) / 1e12
+                return {"bound": "mfma", "achieved": a_, "peak": LP_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": a_ / LP_PEAK_TFLOPS, "algorithmic_per_launch": flops_,
+                        "avg_launch_ms": ms_}
             lp[prec] = {
                 "pairs_per_s": 1000.0 / ms, "ms_per_pair": ms,
                 "rel_l2_forward_vs_fp32": float((v2.double() - ref_v).norm() / ref_v.norm()),
                 "rel_l2_back_vs_fp32": float((b2.double() - ref_b).norm() / ref_b.norm()),
                 "kernels_ms_per_launch": kav,
-                "conv_fwd_roofline": None if not fwd_ms else {
-                    "bound": "mfma", "achieved": conv_flops / (fwd_ms * 1e-3) / 1e12,
-                    "peak": LP_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": conv_flops / (fwd_ms * 1e-3) / 1e12 / LP_PEAK_TFLOPS},
+                "conv_fwd_roofline": lp_roof(kav.get("conv_fwd_lp")),
+                "conv_back_roofline": lp_roof(kav.get("conv_back_lp")),
             }
             pl.close()
             del pl, v2, b2
@@ -417,7 +462,7 @@ def main():
                "rel_l2_forward_vs_2d": float((v2.double() - vd.double()).norm() / vd.double().norm()),
                "rel_l2_back_vs_2d": float((b2.double() - bd.double()).norm() / bd.double().norm()),
                "kernels_ms_per_launch": kav,
-               "conv_fwd_roofline": {"bound": "valu", "achieved": sep_flops / (kav["conv_fwd"] * 1e-3) / 1e12,
+               "conv_fwd_roofline": {"bound": "alu", "achieved": sep_flops / (kav["conv_fwd"] * 1e-3) / 1e12,
                                      "peak": FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                                      "frac": sep_flops / (kav["conv_fwd"] * 1e-3) / 1e12 / FP32_VALU_TFLOPS}}
         pl.close()
@@ -503,29 +548,38 @@ def main():
     # Continuous-batching EM service (not part of `value`): Poisson arrivals of
     # reconstructions of three sizes, 8 EM iterations each.
     serving = None
-    if args.serve_requests > 0:
+    precs = [p_ for p_ in args.serve_precisions.split(",") if p_]
+    if args.serve_requests > 0 and precs:
         from paper_2301_09710_amd import serve as sv
-        trace = sv.poisson_trace(args.serve_requests, args.serve_rate, seed=args.seed + 1,
-                                 precision=args.serve_precision)
+        trace0 = sv.poisson_trace(args.serve_requests, args.serve_rate, seed=args.seed + 1)
         t_gen = time.perf_counter()
-        data = {r.rid: sv.RequestData(r, dev) for r in trace}
+        data = {r.rid: sv.RequestData(r, dev) for r in trace0}
         t_gen = time.perf_counter() - t_gen
-        budget = int(0.5 * torch.cuda.get_device_properties(dev).total_memory)
-        sched = sv.Scheduler(budget, args.serve_slots,
-                             lambda r: sv.request_bytes(r.size, r.precision))
-        ex = sv.GpuExecutor(dev, data, max_slots=args.serve_slots, keep_results=False)
-        torch.cuda.synchronize()
-        t_s = time.perf_counter()
-        done = sv.serve(trace, sched, ex)
-        torch.cuda.synchronize()
-        wall_s = time.perf_counter() - t_s
-        serving = sv.summarize(done, wall_s)
-        serving.update({"rate_req_s": args.serve_rate, "slots": args.serve_slots,
-                        "precision": args.serve_precision, "iters": trace[0].iters,
+        serving = {}
+        for prec in precs:
+            trace = sv.poisson_trace(args.serve_requests, args.serve_rate, seed=args.seed + 1,
+                                     precision=prec)
+            budget = int(0.5 * torch.cuda.get_device_properties(dev).total_memory)
+            sched = sv.Scheduler(budget, args.serve_slots,
+                                 lambda r: sv.request_bytes(r.size, r.precision))
+            ex = sv.GpuExecutor(dev, data, max_slots=args.serve_slots, keep_results=False)
+            torch.cuda.synchronize()
+            base = torch.cuda.memory_allocated(dev)
+            torch.cuda.reset_peak_memory_stats(dev)
+            t_s = time.perf_counter()
+            done = sv.serve(trace, sched, ex)
+            torch.cuda.synchronize()
+            wall_s = time.perf_counter() - t_s
+            rec = sv.summarize(done, wall_s)
+            rec.update({"rate_req_s": args.serve_rate, "slots": args.serve_slots,
+                        "precision": prec, "iters": trace[0].iters,
                         "budget_gb": budget / 1e9, "peak_admitted_gb": sched.peak / 1e9,
+                        "peak_measured_gb": (torch.cuda.max_memory_allocated(dev) - base) / 1e9,
                         "wall_s": wall_s, "trace_s": trace[-1].arrival,
                         "data_generation_s (untimed)": t_gen})
-        del data, ex, sched
+            serving[prec] = rec
+            del ex, sched
+        del data
 
     if args.copy_mb > 0:
         nbytes = args.copy_mb << 20
@@ -556,7 +610,10 @@ def main():
         "config": {"workload": "paper-scale FP32 projector pair: 128x128x80 volume (4.8 mm), "
                                "128 views over 360 deg, 37x37 depth/view-dependent Gaussian PSF",
                    "nx": nx, "ny": ny, "nz": nz, "nview": nview, "px": px, "pz": pz,
-                   "cache_mubar": bool(args.cache_mubar), "plan": sel},
+                   "cache_mubar": bool(args.cache_mubar), "plan": sel,
+                   "workspace_bytes": plan.ws_bytes,
+                   "mubar_cache_bytes": (nview * nx * ny * nz * 4) if args.cache_mubar else 0},
+        "uncached_mubar": uncached,
         "pair_latency_ms": {"p50": pct(step_ms, 50), "p99": pct(step_ms, 99),
                             "p10": pct(step_ms, 10), "p90": pct(step_ms, 90)},
         "wall_s_timed": wall,

@@ -76,16 +76,26 @@ def geometry_of(size: str):
     return c["nx"], c["ny"], c["nz"], c["nview"], c["px"], c["pz"], c["dy"]
 
 
+# The caching allocator rounds every device buffer above 1 MiB up to a
+# multiple of 2 MiB; a request holds eight buffers.
+ALLOC_ROUND = 2 << 20
+REQUEST_BUFFERS = 8
+
+
 def request_bytes(size: str, precision: str = "fp32", cache_mubar: bool = True) -> int:
     """Device memory one admitted request holds: the plan workspace and the
-    request's buffers (mu, PSFs, sinogram, background, image, sensitivity)."""
+    request's buffers (mu, PSFs, sinogram, background, image, sensitivity and
+    the projection of ones the sensitivity is made from), each rounded up as
+    the caching allocator rounds it."""
     nx, ny, nz, nview, px, pz, dy = geometry_of(size)
     g, _ = spect.make_geom(nx, ny, nz, nview, px, pz, dy,
                            flags=spect.SPECT_CACHE_MUBAR if cache_mubar else 0,
                            conv_precision=spect.PRECISIONS[precision])
-    ws = spect.spect_workspace_bytes(g)
     N, M = nx * ny * nz, nview * nz * nx
-    return ws + 4 * (3 * N + 2 * M + nview * ny * pz * px)
+    bufs = [spect.spect_workspace_bytes(g), 4 * N, 4 * N, 4 * N, 4 * M, 4 * M, 4 * M,
+            4 * nview * ny * pz * px]
+    assert len(bufs) == REQUEST_BUFFERS
+    return sum(-(-b // ALLOC_ROUND) * ALLOC_ROUND for b in bufs)
 
 
 # ---------------------------------------------------------------- scheduler
@@ -168,7 +178,11 @@ class RequestData:
     map, PSFs, Poisson sinogram y ~ Poisson(A x_true + r) with a uniform
     background r of 5% of the mean projection.  A x_true is computed with the
     GPU projector once, before the trace starts (the request arrives with its
-    measured data)."""
+    measured data).  The inputs are kept in pinned host memory, so that
+    admitting the request copies them to the device asynchronously on its
+    own stream; ``symmetric_x`` records whether every PSF row equals its
+    mirror image in x (checked here, on the host), which lets the plan pair
+    taps without a device check."""
 
     _psf_cache: Dict[str, np.ndarray] = {}
 
@@ -191,6 +205,9 @@ class RequestData:
         self.y = y.cpu().numpy()
         self.r = r.cpu().numpy()
         plan.close()
+        self.symmetric_x = bool(np.array_equal(psf, psf[..., ::-1]))
+        self.pinned = {k: torch.from_numpy(getattr(self, k)).pin_memory()
+                       for k in ("mu", "psf", "y", "r")}
 
 
 class GpuExecutor:
@@ -214,15 +231,19 @@ class GpuExecutor:
         self.slots: Dict[int, _Slot] = {}
 
     def start(self, req: Request, now: float) -> None:
+        """Admit a request without waiting on the device: its inputs are copied
+        from pinned host memory on its own stream, the plan is created on that
+        stream (with the PSF symmetry known from the host, so the plan does
+        not wait for a device check), and the sensitivity back projection is
+        enqueued behind them."""
         torch = self.torch
         d = self.data[req.rid]
         stream = self.free_streams.pop()
         with torch.cuda.stream(stream):
-            mu = torch.from_numpy(d.mu).to(self.device)
-            psf = torch.from_numpy(d.psf).to(self.device)
-            y = torch.from_numpy(d.y).to(self.device)
-            r = torch.from_numpy(d.r).to(self.device)
-            plan = spect.Plan(mu, psf, d.dy, cache_mubar=self.cache_mubar, precision=req.precision)
+            mu, psf, y, r = (d.pinned[k].to(self.device, non_blocking=True)
+                             for k in ("mu", "psf", "y", "r"))
+            plan = spect.Plan(mu, psf, d.dy, cache_mubar=self.cache_mubar, precision=req.precision,
+                              mirror="assume" if d.symmetric_x else "off")
             sens = plan.back(torch.ones(plan.proj_shape, dtype=torch.float32, device=self.device))
             x = torch.ones(plan.vol_shape, dtype=torch.float32, device=self.device)
         self.slots[req.rid] = _Slot(req, plan, stream, x, y, r, sens, now)

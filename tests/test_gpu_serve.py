@@ -62,6 +62,7 @@ def test_served_result_equals_plain_em_loop(mix):
     d = data[r.rid]
     plan = spect.Plan(torch.from_numpy(d.mu).to(DEV), torch.from_numpy(d.psf).to(DEV), d.dy,
                       cache_mubar=True)
+    assert d.symmetric_x                       # the served plan pairs taps on the host's word
     sens = plan.back(torch.ones(plan.proj_shape, device=DEV))
     x = torch.ones(plan.vol_shape, device=DEV)
     y, rr = torch.from_numpy(d.y).to(DEV), torch.from_numpy(d.r).to(DEV)
@@ -73,10 +74,35 @@ def test_served_result_equals_plain_em_loop(mix):
 
 
 def test_memory_budget_respected_under_pressure(mix):
+    """The budget holds for the device memory the requests actually hold, as
+    torch's allocator counts it (live buffers, already rounded to its 2 MiB
+    granules), not only for the scheduler's own bookkeeping."""
     trace, data = mix
     need = {r.rid: sv.request_bytes(r.size, r.precision) for r in trace}
     budget = int(max(need.values()) * 1.2)          # the largest fits, never two large ones
     say(f"serve: budget {budget / 2 ** 30:.2f} GiB")
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated(DEV)
+    torch.cuda.reset_peak_memory_stats(DEV)
     done, sched = _run(trace, data, 4, budget)
+    measured = torch.cuda.max_memory_allocated(DEV) - base
+    say(f"serve: admitted peak {sched.peak / 2 ** 30:.3f} GiB, measured peak "
+        f"{measured / 2 ** 30:.3f} GiB")
     assert sorted(done) == [r.rid for r in trace]
     assert sched.peak <= budget
+    assert measured <= budget
+
+
+def test_request_bytes_counts_what_a_request_allocates(mix):
+    """request_bytes is an upper bound on the device memory one admitted
+    request allocates (measured around a served request alone)."""
+    trace, data = mix
+    for r in (trace[0], trace[3], trace[4]):
+        torch.cuda.synchronize()
+        base = torch.cuda.memory_allocated(DEV)
+        torch.cuda.reset_peak_memory_stats(DEV)
+        _run([sv.Request(r.rid, r.size, r.seed, 0.0, r.iters, r.precision)], data, 1, 64 << 30)
+        measured = torch.cuda.max_memory_allocated(DEV) - base
+        say(f"serve: {r.size}/{r.precision}: measured {measured / 2 ** 20:.1f} MiB, "
+            f"request_bytes {sv.request_bytes(r.size, r.precision) / 2 ** 20:.1f} MiB")
+        assert measured <= sv.request_bytes(r.size, r.precision)
