@@ -183,6 +183,57 @@ hipError_t timed(const Plan& p, KernelId id, hipStream_t s, F&& launch) {
 }
 
 spect_status compute_layout(const spect_geom& g, Layout* lay, int* view_batch, int* nchunk);
+// Kernel selection and tiling of a plan over the workspace ws (no device work
+// beyond occupancy queries; the tables, the attenuation cache and the mirror
+// check are the caller's).
+void configure_plan(Plan& p, const spect_geom& g, const Layout& lay, int view_batch, int nchunk,
+                    const float* d_mu, const float* d_psf, char* ws);
+// The forward projection of Alg. 1 on a configured plan with its tables in place.
+spect_status forward_impl(const Plan& p, const float* x, float* v, hipStream_t s);
+
+// ---- per-view rotation tables (host and device) ----
+// Default angles theta_l = 2 pi l / nview split exactly as theta = M pi/2 + phi,
+// phi in [-pi/4, pi/4): M = floor((8 l + nview) / (2 nview)), m = M mod 4.
+__host__ __device__ inline void split_default_view(int l, int nview, int* m, double* phi) {
+  const long long M = (8LL * l + nview) / (2LL * nview);
+  *phi = (3.14159265358979323846 / 2.0) * (double)(4LL * l - M * nview) / (double)nview;
+  *m = (int)(((M % 4) + 4) % 4);
+}
+
+// Integer part and fraction of v, the fraction in [0, 1) after rounding to float.
+__host__ __device__ inline void split_pos(double v, int32_t* ip, float* frac) {
+  double fl = ::floor(v);
+  float f = (float)(v - fl);
+  if (f >= 1.0f) { f = 0.0f; fl += 1.0; }
+  *ip = (int32_t)fl;
+  *frac = f;
+}
+
+// Entry (ps, r) of one view's tables for the residual angle phi (see Tables):
+// off2[0..1] and w of row/column r of pass group ps.
+__host__ __device__ inline void table_entry(int n, bool bilinear, double phi, int ps, int r,
+                                            int32_t* off2, float2* w) {
+  const double c = (n - 1) / 2.0;
+  const double u = (double)r - c;
+  if (bilinear) {
+    const double s = ::sin(phi), co = ::cos(phi);
+    // ps 0: row term (index j = r), ps 1: column term (index i = r)
+    const double ti = ps == 0 ? s * u : c + co * u;
+    const double tj = ps == 0 ? c + co * u : -s * u;
+    float fi, fj;
+    split_pos(ti, &off2[0], &fi);
+    split_pos(tj, &off2[1], &fj);
+    *w = make_float2(fi, fj);
+  } else {
+    // passes 1, 3: shift along i for row j = r; pass 2: shift along j for column i = r
+    const double d = ps == 0 ? ::tan(phi / 2.0) * u : -::sin(phi) * u;
+    const double fl = ::floor(d);
+    const double f = d - fl;
+    off2[0] = (int32_t)fl;
+    off2[1] = 0;
+    *w = make_float2((float)(1.0 - f), (float)f);
+  }
+}
 
 bool conv_mfma_supported(const spect_geom& g);
 ConvShape make_conv_shape(const spect_geom& g, int jc_fwd, int jc_back);

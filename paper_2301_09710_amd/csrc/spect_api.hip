@@ -82,30 +82,18 @@ spect_status compute_layout(const spect_geom& g, Layout* lay, int* view_batch, i
 
 // theta = M pi/2 + phi, phi in [-pi/4, pi/4); integer rule for default angles.
 static void split_view(const spect_geom& g, int l, int* m, double* phi) {
-  long long M;
   if (!g.angles) {
-    M = (8LL * l + g.nview) / (2LL * g.nview);
-    *phi = (M_PI / 2.0) * (double)(4LL * l - M * g.nview) / (double)g.nview;
-  } else {
-    const double th = g.angles[l];
-    M = (long long)std::floor(th / (M_PI / 2.0) + 0.5);
-    *phi = th - (double)M * (M_PI / 2.0);
+    split_default_view(l, g.nview, m, phi);
+    return;
   }
+  const double th = g.angles[l];
+  const long long M = (long long)std::floor(th / (M_PI / 2.0) + 0.5);
+  *phi = th - (double)M * (M_PI / 2.0);
   *m = (int)(((M % 4) + 4) % 4);
-}
-
-// Integer part and fraction of v, the fraction in [0, 1) after rounding to float.
-static void split_pos(double v, int32_t* ip, float* frac) {
-  double fl = std::floor(v);
-  float f = (float)(v - fl);
-  if (f >= 1.0f) { f = 0.0f; fl += 1.0; }
-  *ip = (int32_t)fl;
-  *frac = f;
 }
 
 static void fill_tables(const spect_geom& g, int32_t* q, int32_t* off, float2* w, float2* rot) {
   const int n = g.nx;
-  const double c = (n - 1) / 2.0;
   const bool bil = (g.flags & SPECT_ROT_BILINEAR) != 0;
   for (int l = 0; l < g.nview; ++l) {
     int m;
@@ -113,30 +101,11 @@ static void fill_tables(const spect_geom& g, int32_t* q, int32_t* off, float2* w
     split_view(g, l, &m, &phi);
     q[l] = m;
     rot[l] = make_float2((float)std::cos(phi), (float)std::sin(phi));
-    const double t = std::tan(phi / 2.0), s = std::sin(phi), co = std::cos(phi);
-    for (int r = 0; r < n; ++r) {
-      const double u = (double)r - c;
+    for (int r = 0; r < n; ++r)
       for (int ps = 0; ps < 2; ++ps) {
         const size_t e = ((size_t)l * 2 + ps) * n + r;
-        if (bil) {
-          // ps 0: row term (index j = r), ps 1: column term (index i = r)
-          const double ti = ps == 0 ? s * u : c + co * u;
-          const double tj = ps == 0 ? c + co * u : -s * u;
-          float fi, fj;
-          split_pos(ti, &off[2 * e], &fi);
-          split_pos(tj, &off[2 * e + 1], &fj);
-          w[e] = make_float2(fi, fj);
-        } else {
-          // passes 1, 3: shift along i for row j = r; pass 2: shift along j for column i = r
-          const double d = ps == 0 ? t * u : -s * u;
-          const double fl = std::floor(d);
-          const double f = d - fl;
-          off[2 * e] = (int32_t)fl;
-          off[2 * e + 1] = 0;
-          w[e] = make_float2((float)(1.0 - f), (float)f);
-        }
+        table_entry(n, bil, phi, ps, r, &off[2 * e], &w[e]);
       }
-    }
   }
 }
 
@@ -160,7 +129,139 @@ static void profiler_free(Profiler* pr) {
 }
 }  // namespace spect
 
+namespace spect {
+
+void configure_plan(Plan& p_, const spect_geom& g_, const Layout& lay, int vb, int nc,
+                    const float* d_mu, const float* d_psf, char* ws) {
+  Plan* p = &p_;
+  const spect_geom* g = &g_;
+  p->g = *g;
+  p->g.angles = nullptr;
+  p->view_batch = vb;
+  p->nchunk = nc;
+  p->mu = d_mu;
+  p->psf = d_psf;
+  p->ws = ws;
+  p->lay = lay;
+  p->prof = nullptr;
+  p->bilinear = (g->flags & SPECT_ROT_BILINEAR) != 0;
+  p->tab.quarter = reinterpret_cast<const int32_t*>(p->ws + lay.tables_quarter);
+  p->tab.off = reinterpret_cast<const int32_t*>(p->ws + lay.tables_off);
+  p->tab.w = reinterpret_cast<const float2*>(p->ws + lay.tables_w);
+  p->tab.rot = reinterpret_cast<const float2*>(p->ws + lay.tables_rot);
+  p->mubar = nullptr;
+  p->mubar_batch = nullptr;
+  p->rot_scratch = g->nx > kMaxLdsN ? reinterpret_cast<float*>(p->ws + lay.rot_scratch) : nullptr;
+  p->rot_fwd_vg = tune_rot_fwd_views(*g, vb);
+  p->use_mfma = conv_mfma_supported(*g);
+  p->conv = make_conv_shape(*g, kFwdJChunk, kBackJChunk);
+  p->m4 = make_m4_shape(*g);
+  p->use_m4 = false;
+  p->separable = (g->flags & SPECT_PSF_SEPARABLE) != 0;
+  if (p->separable) {
+    p->use_mfma = false;
+    p->sep = make_sep_shape(*g);
+    tune_sep_chunks(p->sep, g->nview);
+    p->nchunk = p->sep.nchunk;
+  } else if (p->use_mfma) {
+    tune_conv_chunks(p->conv, g->nview);   // independent of view_batch: same sums
+    p->nchunk = p->conv.nchunk;          // forward partial sums per view
+    // SPECT_TILING_4X4 / SPECT_TILING_16X16 override the cost model
+    bool m4 = m4_preferred(p->m4, p->conv);
+    if (g->flags & SPECT_TILING_4X4) m4 = p->m4.ok;
+    if (g->flags & SPECT_TILING_16X16) m4 = false;
+    if (m4) {
+      tune_m4_chunks(p->m4, g->nview);
+      p->use_m4 = true;
+      p->nchunk = p->m4.nchunk;
+    }
+  }
+  p->conv_precision = g->conv_precision;
+  if (p->conv_precision != SPECT_CONV_FP32) {
+    p->lp = make_lp_shape(*g);
+    tune_lp_chunks(p->lp, g->nview, p->conv_precision);
+    p->nchunk = p->lp.nchunk;
+  }
+  if (!(g->flags & SPECT_CACHE_MUBAR))
+    p->mubar_batch = reinterpret_cast<float*>(p->ws + lay.mubar_batch);
+}
+
+}  // namespace spect
+
 using namespace spect;
+
+// Attenuation factors of views [v0, v0 + nvb): the cache (computed at plan
+// creation) or the batch buffer, filled here.  Returns the base pointer and
+// the view offset to add to a batch-relative view index.
+static hipError_t mubar_for_batch(const Plan& p, int v0, int nvb, hipStream_t s,
+                                  const float** mb, int* off) {
+  if (p.mubar) {
+    *mb = p.mubar;
+    *off = v0;
+    return hipSuccess;
+  }
+  *mb = p.mubar_batch;
+  *off = 0;
+  return timed(p, K_MUBAR, s, [&] { return launch_mubar(p, p.mubar_batch, v0, nvb, v0, s); });
+}
+
+spect_status spect::forward_impl(const Plan& p, const float* x, float* v, hipStream_t s) {
+  float* W = reinterpret_cast<float*>(p.ws + p.lay.vol_batch);
+  float* part = reinterpret_cast<float*>(p.ws + p.lay.fwd_partial);
+  for (int v0 = 0; v0 < p.g.nview; v0 += p.view_batch) {
+    const int nvb = (p.g.nview - v0 < p.view_batch) ? p.g.nview - v0 : p.view_batch;
+    const float* mb;
+    int mb_off;
+    if (mubar_for_batch(p, v0, nvb, s, &mb, &mb_off) != hipSuccess) return SPECT_ERR_HIP;
+    if (timed(p, K_ROT_FWD, s, [&] { return launch_rot_fwd(p, x, mb, mb_off, W, v0, nvb, s); }) !=
+        hipSuccess)
+      return SPECT_ERR_HIP;
+    const hipError_t ec =
+        p.conv_precision != SPECT_CONV_FP32
+            ? timed(p, K_CONV_FWD_LP, s, [&] { return launch_conv_fwd_lp(p, W, part, v0, nvb, s); })
+            : timed(p, K_CONV_FWD, s, [&] {
+                if (p.separable) return launch_conv_sep(p, false, W, part, v0, nvb, s);
+                return p.use_mfma ? launch_conv_fwd_mfma(p, W, part, v0, nvb, s)
+                                  : launch_conv_fwd(p, W, part, v0, nvb, s);
+              });
+    if (ec != hipSuccess) return SPECT_ERR_HIP;
+    if (timed(p, K_FWD_REDUCE, s, [&] { return launch_fwd_reduce(p, part, v, v0, nvb, s); }) !=
+        hipSuccess)
+      return SPECT_ERR_HIP;
+  }
+  return SPECT_OK;
+}
+
+static spect_status back_impl(const Plan& p, const float* v, float* x, hipStream_t s) {
+  float* U = reinterpret_cast<float*>(p.ws + p.lay.vol_batch);
+  float* part = reinterpret_cast<float*>(p.ws + p.lay.back_partial);
+  for (int v0 = 0; v0 < p.g.nview; v0 += p.view_batch) {
+    const int nvb = (p.g.nview - v0 < p.view_batch) ? p.g.nview - v0 : p.view_batch;
+    const hipError_t ec =
+        p.conv_precision != SPECT_CONV_FP32
+            ? timed(p, K_CONV_BACK_LP, s, [&] { return launch_conv_back_lp(p, v, U, v0, nvb, s); })
+            : timed(p, K_CONV_BACK, s, [&] {
+                if (p.separable) return launch_conv_sep(p, true, v, U, v0, nvb, s);  // folds included
+                return p.use_mfma ? launch_conv_back_mfma(p, v, U, v0, nvb, s)
+                                  : launch_conv_back(p, v, U, v0, nvb, s);
+              });
+    if (ec != hipSuccess) return SPECT_ERR_HIP;
+    if (p.use_mfma &&
+        timed(p, K_CONV_BACK_EDGES, s,
+              [&] { return launch_conv_back_edges(p, v, U, v0, nvb, s); }) != hipSuccess)
+      return SPECT_ERR_HIP;
+    const float* mb;
+    int mb_off;
+    if (mubar_for_batch(p, v0, nvb, s, &mb, &mb_off) != hipSuccess) return SPECT_ERR_HIP;
+    if (timed(p, K_ROT_BACK, s, [&] {
+          return launch_rot_back(p, U, mb, mb_off, part, v0, nvb, v0 > 0, s);
+        }) != hipSuccess)
+      return SPECT_ERR_HIP;
+  }
+  if (timed(p, K_BACK_REDUCE, s, [&] { return launch_back_reduce(p, part, x, s); }) != hipSuccess)
+    return SPECT_ERR_HIP;
+  return SPECT_OK;
+}
 
 extern "C" {
 
@@ -223,14 +324,7 @@ spect_status spect_plan_create(spect_plan* out, const spect_geom* g, const float
 
   Plan* p = new (std::nothrow) Plan();
   if (!p) return SPECT_ERR_HIP;
-  p->g = *g;
-  p->g.angles = nullptr;
-  p->view_batch = vb;
-  p->nchunk = nc;
-  p->mu = d_mu;
-  p->psf = d_psf;
-  p->ws = static_cast<char*>(d_workspace);
-  p->lay = lay;
+  configure_plan(*p, *g, lay, vb, nc, d_mu, d_psf, static_cast<char*>(d_workspace));
   const size_t n = (size_t)g->nx;
   p->h_quarter = static_cast<int32_t*>(std::malloc(g->nview * sizeof(int32_t)));
   p->h_off = static_cast<int32_t*>(std::malloc(g->nview * 2 * n * 2 * sizeof(int32_t)));
@@ -240,12 +334,7 @@ spect_status spect_plan_create(spect_plan* out, const spect_geom* g, const float
     spect_plan_destroy(reinterpret_cast<spect_plan>(p));
     return SPECT_ERR_HIP;
   }
-  p->bilinear = (g->flags & SPECT_ROT_BILINEAR) != 0;
   fill_tables(*g, p->h_quarter, p->h_off, p->h_w, p->h_rot);
-  p->tab.quarter = reinterpret_cast<const int32_t*>(p->ws + lay.tables_quarter);
-  p->tab.off = reinterpret_cast<const int32_t*>(p->ws + lay.tables_off);
-  p->tab.w = reinterpret_cast<const float2*>(p->ws + lay.tables_w);
-  p->tab.rot = reinterpret_cast<const float2*>(p->ws + lay.tables_rot);
   hipError_t e = hipMemcpyAsync(p->ws + lay.tables_quarter, p->h_quarter,
                                 g->nview * sizeof(int32_t), hipMemcpyHostToDevice, stream);
   if (e == hipSuccess)
@@ -257,39 +346,6 @@ spect_status spect_plan_create(spect_plan* out, const spect_geom* g, const float
   if (e == hipSuccess)
     e = hipMemcpyAsync(p->ws + lay.tables_rot, p->h_rot, g->nview * sizeof(float2),
                        hipMemcpyHostToDevice, stream);
-  p->mubar = nullptr;
-  p->mubar_batch = nullptr;
-  p->rot_scratch = g->nx > kMaxLdsN ? reinterpret_cast<float*>(p->ws + lay.rot_scratch) : nullptr;
-  p->rot_fwd_vg = tune_rot_fwd_views(*g, vb);
-  p->use_mfma = conv_mfma_supported(*g);
-  p->conv = make_conv_shape(*g, kFwdJChunk, kBackJChunk);
-  p->m4 = make_m4_shape(*g);
-  p->use_m4 = false;
-  p->separable = (g->flags & SPECT_PSF_SEPARABLE) != 0;
-  if (p->separable) {
-    p->use_mfma = false;
-    p->sep = make_sep_shape(*g);
-    tune_sep_chunks(p->sep, g->nview);
-    p->nchunk = p->sep.nchunk;
-  } else if (p->use_mfma) {
-    tune_conv_chunks(p->conv, g->nview);   // independent of view_batch: same sums
-    p->nchunk = p->conv.nchunk;          // forward partial sums per view
-    // SPECT_TILING_4X4 / SPECT_TILING_16X16 override the cost model
-    bool m4 = m4_preferred(p->m4, p->conv);
-    if (g->flags & SPECT_TILING_4X4) m4 = p->m4.ok;
-    if (g->flags & SPECT_TILING_16X16) m4 = false;
-    if (m4) {
-      tune_m4_chunks(p->m4, g->nview);
-      p->use_m4 = true;
-      p->nchunk = p->m4.nchunk;
-    }
-  }
-  p->conv_precision = g->conv_precision;
-  if (p->conv_precision != SPECT_CONV_FP32) {
-    p->lp = make_lp_shape(*g);
-    tune_lp_chunks(p->lp, g->nview, p->conv_precision);
-    p->nchunk = p->lp.nchunk;
-  }
   // PSF rows symmetric in x (a centred Gaussian, any circularly symmetric
   // response): the 4x4-block kernels pair taps a and px-1-a.  Checked exactly
   // on the device unless the caller states the symmetry (SPECT_PSF_SYMMETRIC_X)
@@ -306,8 +362,6 @@ spect_status spect_plan_create(spect_plan* out, const spect_geom* g, const float
       e = timed(*p, K_MUBAR, stream,
                 [&] { return launch_mubar(*p, cache, 0, g->nview, 0, stream); });
     p->mubar = cache;
-  } else {
-    p->mubar_batch = reinterpret_cast<float*>(p->ws + lay.mubar_batch);
   }
   if (e != hipSuccess) {
     // make sure no queued copy still reads the host tables before freeing them
@@ -331,78 +385,6 @@ spect_status spect_plan_destroy(spect_plan plan) {
   return SPECT_OK;
 }
 
-// Attenuation factors of views [v0, v0 + nvb): the cache (computed at plan
-// creation) or the batch buffer, filled here.  Returns the base pointer and
-// the view offset to add to a batch-relative view index.
-static hipError_t mubar_for_batch(const Plan& p, int v0, int nvb, hipStream_t s,
-                                  const float** mb, int* off) {
-  if (p.mubar) {
-    *mb = p.mubar;
-    *off = v0;
-    return hipSuccess;
-  }
-  *mb = p.mubar_batch;
-  *off = 0;
-  return timed(p, K_MUBAR, s, [&] { return launch_mubar(p, p.mubar_batch, v0, nvb, v0, s); });
-}
-
-static spect_status forward_impl(const Plan& p, const float* x, float* v, hipStream_t s) {
-  float* W = reinterpret_cast<float*>(p.ws + p.lay.vol_batch);
-  float* part = reinterpret_cast<float*>(p.ws + p.lay.fwd_partial);
-  for (int v0 = 0; v0 < p.g.nview; v0 += p.view_batch) {
-    const int nvb = (p.g.nview - v0 < p.view_batch) ? p.g.nview - v0 : p.view_batch;
-    const float* mb;
-    int mb_off;
-    if (mubar_for_batch(p, v0, nvb, s, &mb, &mb_off) != hipSuccess) return SPECT_ERR_HIP;
-    if (timed(p, K_ROT_FWD, s, [&] { return launch_rot_fwd(p, x, mb, mb_off, W, v0, nvb, s); }) !=
-        hipSuccess)
-      return SPECT_ERR_HIP;
-    const hipError_t ec =
-        p.conv_precision != SPECT_CONV_FP32
-            ? timed(p, K_CONV_FWD_LP, s, [&] { return launch_conv_fwd_lp(p, W, part, v0, nvb, s); })
-            : timed(p, K_CONV_FWD, s, [&] {
-                if (p.separable) return launch_conv_sep(p, false, W, part, v0, nvb, s);
-                return p.use_mfma ? launch_conv_fwd_mfma(p, W, part, v0, nvb, s)
-                                  : launch_conv_fwd(p, W, part, v0, nvb, s);
-              });
-    if (ec != hipSuccess) return SPECT_ERR_HIP;
-    if (timed(p, K_FWD_REDUCE, s, [&] { return launch_fwd_reduce(p, part, v, v0, nvb, s); }) !=
-        hipSuccess)
-      return SPECT_ERR_HIP;
-  }
-  return SPECT_OK;
-}
-
-static spect_status back_impl(const Plan& p, const float* v, float* x, hipStream_t s) {
-  float* U = reinterpret_cast<float*>(p.ws + p.lay.vol_batch);
-  float* part = reinterpret_cast<float*>(p.ws + p.lay.back_partial);
-  for (int v0 = 0; v0 < p.g.nview; v0 += p.view_batch) {
-    const int nvb = (p.g.nview - v0 < p.view_batch) ? p.g.nview - v0 : p.view_batch;
-    const hipError_t ec =
-        p.conv_precision != SPECT_CONV_FP32
-            ? timed(p, K_CONV_BACK_LP, s, [&] { return launch_conv_back_lp(p, v, U, v0, nvb, s); })
-            : timed(p, K_CONV_BACK, s, [&] {
-                if (p.separable) return launch_conv_sep(p, true, v, U, v0, nvb, s);  // folds included
-                return p.use_mfma ? launch_conv_back_mfma(p, v, U, v0, nvb, s)
-                                  : launch_conv_back(p, v, U, v0, nvb, s);
-              });
-    if (ec != hipSuccess) return SPECT_ERR_HIP;
-    if (p.use_mfma &&
-        timed(p, K_CONV_BACK_EDGES, s,
-              [&] { return launch_conv_back_edges(p, v, U, v0, nvb, s); }) != hipSuccess)
-      return SPECT_ERR_HIP;
-    const float* mb;
-    int mb_off;
-    if (mubar_for_batch(p, v0, nvb, s, &mb, &mb_off) != hipSuccess) return SPECT_ERR_HIP;
-    if (timed(p, K_ROT_BACK, s, [&] {
-          return launch_rot_back(p, U, mb, mb_off, part, v0, nvb, v0 > 0, s);
-        }) != hipSuccess)
-      return SPECT_ERR_HIP;
-  }
-  if (timed(p, K_BACK_REDUCE, s, [&] { return launch_back_reduce(p, part, x, s); }) != hipSuccess)
-    return SPECT_ERR_HIP;
-  return SPECT_OK;
-}
 
 spect_status spect_forward(spect_plan plan, const float* d_x, float* d_v, hipStream_t stream) {
   if (!plan || !d_x || !d_v) return SPECT_ERR_NULL;
