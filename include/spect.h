@@ -200,6 +200,25 @@ spect_status spect_em_step_vjp(spect_plan plan, const float* d_x, const float* d
                                const float* d_r, const float* d_sens, const float* d_g,
                                float* d_gx, float* d_gy, hipStream_t stream);
 
+/* v = A x without a plan and without allocating anything, for callers that
+ * cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  The same operator and kernels as
+ * spect_forward on a plan of geometry g (Alg. 1).  What a plan's workspace
+ * would hold (rotation tables, computed on the device; the attenuation factors
+ * of a view batch; weighted volumes; partial sums) lives in a static device
+ * array of the library, 64 MiB per device, which spect_workspace_bytes(g)
+ * must not exceed (else SPECT_ERR_WORKSPACE, before any device work; choose
+ * g->view_batch to fit).  The array is shared by every call on a device and
+ * keeps the last call's contents: calls that overlap on one device race.
+ * Restrictions: g->angles must be NULL (default angles; else
+ * SPECT_ERR_UNSUPPORTED); SPECT_CACHE_MUBAR is ignored; mirror-image taps are
+ * paired only with SPECT_PSF_SYMMETRIC_X (no device check).  d_mu
+ * [nz][ny][nx], d_psf as for spect_plan_create, d_x [nz][ny][nx], d_v
+ * [nview][nz][nx] (overwritten); all 4-byte aligned.  The first call on a
+ * device looks up the array's address there (hipGetSymbolAddress). */
+spect_status spect_forward_static(const spect_geom* g, const float* d_mu, const float* d_psf,
+                                  const float* d_x, float* d_v, hipStream_t stream);
+
 /* Release the host plan object (does not free borrowed device memory). */
 spect_status spect_plan_destroy(spect_plan plan);
 

@@ -37,7 +37,8 @@ STATUS_NAMES = {
 }
 EXPORTED = ("spect_workspace_bytes", "spect_plan_create", "spect_forward", "spect_back",
             "spect_em_step", "spect_reg_em_step", "spect_em_step_vjp", "spect_plan_destroy", "spect_status_string", "spect_dot_f64",
-            "spect_profile_start", "spect_profile_stop", "spect_version", "spect_plan_describe")
+            "spect_profile_start", "spect_profile_stop", "spect_version", "spect_plan_describe",
+            "spect_forward_static")
 
 
 class SpectError(RuntimeError):
@@ -92,6 +93,9 @@ def _lib():
         lib.spect_version.restype = c_char_p
         lib.spect_plan_describe.argtypes = [c_void_p, ctypes.c_char_p, c_size_t]
         lib.spect_plan_describe.restype = c_int
+        lib.spect_forward_static.argtypes = [POINTER(spect_geom), c_void_p, c_void_p, c_void_p,
+                                             c_void_p, c_void_p]
+        lib.spect_forward_static.restype = c_int
         _LIB = lib
     return _LIB
 
@@ -162,6 +166,13 @@ def spect_em_step_vjp(plan: int, d_x: int, d_y: int, d_r, d_sens: int, d_g: int,
     st = _lib().spect_em_step_vjp(plan, d_x, d_y, d_r, d_sens, d_g, d_gx, d_gy, stream)
     if st != SPECT_OK:
         raise SpectError(st, "spect_em_step_vjp")
+
+
+def spect_forward_static(geom: spect_geom, d_mu: int, d_psf: int, d_x: int, d_v: int,
+                         stream: int) -> None:
+    st = _lib().spect_forward_static(ctypes.byref(geom), d_mu, d_psf, d_x, d_v, stream)
+    if st != SPECT_OK:
+        raise SpectError(st, "spect_forward_static")
 
 
 def spect_plan_destroy(plan: int) -> None:

@@ -168,3 +168,19 @@ def test_direct_convolution_shape_is_accepted_in_fp32_only():
         with pytest.raises(spect.SpectError) as e:
             spect.spect_workspace_bytes(g)
         assert e.value.status == 5
+
+
+def test_static_forward_rejects_before_any_gpu_call():
+    """spect_forward_static validates the geometry and checks that its
+    workspace fits the library's static array before touching a device."""
+    lib = spect.load()
+    fake = 1 << 40
+    g, _ = spect.make_geom(128, 128, 80, 128, 37, 37, 4.8)          # 1.4 GiB of workspace
+    assert lib.spect_forward_static(ctypes.byref(g), fake, fake, fake, fake, None) == 4
+    g, _keep = spect.make_geom(16, 16, 8, 3, 3, 3, 1.0, angles=[0.0, 1.0, 2.0])
+    assert lib.spect_forward_static(ctypes.byref(g), fake, fake, fake, fake, None) == 5
+    g, _ = spect.make_geom(16, 16, 8, 3, 4, 3, 1.0)                   # even PSF
+    assert lib.spect_forward_static(ctypes.byref(g), fake, fake, fake, fake, None) == 2
+    g, _ = spect.make_geom(16, 16, 8, 3, 3, 3, 1.0)
+    assert lib.spect_forward_static(ctypes.byref(g), None, fake, fake, fake, None) == 1
+    assert lib.spect_forward_static(ctypes.byref(g), fake, fake, fake + 2, fake, None) == 7
