@@ -108,6 +108,17 @@ typedef enum {
 #define SPECT_TILING_16X16 0x40u /* FP32 convolution as 16x16x4 Toeplitz blocks, instead of
                                     the plan's cost model.  Exclusive with SPECT_TILING_4X4
                                     (else SPECT_ERR_VALUE). */
+#define SPECT_CONV_FFT 0x80u    /* PSF convolution through FP32 FFTs, as Sec. II-A computes it:
+                                   the same operator (replicate padding, exact adjoint with
+                                   the padding's fold), evaluated as circular convolutions of
+                                   a size that holds the padded plane, with the depth sum
+                                   taken on the spectra.  Any PSF (no symmetry needed).  The
+                                   plan computes the PSF spectra once (nview*ny spectra of
+                                   about (Lx/2) Lz complex values, Lx >= nx+px-1 and
+                                   Lz >= nz+pz-1 the smallest even products of 2, 3, 5) and
+                                   keeps them in the workspace.  FP32 only, not with
+                                   SPECT_PSF_SEPARABLE; planes whose transform does not fit
+                                   the kernels' LDS give SPECT_ERR_UNSUPPORTED. */
 
 /* Geometry of one plan (host struct, copied by spect_plan_create). */
 typedef struct {
@@ -120,7 +131,8 @@ typedef struct {
                              during spect_plan_create */
   uint32_t flags;         /* SPECT_CACHE_MUBAR | SPECT_ROT_BILINEAR | SPECT_PSF_SEPARABLE |
                              SPECT_PSF_ALL_TAPS | SPECT_PSF_SYMMETRIC_X | SPECT_TILING_4X4 |
-                             SPECT_TILING_16X16, or 0; other bits give SPECT_ERR_VALUE */
+                             SPECT_TILING_16X16 | SPECT_CONV_FFT, or 0; other bits give
+                             SPECT_ERR_VALUE */
   int32_t view_batch;     /* views processed per internal batch; 0 = all.
                              Smaller batches need less workspace. */
   int32_t conv_precision; /* SPECT_CONV_FP32 (0), SPECT_CONV_BF16, SPECT_CONV_FP16 or
@@ -254,7 +266,7 @@ spect_status spect_profile_stop(spect_plan plan, spect_kernel_time* out, int32_t
 const char* spect_version(void);
 
 /* The kernels a plan selected, as one line of key=value pairs written to buf
- * (NUL-terminated, truncated to len bytes): conv = fp32-4x4 | fp32-16x16 |
+ * (NUL-terminated, truncated to len bytes): conv = fft | fp32-4x4 | fp32-16x16 |
  * fp32-direct (plain FP32 kernels, for PSFs taller than the matrix-core tiles
  * hold: pz >= 67) | separable | bf16 | fp16 | bf16x3, mirror = 1 when the FP32 4x4-block
  * convolution pairs mirror-image taps (see spect_plan_create), rotation =

@@ -85,6 +85,21 @@ struct LpShape {
   int nchunk, nchunk_back;// depth chunks (forward, adjoint)
 };
 
+// Transform sizes and pass radices of the FFT convolution (see conv_fft.hip).
+constexpr int kMaxFftPass = 12;
+struct FftShape {
+  int nx, ny, nz, px, pz, ha, hb;
+  int Lx, Lz;             // transform sizes (even, factors 2, 3, 5) >= padded plane
+  int Lh, H;              // Lx / 2, Lz / 2
+  int stride;             // row stride of the LDS plane (complex elements)
+  int nrx, nrz;           // passes along x and z
+  int rx[kMaxFftPass], rz[kMaxFftPass];
+  int NR, NS;             // regular spectrum slots, all slots (complex) per plane
+  float r_lx, r_lh, r_lh1, r_nx;  // 1 / Lx, 1 / Lh, 1 / (Lh - 1), 1 / nx
+  int nchunk, nchunk_back;
+  bool ok;                // fits the kernels' registers and LDS
+};
+
 // Per-view geometry tables, on the device (inside the workspace).
 //   quarter[l]             : m, number of quarter turns (0..3)
 //   off[l][0][j], w[l][0][j]: passes 1 and 3 (along i, one entry per row j)
@@ -120,6 +135,10 @@ struct Layout {
   size_t rot_scratch;   // working slices of the rotation kernels when nx > kMaxLdsN
   size_t em_proj2;      // nview * nz * nx floats (EM vector-Jacobian product)
   size_t em_vol2;       // N floats (EM vector-Jacobian product)
+  size_t fft_tables;    // 2 Lx + Lz ints: transform index tables (SPECT_CONV_FFT)
+  size_t fft_spectra;   // nview * ny * NS complex: PSF spectra (SPECT_CONV_FFT)
+  size_t fft_part;      // nchunk * view_batch * NS complex: forward partial spectra
+  size_t fft_vproj;     // view_batch * NS complex: projection spectra (adjoint)
   size_t total;
 };
 
@@ -127,7 +146,8 @@ struct Layout {
 enum KernelId {
   K_MUBAR = 0, K_ROT_FWD, K_CONV_FWD, K_FWD_REDUCE, K_CONV_BACK, K_ROT_BACK,
   K_BACK_REDUCE, K_EM_RATIO, K_EM_UPDATE, K_CONV_BACK_EDGES, K_EM_VJP, K_CONV_FWD_LP,
-  K_CONV_BACK_LP, K_EM_REG_UPDATE, K_COUNT
+  K_CONV_BACK_LP, K_EM_REG_UPDATE, K_PSF_SPECTRA, K_CONV_FWD_FFT, K_FWD_FFT_FINISH,
+  K_BACK_FFT_PREP, K_CONV_BACK_FFT, K_COUNT
 };
 extern const char* const kKernelNames[K_COUNT];
 
@@ -159,6 +179,8 @@ struct Plan {
   SepShape sep;
   int conv_precision;   // SPECT_CONV_FP32 / _BF16 / _FP16
   LpShape lp;           // tiling of the reduced-precision convolution
+  bool use_fft;         // SPECT_CONV_FFT: convolution through the FFT
+  FftShape fft;
   Profiler* prof;       // non-null while spect_profile_start is active
   // host copies of the tables (kept alive for the asynchronous upload)
   int32_t* h_quarter;
@@ -300,6 +322,13 @@ hipError_t launch_em_vjp_ratio(float* t, const float* v, const float* y, const f
 hipError_t launch_add(float* a, const float* b, size_t n, hipStream_t s);
 hipError_t launch_em_reg_update(float* x, const float* e, const float* sens, const float* u,
                                 float beta, size_t n, hipStream_t s);
+FftShape make_fft_shape(const spect_geom& g);
+void tune_fft_chunks(FftShape& s, int views);
+hipError_t launch_fft_psf_spectra(const Plan& p, hipStream_t s);
+hipError_t launch_conv_fwd_fft(const Plan& p, const float* W, int view0, int nvb, hipStream_t s);
+hipError_t launch_fwd_fft_finish(const Plan& p, float* v, int view0, int nvb, hipStream_t s);
+hipError_t launch_back_fft_prep(const Plan& p, const float* v, int view0, int nvb, hipStream_t s);
+hipError_t launch_conv_back_fft(const Plan& p, float* U, int view0, int nvb, hipStream_t s);
 hipError_t launch_dot_f64(const float* a, const float* b, size_t n, double* out, hipStream_t s);
 
 }  // namespace spect

@@ -21,7 +21,7 @@ static spect_status validate(const spect_geom* g) {
   if (!(std::isfinite(g->dy) && g->dy > 0.0)) return SPECT_ERR_VALUE;
   if (g->flags & ~(SPECT_CACHE_MUBAR | SPECT_ROT_BILINEAR | SPECT_PSF_SEPARABLE |
                    SPECT_PSF_ALL_TAPS | SPECT_PSF_SYMMETRIC_X | SPECT_TILING_4X4 |
-                   SPECT_TILING_16X16))
+                   SPECT_TILING_16X16 | SPECT_CONV_FFT))
     return SPECT_ERR_VALUE;
   if ((g->flags & SPECT_PSF_ALL_TAPS) && (g->flags & SPECT_PSF_SYMMETRIC_X)) return SPECT_ERR_VALUE;
   if ((g->flags & SPECT_TILING_4X4) && (g->flags & SPECT_TILING_16X16)) return SPECT_ERR_VALUE;
@@ -36,6 +36,12 @@ static spect_status validate(const spect_geom* g) {
   // index arithmetic inside a plane / slice uses 32-bit ints
   if ((int64_t)g->nx * g->nz > (1 << 30) || (int64_t)g->px * g->pz > (1 << 20))
     return SPECT_ERR_UNSUPPORTED;
+  if (g->flags & SPECT_CONV_FFT) {
+    // the FFT form: FP32, general PSFs, planes whose transforms fit LDS
+    if (g->conv_precision != SPECT_CONV_FP32 || (g->flags & SPECT_PSF_SEPARABLE) ||
+        !make_fft_shape(*g).ok)
+      return SPECT_ERR_UNSUPPORTED;
+  }
   if (g->flags & SPECT_PSF_SEPARABLE) {
     // separable PSFs: FP32 1-D passes only
     if (g->conv_precision != SPECT_CONV_FP32 || !make_sep_shape(*g).ok) return SPECT_ERR_UNSUPPORTED;
@@ -74,6 +80,15 @@ spect_status compute_layout(const spect_geom& g, Layout* lay, int* view_batch, i
   lay->em_vol = take(N * sizeof(float));
   lay->em_proj2 = take(M * sizeof(float));
   lay->em_vol2 = take(N * sizeof(float));
+  lay->fft_tables = lay->fft_spectra = lay->fft_part = lay->fft_vproj = 0;
+  if (g.flags & SPECT_CONV_FFT) {
+    const FftShape fs = make_fft_shape(g);
+    const size_t ns = (size_t)fs.NS * sizeof(float2);
+    lay->fft_tables = take((size_t)(2 * fs.Lx + fs.Lz) * sizeof(int));
+    lay->fft_spectra = take((size_t)g.nview * g.ny * ns);
+    lay->fft_part = take((size_t)kMaxChunks * vb * ns);
+    lay->fft_vproj = take((size_t)vb * ns);
+  }
   lay->total = off;
   *view_batch = vb;
   *nchunk = nc;
@@ -116,7 +131,9 @@ const char* const kKernelNames[K_COUNT] = {"mubar", "rot_fwd",  "conv_fwd",
                                            "fwd_reduce",  "conv_back", "rot_back",
                                            "back_reduce", "em_ratio", "em_update",
                                            "conv_back_edges", "em_vjp", "conv_fwd_lp",
-                                           "conv_back_lp", "em_reg_update"};
+                                           "conv_back_lp", "em_reg_update", "psf_spectra",
+                                           "conv_fwd_fft", "fwd_fft_finish", "back_fft_prep",
+                                           "conv_back_fft"};
 
 static void profiler_free(Profiler* pr) {
   if (!pr) return;
@@ -182,6 +199,13 @@ void configure_plan(Plan& p_, const spect_geom& g_, const Layout& lay, int vb, i
     tune_lp_chunks(p->lp, g->nview, p->conv_precision);
     p->nchunk = p->lp.nchunk;
   }
+  p->use_fft = (g->flags & SPECT_CONV_FFT) != 0;
+  if (p->use_fft) {
+    p->use_mfma = p->use_m4 = false;
+    p->fft = make_fft_shape(*g);
+    tune_fft_chunks(p->fft, vb);
+    p->nchunk = p->fft.nchunk;
+  }
   if (!(g->flags & SPECT_CACHE_MUBAR))
     p->mubar_batch = reinterpret_cast<float*>(p->ws + lay.mubar_batch);
 }
@@ -216,6 +240,14 @@ spect_status spect::forward_impl(const Plan& p, const float* x, float* v, hipStr
     if (timed(p, K_ROT_FWD, s, [&] { return launch_rot_fwd(p, x, mb, mb_off, W, v0, nvb, s); }) !=
         hipSuccess)
       return SPECT_ERR_HIP;
+    if (p.use_fft) {
+      if (timed(p, K_CONV_FWD_FFT, s, [&] { return launch_conv_fwd_fft(p, W, v0, nvb, s); }) !=
+              hipSuccess ||
+          timed(p, K_FWD_FFT_FINISH, s, [&] { return launch_fwd_fft_finish(p, v, v0, nvb, s); }) !=
+              hipSuccess)
+        return SPECT_ERR_HIP;
+      continue;
+    }
     const hipError_t ec =
         p.conv_precision != SPECT_CONV_FP32
             ? timed(p, K_CONV_FWD_LP, s, [&] { return launch_conv_fwd_lp(p, W, part, v0, nvb, s); })
@@ -238,7 +270,12 @@ static spect_status back_impl(const Plan& p, const float* v, float* x, hipStream
   for (int v0 = 0; v0 < p.g.nview; v0 += p.view_batch) {
     const int nvb = (p.g.nview - v0 < p.view_batch) ? p.g.nview - v0 : p.view_batch;
     const hipError_t ec =
-        p.conv_precision != SPECT_CONV_FP32
+        p.use_fft
+            ? (timed(p, K_BACK_FFT_PREP, s, [&] { return launch_back_fft_prep(p, v, v0, nvb, s); }) !=
+                       hipSuccess
+                   ? hipErrorUnknown
+                   : timed(p, K_CONV_BACK_FFT, s, [&] { return launch_conv_back_fft(p, U, v0, nvb, s); }))
+        : p.conv_precision != SPECT_CONV_FP32
             ? timed(p, K_CONV_BACK_LP, s, [&] { return launch_conv_back_lp(p, v, U, v0, nvb, s); })
             : timed(p, K_CONV_BACK, s, [&] {
                 if (p.separable) return launch_conv_sep(p, true, v, U, v0, nvb, s);  // folds included
@@ -272,7 +309,8 @@ spect_status spect_plan_describe(spect_plan plan, char* buf, size_t len) {
   if (len == 0) return SPECT_ERR_VALUE;
   const Plan* p = reinterpret_cast<const Plan*>(plan);
   static const char* const kLp[] = {"fp32", "bf16", "fp16", "bf16x3"};
-  const char* conv = p->separable ? "separable"
+  const char* conv = p->use_fft ? "fft"
+                     : p->separable ? "separable"
                      : p->conv_precision != SPECT_CONV_FP32 ? kLp[p->conv_precision & 3]
                      : p->use_m4    ? "fp32-4x4"
                      : p->use_mfma  ? "fp32-16x16"
@@ -356,6 +394,8 @@ spect_status spect_plan_create(spect_plan* out, const spect_geom* g, const float
     else if (!(g->flags & SPECT_PSF_ALL_TAPS))
       e = detect_m4_mirror(*p, reinterpret_cast<int*>(p->ws + lay.em_vol), stream);
   }
+  if (e == hipSuccess && p->use_fft)
+    e = timed(*p, K_PSF_SPECTRA, stream, [&] { return launch_fft_psf_spectra(*p, stream); });
   if (g->flags & SPECT_CACHE_MUBAR) {
     float* cache = reinterpret_cast<float*>(p->ws + lay.mubar_cache);
     if (e == hipSuccess)

@@ -101,5 +101,6 @@ extern "C" spect_status spect_forward_static(const spect_geom* g, const float* d
                      reinterpret_cast<float2*>(ws + lay.tables_w),
                      reinterpret_cast<float2*>(ws + lay.tables_rot));
   if (hipGetLastError() != hipSuccess) return SPECT_ERR_HIP;
+  if (p.use_fft && launch_fft_psf_spectra(p, stream) != hipSuccess) return SPECT_ERR_HIP;
   return forward_impl(p, d_x, d_v, stream);
 }

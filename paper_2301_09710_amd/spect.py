@@ -25,6 +25,8 @@ SPECT_PSF_ALL_TAPS = 0x8
 SPECT_PSF_SYMMETRIC_X = 0x10
 SPECT_TILING_4X4 = 0x20
 SPECT_TILING_16X16 = 0x40
+SPECT_CONV_FFT = 0x80
+METHODS = {"direct": 0, "fft": SPECT_CONV_FFT}
 MIRRORS = {"auto": 0, "off": SPECT_PSF_ALL_TAPS, "assume": SPECT_PSF_SYMMETRIC_X}
 TILINGS = {"auto": 0, "4x4": SPECT_TILING_4X4, "16x16": SPECT_TILING_16X16}
 ROTATIONS = {"3pass": 0, "bilinear": SPECT_ROT_BILINEAR}
@@ -246,10 +248,13 @@ class Plan:
     PSF row symmetric in x), "off" (SPECT_PSF_ALL_TAPS) or "assume"
     (SPECT_PSF_SYMMETRIC_X: the caller states the symmetry; no check, no
     wait).  tiling: "auto", "4x4" or "16x16" (the FP32 convolution's blocks).
+    method: "direct" (the convolution sum on the matrix cores) or "fft"
+    (SPECT_CONV_FFT: FP32 FFTs, the same operator).
     """
 
     def __init__(self, mu, psf, dy, angles=None, cache_mubar=False, view_batch=0,
-                 precision="fp32", rotation="3pass", mirror="auto", tiling="auto"):
+                 precision="fp32", rotation="3pass", mirror="auto", tiling="auto",
+                 method="direct"):
         import torch
         self.device = mu.device
         if self.device.type != "cuda":
@@ -281,8 +286,12 @@ class Plan:
             raise ValueError(f"mirror must be one of {sorted(MIRRORS)}")
         if tiling not in TILINGS:
             raise ValueError(f"tiling must be one of {sorted(TILINGS)}")
+        if method not in METHODS:
+            raise ValueError(f"method must be one of {sorted(METHODS)}")
+        self.method = method
         flags = ((SPECT_CACHE_MUBAR if cache_mubar else 0) | ROTATIONS[rotation] |
-                 (SPECT_PSF_SEPARABLE if sep else 0) | MIRRORS[mirror] | TILINGS[tiling])
+                 (SPECT_PSF_SEPARABLE if sep else 0) | MIRRORS[mirror] | TILINGS[tiling] |
+                 METHODS[method])
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
         self.precision = precision

@@ -51,7 +51,7 @@ def test_status_strings():
     (dict(nview=0), 2),
     (dict(dy=0.0), 3),
     (dict(dy=float("nan")), 3),
-    (dict(flags=0x80), 3),            # unknown flag bit
+    (dict(flags=0x100), 3),           # unknown flag bit
     (dict(flags=0x18), 3),            # all taps and stated symmetry together
     (dict(flags=0x60), 3),            # both FP32 tilings together
     (dict(flags=0x4, conv_precision=1), 5),   # separable PSFs: FP32 only
@@ -184,3 +184,25 @@ def test_static_forward_rejects_before_any_gpu_call():
     g, _ = spect.make_geom(16, 16, 8, 3, 3, 3, 1.0)
     assert lib.spect_forward_static(ctypes.byref(g), None, fake, fake, fake, None) == 1
     assert lib.spect_forward_static(ctypes.byref(g), fake, fake, fake + 2, fake, None) == 7
+
+
+def test_fft_flag_validation_and_workspace():
+    """SPECT_CONV_FFT: FP32 only, not with separable PSFs; the plan keeps the
+    PSF spectra, so the workspace grows by at least nview * ny spectra."""
+    base, _ = spect.make_geom(128, 128, 80, 128, 37, 37, 4.8)
+    fft, _ = spect.make_geom(128, 128, 80, 128, 37, 37, 4.8, flags=spect.SPECT_CONV_FFT)
+    b0, b1 = spect.spect_workspace_bytes(base), spect.spect_workspace_bytes(fft)
+    # 180 x 120 transforms: 89 x 120 + 2 x 61 complex slots per PSF
+    assert b1 - b0 >= 128 * 128 * (89 * 120 + 122) * 8
+    for kw in (dict(conv_precision=1), dict(conv_precision=3),
+               dict(flags=spect.SPECT_CONV_FFT | spect.SPECT_PSF_SEPARABLE)):
+        args = dict(flags=spect.SPECT_CONV_FFT)
+        args.update(kw)
+        g, _ = spect.make_geom(32, 32, 20, 16, 7, 7, 1.0, **args)
+        with pytest.raises(spect.SpectError) as e:
+            spect.spect_workspace_bytes(g)
+        assert e.value.status == 5
+    g, _ = spect.make_geom(256, 256, 160, 128, 37, 37, 2.4, flags=spect.SPECT_CONV_FFT)
+    with pytest.raises(spect.SpectError) as e:      # 300 x 200 transforms exceed LDS
+        spect.spect_workspace_bytes(g)
+    assert e.value.status == 5
