@@ -34,212 +34,19 @@
 #include <type_traits>
 #include <utility>
 
+#include "fft_core.h"
 #include "internal.h"
 
 namespace spect {
 namespace {
+
+using namespace fft;
 
 constexpr int kFftThreads = 512;
 constexpr int kMaxPlane = 12288;  // complex elements of the LDS plane (Lz / 2 x Lx) at most
 constexpr int kMaxSlots = 24;     // regular slots a thread owns
 constexpr int kMaxPlaneRegs = 24; // raw plane values a thread prefetches (forward)
 constexpr int kMaxFftLen = 1024;   // transform length along x at most
-
-// q / d and q mod d for 0 <= q < 2^16 and 1 <= d < 2^16 through the FP32
-// reciprocal rd = 1 / d: (q + 1/2) / d lies at least 1 / (2 d) from an
-// integer, and the rounding error of (q + 1/2) rd is below 2^-22 (q + 1/2) / d,
-// far less.
-__device__ __forceinline__ int fdiv(int q, float rd) { return (int)(((float)q + 0.5f) * rd); }
-
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-// a * conj(b)
-__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
-  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
-}
-__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
-// i s a
-__device__ __forceinline__ float2 cimul(float2 a, float s) { return make_float2(-s * a.y, s * a.x); }
-__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
-
-// R-point DFT in place, X[m] = sum_r v[r] exp(sg 2 pi i r m / R), sg = -1
-// (forward) or +1 (inverse).
-template <int R, bool kInv>
-__device__ __forceinline__ void dft(float2 (&v)[R]) {
-  constexpr float sg = kInv ? 1.0f : -1.0f;
-  if constexpr (R == 2) {
-    const float2 a = v[0], b = v[1];
-    v[0] = cadd(a, b);
-    v[1] = csub(a, b);
-  } else if constexpr (R == 3) {
-    const float h = 0.86602540378443864676f;   // sin(2 pi / 3)
-    const float2 s = cadd(v[1], v[2]), d = csub(v[1], v[2]);
-    const float2 t = make_float2(v[0].x - 0.5f * s.x, v[0].y - 0.5f * s.y);
-    const float2 u = cimul(d, sg * h);
-    v[0] = cadd(v[0], s);
-    v[1] = cadd(t, u);
-    v[2] = csub(t, u);
-  } else if constexpr (R == 4) {
-    const float2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
-    const float2 c = cadd(v[1], v[3]), d = cimul(csub(v[1], v[3]), sg);
-    v[0] = cadd(a, c);
-    v[2] = csub(a, c);
-    v[1] = cadd(b, d);
-    v[3] = csub(b, d);
-  } else {
-    static_assert(R == 5, "radix 2, 3, 4 or 5");
-    const float c1 = 0.30901699437494742410f;    // cos(2 pi / 5)
-    const float c2 = -0.80901699437494742410f;   // cos(4 pi / 5)
-    const float s1 = 0.95105651629515357212f;    // sin(2 pi / 5)
-    const float s2 = 0.58778525229247312917f;    // sin(4 pi / 5)
-    const float2 a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
-    const float2 a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
-    const float2 x0 = v[0];
-    const float2 r1 = make_float2(x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y);
-    const float2 r2 = make_float2(x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y);
-    const float2 i1 = cimul(make_float2(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y), sg);
-    const float2 i2 = cimul(make_float2(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y), sg);
-    v[0] = cadd(x0, cadd(a1, a2));
-    v[1] = cadd(r1, i1);
-    v[4] = csub(r1, i1);
-    v[2] = cadd(r2, i2);
-    v[3] = csub(r2, i2);
-  }
-}
-
-// Index tables of one plan's transforms (in LDS):
-//   posx[f], posz[q]: where frequency f (q) of a transform along x (z) sits
-//     after the in-place decimation-in-frequency passes (mixed-radix digit
-//     reversal);
-//   vc1[v], vc2[v]: the columns of virtual column v (x frequency f < Lx/2) in
-//     the first and the second half of the row pairs, in increasing vc1; v = 0
-//     is frequency 0 (with Lx/2 in the second half: the two real columns).
-struct Tabs {
-  const int* posx;
-  const int* posz;
-  const int* vc1;
-  const int* vc2;
-};
-
-// Twiddle constants of the composite radices, evaluated at compile time
-// (Taylor series in FP64 on [-pi, pi]).
-constexpr double kTwoPi = 6.28318530717958647692528676655900577;
-constexpr double csin(double x) {
-  while (x > kTwoPi / 2) x -= kTwoPi;
-  while (x < -kTwoPi / 2) x += kTwoPi;
-  double term = x, sum = x;
-  for (int n = 1; n < 30; ++n) {
-    term *= -x * x / ((2.0 * n) * (2.0 * n + 1.0));
-    sum += term;
-  }
-  return sum;
-}
-constexpr double ccos(double x) { return csin(x + kTwoPi / 4); }
-
-template <class F, int... I>
-__device__ __forceinline__ void unroll_seq(F&& f, std::integer_sequence<int, I...>) {
-  (f(std::integral_constant<int, I>()), ...);
-}
-template <int N, class F>
-__device__ __forceinline__ void unroll(F&& f) {
-  unroll_seq(f, std::make_integer_sequence<int, N>());
-}
-
-// Factors of the composite radices: R = Ra Rb.
-template <int R> struct Split;
-template <> struct Split<6> { static constexpr int a = 2, b = 3; };
-template <> struct Split<8> { static constexpr int a = 2, b = 4; };
-template <> struct Split<9> { static constexpr int a = 3, b = 3; };
-template <> struct Split<10> { static constexpr int a = 2, b = 5; };
-template <> struct Split<12> { static constexpr int a = 3, b = 4; };
-template <> struct Split<15> { static constexpr int a = 3, b = 5; };
-
-template <int R, bool kInv>
-__device__ __forceinline__ void dft_any(float2 (&v)[R]);
-
-// R-point DFT for R = Ra Rb in registers (Cooley-Tukey): input n = Rb n1 + n2,
-// Ra-point DFTs over n1, twiddles exp(sg 2 pi i n2 k1 / R), Rb-point DFTs over
-// n2, output k = k1 + Ra k2 (natural order).
-template <int Ra, int Rb, bool kInv>
-__device__ __forceinline__ void dft_comp(float2 (&v)[Ra * Rb]) {
-  constexpr int R = Ra * Rb;
-  constexpr double sg = kInv ? 1.0 : -1.0;
-  float2 y[Ra][Rb];
-  unroll<Rb>([&](auto n2c) {
-    constexpr int n2 = decltype(n2c)::value;
-    float2 t[Ra];
-    unroll<Ra>([&](auto n1c) { t[decltype(n1c)::value] = v[Rb * decltype(n1c)::value + n2]; });
-    dft_any<Ra, kInv>(t);
-    unroll<Ra>([&](auto k1c) {
-      constexpr int k1 = decltype(k1c)::value;
-      constexpr int e = (n2 * k1) % R;
-      if constexpr (e == 0) {
-        y[k1][n2] = t[k1];
-      } else {
-        constexpr float c = (float)ccos(kTwoPi * e / R);
-        constexpr float sn = (float)csin(sg * kTwoPi * e / R);
-        y[k1][n2] = cmul(t[k1], make_float2(c, sn));
-      }
-    });
-  });
-  unroll<Ra>([&](auto k1c) {
-    constexpr int k1 = decltype(k1c)::value;
-    float2 t[Rb];
-    unroll<Rb>([&](auto n2c) { t[decltype(n2c)::value] = y[k1][decltype(n2c)::value]; });
-    dft_any<Rb, kInv>(t);
-    unroll<Rb>([&](auto k2c) { v[k1 + Ra * decltype(k2c)::value] = t[decltype(k2c)::value]; });
-  });
-}
-
-template <int R, bool kInv>
-__device__ __forceinline__ void dft_any(float2 (&v)[R]) {
-  if constexpr (R <= 5) dft<R, kInv>(v);
-  else dft_comp<Split<R>::a, Split<R>::b, kInv>(v);
-}
-
-// Element t of transform b: rows (b = row pair, along x) or virtual columns
-// (b = virtual column, along z).
-struct RowAddr {
-  int stride;
-  __device__ __forceinline__ int operator()(int b, int t) const { return b * stride + t; }
-};
-struct ColAddr {
-  int stride, H;
-  const int* vc1;
-  const int* vc2;
-  __device__ __forceinline__ int operator()(int b, int t) const {
-    return t < H ? t * stride + vc1[b] : (t - H) * stride + vc2[b];
-  }
-};
-
-// Stage twiddles w[r] = tw[r d] = exp(-2 pi i r d / N) for r < R (w[0] unused).
-// For R = Ra Rb, r = k1 + Ra k2: w[r] = tw[k1 d] tw[Ra k2 d], Ra + Rb - 2
-// table reads instead of R - 1 (one more FP32 rounding per twiddle).
-template <int R>
-__device__ __forceinline__ void stage_twiddles(float2 (&w)[R], const float2* tw, int d) {
-  if constexpr (R <= 5) {
-#pragma unroll
-    for (int r = 1; r < R; ++r) w[r] = tw[r * d];
-  } else {
-    constexpr int Ra = Split<R>::a, Rb = Split<R>::b;
-    float2 ta[Ra], tb[Rb];
-#pragma unroll
-    for (int k1 = 1; k1 < Ra; ++k1) ta[k1] = tw[k1 * d];
-#pragma unroll
-    for (int k2 = 1; k2 < Rb; ++k2) tb[k2] = tw[Ra * k2 * d];
-#pragma unroll
-    for (int k2 = 0; k2 < Rb; ++k2)
-#pragma unroll
-      for (int k1 = 0; k1 < Ra; ++k1) {
-        const int r = k1 + Ra * k2;
-        if (r == 0) continue;
-        w[r] = k2 == 0 ? ta[k1] : (k1 == 0 ? tb[k2] : cmul(ta[k1], tb[k2]));
-      }
-  }
-}
 
 // One in-place pass of radix R over `batch` transforms of length N, stage of
 // sub-transform length Ns (S = Ns / R).  Forward (decimation in frequency):
@@ -772,26 +579,8 @@ __global__ __launch_bounds__(kFftThreads) void conv_back_fft(const float2* __res
     __syncthreads();
     if (j + 1 < j1) load_p(j + 1);
     fft2_inverse(m.A, s, m.t, m.twx, m.twz);
-    // fold of the padded columns onto column i (the padded columns that
-    // clamp onto i), for every padded row, then of the padded rows onto row k
-    const int KZ = s.nz + 2 * s.hb;
-    for (int e = tid; e < KZ * s.nx; e += kFftThreads) {
-      const int zz = fdiv(e, s.r_nx), i = e - zz * s.nx;
-      const int xl = (i == 0) ? 0 : i + s.ha;
-      const int xh = (i == s.nx - 1) ? s.nx - 1 + 2 * s.ha : i + s.ha;
-      float acc = 0.0f;
-      for (int xx = xl; xx <= xh; ++xx) acc += plane_at(m.A, s, zz, xx);
-      m.raw[e] = acc;
-    }
-    __syncthreads();
-    for (int e = tid; e < s.nz * s.nx; e += kFftThreads) {
-      const int k = fdiv(e, s.r_nx), i = e - k * s.nx;
-      const int zl = (k == 0) ? 0 : k + s.hb;
-      const int zh = (k == s.nz - 1) ? s.nz - 1 + 2 * s.hb : k + s.hb;
-      float acc = 0.0f;
-      for (int zz = zl; zz <= zh; ++zz) acc += m.raw[zz * s.nx + i];
-      Ul[(size_t)k * rs + (size_t)j * s.nx + i] = acc;
-    }
+    fold_store(m.A, m.raw, s.nx, s.nz, s.ha, s.hb, Ul + (size_t)j * s.nx, rs,
+               [&](const float2* A, int k, int c) { return plane_at(A, s, k, c); }, kFftThreads);
   }
 }
 
@@ -934,7 +723,8 @@ FftShape make_fft_shape(const spect_geom& g) {
             (s.NR + kFftThreads - 1) / kFftThreads <= kMaxSlots && s.H + 1 <= kFftThreads &&
             g.nz * g.nx <= kMaxPlaneRegs * kFftThreads && fft_smem(s, 1) <= kLdsBytes &&
             fft_smem(s, 2) <= kLdsBytes;
-  s.ok = ok;
+  s.cfg = fft_fixed_config(s);
+  s.ok = ok || s.cfg != 0;
   return s;
 }
 
@@ -954,6 +744,7 @@ void tune_fft_chunks(FftShape& s, int views) {
 
 hipError_t launch_fft_psf_spectra(const Plan& p, hipStream_t st) {
   const FftShape& s = p.fft;
+  if (s.cfg) return launch_fft_fixed(p, kFftSpectra, nullptr, nullptr, 0, 0, st);
   hipLaunchKernelGGL(fft_index_tables, dim3(1), dim3(kFftThreads), 0, st,
                      reinterpret_cast<int*>(p.ws + p.lay.fft_tables), s);
   hipError_t e = hipGetLastError();
@@ -968,16 +759,19 @@ hipError_t launch_fft_psf_spectra(const Plan& p, hipStream_t st) {
 }
 
 hipError_t launch_conv_fwd_fft(const Plan& p, const float* W, int view0, int nvb, hipStream_t st) {
+  if (p.fft.cfg) return launch_fft_fixed(p, kFftForward, W, nullptr, view0, nvb, st);
   return small_slots(p.fft) ? launch_fwd_ks<8>(p, W, view0, nvb, st)
                             : launch_fwd_ks<kMaxSlots>(p, W, view0, nvb, st);
 }
 
 hipError_t launch_fwd_fft_finish(const Plan& p, float* v, int view0, int nvb, hipStream_t st) {
+  if (p.fft.cfg) return launch_fft_fixed(p, kFftFinish, nullptr, v, view0, nvb, st);
   return small_slots(p.fft) ? launch_finish_ks<8>(p, v, view0, nvb, st)
                             : launch_finish_ks<kMaxSlots>(p, v, view0, nvb, st);
 }
 
 hipError_t launch_back_fft_prep(const Plan& p, const float* v, int view0, int nvb, hipStream_t st) {
+  if (p.fft.cfg) return launch_fft_fixed(p, kFftBackPrep, v, nullptr, view0, nvb, st);
   const FftShape& s = p.fft;
   const size_t sm = fft_smem(s, 0);
   hipError_t e = set_fft_smem((const void*)back_fft_prep, sm);
@@ -988,6 +782,7 @@ hipError_t launch_back_fft_prep(const Plan& p, const float* v, int view0, int nv
 }
 
 hipError_t launch_conv_back_fft(const Plan& p, float* U, int view0, int nvb, hipStream_t st) {
+  if (p.fft.cfg) return launch_fft_fixed(p, kFftBack, nullptr, U, view0, nvb, st);
   return small_slots(p.fft) ? launch_back_ks<8>(p, U, view0, nvb, st)
                             : launch_back_ks<kMaxSlots>(p, U, view0, nvb, st);
 }

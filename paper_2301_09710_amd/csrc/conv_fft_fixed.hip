@@ -1,0 +1,541 @@
+// The FFT convolution of conv_fft.hip for transform sizes fixed at compile
+// time (Sec. II-A: each depth plane convolved with its PSF by FFT, replicate
+// padding; the adjoint with the padding's fold).  Same operator, same data
+// flow and the same slot semantics (regular bins, then the two real columns'
+// bins for z frequencies 0..Lz/2) as the runtime-size kernels; only the order
+// of the regular slots differs (here: LDS order), and every spectrum a plan
+// uses comes from the same kernels.  With the sizes and the two radices per
+// axis known to the compiler, every index -- butterfly, twiddle, digit
+// reversal, slot position -- is constant arithmetic instead of table lookups
+// and divisions, and the LDS row stride is odd (Lx + 1 complex values), so
+// that the transform-major passes read and write without bank conflicts.
+//
+// A configuration: Lx = Rx0 Rx1 (Rx1 even), Lz = Rz0 Rz1, each axis two
+// in-place passes (decimation in frequency forward, the exact reverse
+// inverse).  Frequency f along x sits at column (f mod Rx0) (Lx / Rx0) +
+// f / Rx0; the frequencies below Lx/2 are those with f / Rx0 < Rx1 / 2, so
+// virtual column v (x frequency v / (Rx1/2) + Rx0 (v mod Rx1/2)) starts at
+// column (v / (Rx1/2)) (Lx / Rx0) + v mod (Rx1/2), and columns 0 and Rx1/2
+// hold frequencies 0 and Lx/2.
+#include "fft_core.h"
+#include "internal.h"
+
+namespace spect {
+namespace {
+
+using namespace fft;
+
+constexpr int kT = 512;
+
+template <int LX, int LZ, int RX0, int RX1, int RZ0, int RZ1>
+struct Cfg {
+  static constexpr int Lx = LX, Lz = LZ, Lh = LX / 2, H = LZ / 2, ST = LX + 1;
+  static constexpr int Rx0 = RX0, Rx1 = RX1, Rz0 = RZ0, Rz1 = RZ1;
+  static constexpr int Sx = LX / RX0, Sz = LZ / RZ0;
+  static constexpr int HR = RX1 / 2;               // also the column of frequency Lx/2
+  static constexpr int NR = H * (LX - 2), NS = NR + 2 * (H + 1);
+  static constexpr int KS = (NR + kT - 1) / kT;
+  static_assert(RX0 * RX1 == LX && RZ0 * RZ1 == LZ && RX1 % 2 == 0 && LZ % 2 == 0, "config");
+  __device__ static int posx(int f) { return (f % RX0) * Sx + f / RX0; }
+  __device__ static int posz(int q) { return (q % RZ0) * Sz + q / RZ0; }
+  __device__ static int c1(int v) { return (v / HR) * Sx + v % HR; }
+  __device__ static int c2(int v) {
+    const int f = v / HR + RX0 * (v % HR);
+    return posx(f == 0 ? Lh : LX - f);
+  }
+  // LDS index of regular slot q: row pair q / (Lx - 2), columns other than 0 and HR
+  __device__ static int slot(int q) {
+    const int p = q / (LX - 2), c = q - p * (LX - 2) + 1;
+    return p * ST + c + (c >= HR ? 1 : 0);
+  }
+  // LDS index of the packed real-column pair at z frequency zq
+  __device__ static int col0(int zq) {
+    const int r = posz(zq);
+    return r < H ? r * ST : (r - H) * ST + HR;
+  }
+};
+
+// C2 workload planes (128 x 80, 37 x 37 PSF) and the 64 x 40 / 19 x 19 serving planes.
+using Cfg180x120 = Cfg<180, 120, 15, 12, 12, 10>;
+using Cfg90x60 = Cfg<90, 60, 9, 10, 10, 6>;
+
+__device__ __forceinline__ void init_tw(float2* tw, int N) {
+  for (int t = threadIdx.x; t < N; t += kT) {
+    double sn, cs;
+    sincospi(-2.0 * (double)t / (double)N, &sn, &cs);
+    tw[t] = make_float2((float)cs, (float)sn);
+  }
+}
+
+// One in-place pass (see ct_pass in conv_fft.hip): radix R, sub-transform
+// length Ns, rows (along x) or virtual columns (along z).  Lanes take
+// consecutive transforms when the butterflies' stride S is short (then the
+// odd row stride or the virtual-column order spreads them over the banks),
+// consecutive butterflies otherwise.
+template <class C, int R, int Ns, bool kCol, bool kInv>
+__device__ __forceinline__ void pass(float2* A, const float2* tw) {
+  constexpr int N = kCol ? C::Lz : C::Lx;
+  constexpr int batch = kCol ? C::Lh : C::H;
+  constexpr int S = Ns / R, Nb = N / R, B = batch * Nb, step = N / Ns;
+  constexpr bool tmajor = S < 16;
+#pragma unroll 1
+  for (int b = threadIdx.x; b < B; b += kT) {
+    int tb, j;
+    if (tmajor) { j = b / batch; tb = b - j * batch; }
+    else { tb = b / Nb; j = b - tb * Nb; }
+    const int o = j / S, k = j - o * S;
+    const int t0 = o * Ns + k;
+    int ad[R];
+    if constexpr (!kCol) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) ad[r] = tb * C::ST + t0 + r * S;
+    } else {
+      const int b1 = t0 * C::ST + C::c1(tb), b2 = (t0 - C::H) * C::ST + C::c2(tb);
+#pragma unroll
+      for (int r = 0; r < R; ++r) ad[r] = (t0 + r * S < C::H ? b1 : b2) + r * S * C::ST;
+    }
+    float2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = A[ad[r]];
+    float2 w[R];
+    stage_twiddles<R>(w, tw, k * step);
+    if (kInv) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[r] = cmulc(v[r], w[r]);
+      dft_any<R, true>(v);
+    } else {
+      dft_any<R, false>(v);
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], w[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) A[ad[r]] = v[r];
+  }
+  __syncthreads();
+}
+
+// Row pairs after the forward x transforms (R1 at f, R2 at -f; see
+// unpack_rows in conv_fft.hip); lanes take consecutive row pairs.
+template <class C>
+__device__ __forceinline__ void unpack_rows(float2* A) {
+  for (int e = threadIdx.x; e < C::H * C::Lh; e += kT) {
+    const int f = e / C::H, p = e - f * C::H;
+    float2* row = A + p * C::ST;
+    if (f == 0) {
+      const float2 z0 = row[0], zn = row[C::HR];
+      row[0] = make_float2(z0.x, zn.x);
+      row[C::HR] = make_float2(z0.y, zn.y);
+    } else {
+      const int cf = C::posx(f), cm = C::posx(C::Lx - f);
+      const float2 zf = row[cf], zm = cconj(row[cm]);
+      row[cf] = cscale(cadd(zf, zm), 0.5f);
+      row[cm] = cimul(csub(zf, zm), -0.5f);
+    }
+  }
+  __syncthreads();
+}
+
+template <class C>
+__device__ __forceinline__ void repack_rows(float2* A) {
+  for (int e = threadIdx.x; e < C::H * C::Lh; e += kT) {
+    const int f = e / C::H, p = e - f * C::H;
+    float2* row = A + p * C::ST;
+    if (f == 0) {
+      const float2 a = row[0], b = row[C::HR];
+      row[0] = make_float2(a.x, b.x);
+      row[C::HR] = make_float2(a.y, b.y);
+    } else {
+      const int cf = C::posx(f), cm = C::posx(C::Lx - f);
+      const float2 r1 = row[cf], r2 = row[cm];
+      row[cf] = cadd(r1, cimul(r2, 1.0f));
+      row[cm] = cadd(cconj(r1), cimul(cconj(r2), 1.0f));
+    }
+  }
+  __syncthreads();
+}
+
+template <class C, class F>
+__device__ __forceinline__ void fft2_fwd(float2* A, const float2* twx, const float2* twz,
+                                         F&& before_last) {
+  pass<C, C::Rx0, C::Lx, false, false>(A, twx);
+  pass<C, C::Rx1, C::Rx1, false, false>(A, twx);
+  unpack_rows<C>(A);
+  pass<C, C::Rz0, C::Lz, true, false>(A, twz);
+  before_last();
+  pass<C, C::Rz1, C::Rz1, true, false>(A, twz);
+}
+
+template <class C>
+__device__ __forceinline__ void fft2_inv(float2* A, const float2* twx, const float2* twz) {
+  pass<C, C::Rz1, C::Rz1, true, true>(A, twz);
+  pass<C, C::Rz0, C::Lz, true, true>(A, twz);
+  repack_rows<C>(A);
+  pass<C, C::Rx1, C::Rx1, false, true>(A, twx);
+  pass<C, C::Rx0, C::Lx, false, true>(A, twx);
+}
+
+template <class C>
+__device__ __forceinline__ float plane_at(const float2* A, int k, int c) {
+  return k < C::H ? A[k * C::ST + c].x : A[(k - C::H) * C::ST + c].y;
+}
+
+template <class C>
+__device__ __forceinline__ void unpack_col0(const float2* A, int zq, float2* x0, float2* xn) {
+  const float2 y = A[C::col0(zq)];
+  const float2 ym = cconj(A[C::col0(zq == 0 ? 0 : C::Lz - zq)]);
+  *x0 = cscale(cadd(y, ym), 0.5f);
+  *xn = cimul(csub(y, ym), -0.5f);
+}
+
+template <class C>
+__device__ __forceinline__ void pack_col0(float2* A, int zq, float2 x0, float2 xn) {
+  if (zq == 0 || zq == C::H) {
+    A[C::col0(zq)] = make_float2(x0.x, xn.x);
+  } else {
+    A[C::col0(zq)] = cadd(x0, cimul(xn, 1.0f));
+    A[C::col0(C::Lz - zq)] = cadd(cconj(x0), cimul(cconj(xn), 1.0f));
+  }
+}
+
+template <class C>
+__device__ __forceinline__ void store_slots(const float2* A, float2* out, float scale) {
+  for (int q = threadIdx.x; q < C::NR; q += kT) out[q] = cscale(A[C::slot(q)], scale);
+  for (int zq = threadIdx.x; zq <= C::H; zq += kT) {
+    float2 x0, xn;
+    unpack_col0<C>(A, zq, &x0, &xn);
+    out[C::NR + 2 * zq] = cscale(x0, scale);
+    out[C::NR + 2 * zq + 1] = cscale(xn, scale);
+  }
+}
+
+__device__ __forceinline__ int clampi(int q, int lo, int hi) { return q < lo ? lo : (q > hi ? hi : q); }
+
+__device__ __forceinline__ void chunk_range(int c, int nchunk, int ny, int& j0, int& j1) {
+  j0 = (int)(((long long)c * ny) / nchunk);
+  j1 = (int)(((long long)(c + 1) * ny) / nchunk);
+}
+
+// LDS: plane (H x ST complex), twiddles (Lx + Lz), then the raw plane
+// (forward) or the column-folded plane (adjoint).
+template <class C>
+struct Lds {
+  float2* A;
+  float2* twx;
+  float2* twz;
+  float* extra;
+  __device__ explicit Lds(float2* sm) {
+    A = sm;
+    twx = sm + C::H * C::ST;
+    twz = twx + C::Lx;
+    extra = reinterpret_cast<float*>(twz + C::Lz);
+  }
+  __device__ void setup() const {
+    init_tw(twx, C::Lx);
+    init_tw(twz, C::Lz);
+  }
+};
+
+template <class C>
+constexpr size_t smem_bytes(int extra_floats) {
+  return ((size_t)C::H * C::ST + C::Lx + C::Lz) * sizeof(float2) + (size_t)extra_floats * sizeof(float);
+}
+
+// ---------------------------------------------------------------- kernels
+
+template <class C>
+__global__ __launch_bounds__(kT) void psf_spectra_c(const float* __restrict__ psf,
+                                                    float2* __restrict__ P, FftShape s) {
+  extern __shared__ float2 sm2[];
+  const Lds<C> m(sm2);
+  const int jl = blockIdx.x;
+  const float* p = psf + (size_t)jl * s.pz * s.px;
+  m.setup();
+  for (int e = threadIdx.x; e < C::H * C::Lx; e += kT) {
+    const int r = e / C::Lx, c = e - r * C::Lx;
+    const float lo = (r < s.pz && c < s.px) ? p[r * s.px + c] : 0.0f;
+    const float hi = (r + C::H < s.pz && c < s.px) ? p[(r + C::H) * s.px + c] : 0.0f;
+    m.A[r * C::ST + c] = make_float2(lo, hi);
+  }
+  __syncthreads();
+  fft2_fwd<C>(m.A, m.twx, m.twz, [] {});
+  store_slots<C>(m.A, P + (size_t)jl * C::NS, 1.0f / ((float)C::Lx * (float)C::Lz));
+}
+
+template <class C>
+__global__ __launch_bounds__(kT) void conv_fwd_fft_c(const float* __restrict__ W,
+                                                     const float2* __restrict__ P,
+                                                     float2* __restrict__ part, FftShape s,
+                                                     int view0, int nvb) {
+  extern __shared__ float2 sm2[];
+  const Lds<C> m(sm2);
+  const int c = blockIdx.x % s.nchunk, lb = blockIdx.x / s.nchunk, l = view0 + lb;
+  int j0, j1;
+  chunk_range(c, s.nchunk, s.ny, j0, j1);
+  m.setup();
+  const int tid = threadIdx.x, nx = s.nx, nz = s.nz, plane = nz * nx;
+  const size_t rs = (size_t)s.ny * nx;
+  const float* Wl = W + (size_t)lb * nz * rs;
+  const float rnx = 1.0f / (float)nx;
+  float2 acc[C::KS], a0 = make_float2(0.f, 0.f), an = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int q = 0; q < C::KS; ++q) acc[q] = make_float2(0.f, 0.f);
+  // plane j of W straight into the raw LDS region (lane L of a wave writes
+  // the wave's base + 4 L bytes: 64 consecutive elements of the [nz][nx] plane)
+  auto load_plane = [&](int j) {
+    const int lane = tid & 63, wbase = tid - lane;
+    for (int e0 = wbase; e0 < plane; e0 += kT) {
+      const int e = e0 + lane;
+      if (e < plane) {
+        const int k = fdiv(e, rnx), i = e - k * nx;
+        __builtin_amdgcn_global_load_lds(Wl + (size_t)k * rs + (size_t)j * nx + i,
+                                         (__attribute__((address_space(3))) void*)(m.extra + e0),
+                                         4, 0, 0);
+      }
+    }
+  };
+  if (j0 < j1) load_plane(j0);
+  const int KZ = nz + 2 * s.hb, IX = nx + 2 * s.ha;
+  for (int j = j0; j < j1; ++j) {
+    const float2* Pj = P + ((size_t)l * s.ny + j) * C::NS;
+    float2 pr[C::KS], p0 = make_float2(0.f, 0.f), pn = make_float2(0.f, 0.f);
+    auto load_p = [&] {
+#pragma unroll
+      for (int q = 0; q < C::KS; ++q) {
+        const int sl = tid + q * kT;
+        if (sl < C::NR) pr[q] = Pj[sl];
+      }
+      if (tid <= C::H) {
+        p0 = Pj[C::NR + 2 * tid];
+        pn = Pj[C::NR + 2 * tid + 1];
+      }
+    };
+    __builtin_amdgcn_s_waitcnt(0);                 // this plane's loads into raw landed
+    __syncthreads();                               // raw complete, A free, twiddles ready
+    for (int e = tid; e < C::H * C::Lx; e += kT) {
+      const int r = e / C::Lx, cc = e - r * C::Lx;
+      float lo = 0.0f, hi = 0.0f;
+      if (cc < IX) {
+        const int ii = clampi(cc - s.ha, 0, nx - 1);
+        if (r < KZ) lo = m.extra[clampi(r - s.hb, 0, nz - 1) * nx + ii];
+        if (r + C::H < KZ) hi = m.extra[clampi(r + C::H - s.hb, 0, nz - 1) * nx + ii];
+      }
+      m.A[r * C::ST + cc] = make_float2(lo, hi);
+    }
+    __syncthreads();                               // raw consumed
+    if (j + 1 < j1) load_plane(j + 1);
+    fft2_fwd<C>(m.A, m.twx, m.twz, load_p);
+#pragma unroll
+    for (int q = 0; q < C::KS; ++q) {
+      const int sl = tid + q * kT;
+      if (sl < C::NR) {
+        const float2 f = m.A[C::slot(sl)];
+        acc[q].x += pr[q].x * f.x - pr[q].y * f.y;
+        acc[q].y += pr[q].x * f.y + pr[q].y * f.x;
+      }
+    }
+    if (tid <= C::H) {
+      float2 x0, xn;
+      unpack_col0<C>(m.A, tid, &x0, &xn);
+      a0 = cadd(a0, cmul(p0, x0));
+      an = cadd(an, cmul(pn, xn));
+    }
+  }
+  float2* out = part + ((size_t)c * nvb + lb) * C::NS;
+#pragma unroll
+  for (int q = 0; q < C::KS; ++q) {
+    const int sl = tid + q * kT;
+    if (sl < C::NR) out[sl] = acc[q];
+  }
+  if (tid <= C::H) {
+    out[C::NR + 2 * tid] = a0;
+    out[C::NR + 2 * tid + 1] = an;
+  }
+}
+
+template <class C>
+__global__ __launch_bounds__(kT) void fwd_fft_finish_c(const float2* __restrict__ part,
+                                                       float* __restrict__ v, FftShape s,
+                                                       int view0, int nvb) {
+  extern __shared__ float2 sm2[];
+  const Lds<C> m(sm2);
+  const int lb = blockIdx.x, l = view0 + lb, tid = threadIdx.x;
+  m.setup();
+  for (int q = tid; q < C::NR; q += kT) {
+    float2 a = make_float2(0.f, 0.f);
+    for (int c = 0; c < s.nchunk; ++c) a = cadd(a, part[((size_t)c * nvb + lb) * C::NS + q]);
+    m.A[C::slot(q)] = a;
+  }
+  for (int zq = tid; zq <= C::H; zq += kT) {
+    float2 a0 = make_float2(0.f, 0.f), an = make_float2(0.f, 0.f);
+    for (int c = 0; c < s.nchunk; ++c) {
+      const float2* src = part + ((size_t)c * nvb + lb) * C::NS + C::NR + 2 * zq;
+      a0 = cadd(a0, src[0]);
+      an = cadd(an, src[1]);
+    }
+    pack_col0<C>(m.A, zq, a0, an);
+  }
+  __syncthreads();
+  fft2_inv<C>(m.A, m.twx, m.twz);
+  const float rnx = 1.0f / (float)s.nx;
+  for (int e = tid; e < s.nz * s.nx; e += kT) {
+    const int k = fdiv(e, rnx), i = e - k * s.nx;
+    v[((size_t)l * s.nz + k) * s.nx + i] = plane_at<C>(m.A, k + 2 * s.hb, i + 2 * s.ha);
+  }
+}
+
+template <class C>
+__global__ __launch_bounds__(kT) void back_fft_prep_c(const float* __restrict__ v,
+                                                      float2* __restrict__ V, FftShape s,
+                                                      int view0) {
+  extern __shared__ float2 sm2[];
+  const Lds<C> m(sm2);
+  const int lb = blockIdx.x, l = view0 + lb;
+  m.setup();
+  const float* vl = v + (size_t)l * s.nz * s.nx;
+  for (int e = threadIdx.x; e < C::H * C::Lx; e += kT) {
+    const int r = e / C::Lx, cc = e - r * C::Lx;
+    const int i = cc - 2 * s.ha, k1 = r - 2 * s.hb, k2 = r + C::H - 2 * s.hb;
+    const bool in_i = i >= 0 && i < s.nx;
+    const float lo = (in_i && k1 >= 0 && k1 < s.nz) ? vl[k1 * s.nx + i] : 0.0f;
+    const float hi = (in_i && k2 >= 0 && k2 < s.nz) ? vl[k2 * s.nx + i] : 0.0f;
+    m.A[r * C::ST + cc] = make_float2(lo, hi);
+  }
+  __syncthreads();
+  fft2_fwd<C>(m.A, m.twx, m.twz, [] {});
+  store_slots<C>(m.A, V + (size_t)lb * C::NS, 1.0f);
+}
+
+template <class C>
+__global__ __launch_bounds__(kT) void conv_back_fft_c(const float2* __restrict__ V,
+                                                      const float2* __restrict__ P,
+                                                      float* __restrict__ U, FftShape s, int view0,
+                                                      int nvb) {
+  extern __shared__ float2 sm2[];
+  const Lds<C> m(sm2);
+  const int c = blockIdx.x % s.nchunk_back, lb = blockIdx.x / s.nchunk_back, l = view0 + lb;
+  int j0, j1;
+  chunk_range(c, s.nchunk_back, s.ny, j0, j1);
+  m.setup();
+  const int tid = threadIdx.x, nx = s.nx, nz = s.nz;
+  const float2* Vl = V + (size_t)lb * C::NS;
+  float2 vr[C::KS], v0 = make_float2(0.f, 0.f), vn = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int q = 0; q < C::KS; ++q) {
+    const int sl = tid + q * kT;
+    if (sl < C::NR) vr[q] = Vl[sl];
+  }
+  if (tid <= C::H) {
+    v0 = Vl[C::NR + 2 * tid];
+    vn = Vl[C::NR + 2 * tid + 1];
+  }
+  const size_t rs = (size_t)s.ny * nx;
+  float* Ul = U + (size_t)lb * nz * rs;
+  float2 pr[C::KS], p0 = make_float2(0.f, 0.f), pn = make_float2(0.f, 0.f);
+  auto load_p = [&](int j) {
+    const float2* Pj = P + ((size_t)l * s.ny + j) * C::NS;
+#pragma unroll
+    for (int q = 0; q < C::KS; ++q) {
+      const int sl = tid + q * kT;
+      if (sl < C::NR) pr[q] = Pj[sl];
+    }
+    if (tid <= C::H) {
+      p0 = Pj[C::NR + 2 * tid];
+      pn = Pj[C::NR + 2 * tid + 1];
+    }
+  };
+  if (j0 < j1) load_p(j0);
+  for (int j = j0; j < j1; ++j) {
+    __syncthreads();                               // A and the folded plane free
+#pragma unroll
+    for (int q = 0; q < C::KS; ++q) {
+      const int sl = tid + q * kT;
+      if (sl < C::NR) m.A[C::slot(sl)] = cmulc(vr[q], pr[q]);
+    }
+    if (tid <= C::H) pack_col0<C>(m.A, tid, cmulc(v0, p0), cmulc(vn, pn));
+    __syncthreads();
+    if (j + 1 < j1) load_p(j + 1);                 // the next plane's spectrum, during this one
+    fft2_inv<C>(m.A, m.twx, m.twz);
+    fold_store(m.A, m.extra, nx, nz, s.ha, s.hb, Ul + (size_t)j * nx, rs,
+               [](const float2* A, int k, int c) { return plane_at<C>(A, k, c); }, kT);
+  }
+}
+
+hipError_t set_smem(const void* fn, size_t sm) {
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+}
+
+template <class C>
+hipError_t launch_c(const Plan& p, int which, const void* in, void* out, int view0, int nvb,
+                    hipStream_t st) {
+  const FftShape& s = p.fft;
+  char* ws = p.ws;
+  const float2* P = reinterpret_cast<const float2*>(ws + p.lay.fft_spectra);
+  float2* part = reinterpret_cast<float2*>(ws + p.lay.fft_part);
+  float2* V = reinterpret_cast<float2*>(ws + p.lay.fft_vproj);
+  hipError_t e = hipSuccess;
+  switch (which) {
+    case kFftSpectra: {
+      const size_t sm = smem_bytes<C>(0);
+      if ((e = set_smem((const void*)psf_spectra_c<C>, sm)) != hipSuccess) return e;
+      hipLaunchKernelGGL(psf_spectra_c<C>, dim3((unsigned)(p.g.nview * p.g.ny)), dim3(kT), sm, st,
+                         p.psf, reinterpret_cast<float2*>(ws + p.lay.fft_spectra), s);
+      break;
+    }
+    case kFftForward: {
+      const size_t sm = smem_bytes<C>(s.nz * s.nx);
+      if ((e = set_smem((const void*)conv_fwd_fft_c<C>, sm)) != hipSuccess) return e;
+      hipLaunchKernelGGL(conv_fwd_fft_c<C>, dim3((unsigned)(nvb * s.nchunk)), dim3(kT), sm, st,
+                         static_cast<const float*>(in), P, part, s, view0, nvb);
+      break;
+    }
+    case kFftFinish: {
+      const size_t sm = smem_bytes<C>(0);
+      if ((e = set_smem((const void*)fwd_fft_finish_c<C>, sm)) != hipSuccess) return e;
+      hipLaunchKernelGGL(fwd_fft_finish_c<C>, dim3((unsigned)nvb), dim3(kT), sm, st, part,
+                         static_cast<float*>(out), s, view0, nvb);
+      break;
+    }
+    case kFftBackPrep: {
+      const size_t sm = smem_bytes<C>(0);
+      if ((e = set_smem((const void*)back_fft_prep_c<C>, sm)) != hipSuccess) return e;
+      hipLaunchKernelGGL(back_fft_prep_c<C>, dim3((unsigned)nvb), dim3(kT), sm, st,
+                         static_cast<const float*>(in), V, s, view0);
+      break;
+    }
+    case kFftBack: {
+      const size_t sm = smem_bytes<C>((s.nz + 2 * s.hb) * s.nx);
+      if ((e = set_smem((const void*)conv_back_fft_c<C>, sm)) != hipSuccess) return e;
+      hipLaunchKernelGGL(conv_back_fft_c<C>, dim3((unsigned)(nvb * s.nchunk_back)), dim3(kT), sm,
+                         st, V, P, static_cast<float*>(out), s, view0, nvb);
+      break;
+    }
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <class C>
+bool fits(const FftShape& s) {
+  return s.Lx == C::Lx && s.Lz == C::Lz && s.nz * s.nx <= 16384 &&
+         smem_bytes<C>(s.nz * s.nx) <= kLdsBytes &&
+         smem_bytes<C>((s.nz + 2 * s.hb) * s.nx) <= kLdsBytes;
+}
+
+}  // namespace
+
+int fft_fixed_config(const FftShape& s) {
+  if (fits<Cfg180x120>(s)) return 1;
+  if (fits<Cfg90x60>(s)) return 2;
+  return 0;
+}
+
+hipError_t launch_fft_fixed(const Plan& p, int which, const void* in, void* out, int view0, int nvb,
+                            hipStream_t st) {
+  switch (p.fft.cfg) {
+    case 1: return launch_c<Cfg180x120>(p, which, in, out, view0, nvb, st);
+    case 2: return launch_c<Cfg90x60>(p, which, in, out, view0, nvb, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace spect

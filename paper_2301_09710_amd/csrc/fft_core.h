@@ -1,0 +1,254 @@
+// Building blocks of the FFT convolution kernels (conv_fft.hip,
+// conv_fft_fixed.hip): complex arithmetic, R-point DFTs in registers for
+// R = 2, 3, 4, 5 and the composites 6, 8, 9, 10, 12, 15, and the stage
+// twiddles of one in-place pass.  Device code only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+#include <utility>
+
+namespace spect {
+namespace fft {
+
+// q / d and q mod d for 0 <= q < 2^16 and 1 <= d < 2^16 through the FP32
+// reciprocal rd = 1 / d: (q + 1/2) / d lies at least 1 / (2 d) from an
+// integer, and the rounding error of (q + 1/2) rd is below 2^-22 (q + 1/2) / d,
+// far less.
+__device__ __forceinline__ int fdiv(int q, float rd) { return (int)(((float)q + 0.5f) * rd); }
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// i s a
+__device__ __forceinline__ float2 cimul(float2 a, float s) { return make_float2(-s * a.y, s * a.x); }
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+
+// R-point DFT in place, X[m] = sum_r v[r] exp(sg 2 pi i r m / R), sg = -1
+// (forward) or +1 (inverse).
+template <int R, bool kInv>
+__device__ __forceinline__ void dft(float2 (&v)[R]) {
+  constexpr float sg = kInv ? 1.0f : -1.0f;
+  if constexpr (R == 2) {
+    const float2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  } else if constexpr (R == 3) {
+    const float h = 0.86602540378443864676f;   // sin(2 pi / 3)
+    const float2 s = cadd(v[1], v[2]), d = csub(v[1], v[2]);
+    const float2 t = make_float2(v[0].x - 0.5f * s.x, v[0].y - 0.5f * s.y);
+    const float2 u = cimul(d, sg * h);
+    v[0] = cadd(v[0], s);
+    v[1] = cadd(t, u);
+    v[2] = csub(t, u);
+  } else if constexpr (R == 4) {
+    const float2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+    const float2 c = cadd(v[1], v[3]), d = cimul(csub(v[1], v[3]), sg);
+    v[0] = cadd(a, c);
+    v[2] = csub(a, c);
+    v[1] = cadd(b, d);
+    v[3] = csub(b, d);
+  } else {
+    static_assert(R == 5, "radix 2, 3, 4 or 5");
+    const float c1 = 0.30901699437494742410f;    // cos(2 pi / 5)
+    const float c2 = -0.80901699437494742410f;   // cos(4 pi / 5)
+    const float s1 = 0.95105651629515357212f;    // sin(2 pi / 5)
+    const float s2 = 0.58778525229247312917f;    // sin(4 pi / 5)
+    const float2 a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+    const float2 a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+    const float2 x0 = v[0];
+    const float2 r1 = make_float2(x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y);
+    const float2 r2 = make_float2(x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y);
+    const float2 i1 = cimul(make_float2(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y), sg);
+    const float2 i2 = cimul(make_float2(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y), sg);
+    v[0] = cadd(x0, cadd(a1, a2));
+    v[1] = cadd(r1, i1);
+    v[4] = csub(r1, i1);
+    v[2] = cadd(r2, i2);
+    v[3] = csub(r2, i2);
+  }
+}
+
+// Index tables of one plan's transforms (in LDS):
+//   posx[f], posz[q]: where frequency f (q) of a transform along x (z) sits
+//     after the in-place decimation-in-frequency passes (mixed-radix digit
+//     reversal);
+//   vc1[v], vc2[v]: the columns of virtual column v (x frequency f < Lx/2) in
+//     the first and the second half of the row pairs, in increasing vc1; v = 0
+//     is frequency 0 (with Lx/2 in the second half: the two real columns).
+struct Tabs {
+  const int* posx;
+  const int* posz;
+  const int* vc1;
+  const int* vc2;
+};
+
+// Twiddle constants of the composite radices, evaluated at compile time
+// (Taylor series in FP64 on [-pi, pi]).
+constexpr double kTwoPi = 6.28318530717958647692528676655900577;
+constexpr double csin(double x) {
+  while (x > kTwoPi / 2) x -= kTwoPi;
+  while (x < -kTwoPi / 2) x += kTwoPi;
+  double term = x, sum = x;
+  for (int n = 1; n < 30; ++n) {
+    term *= -x * x / ((2.0 * n) * (2.0 * n + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double ccos(double x) { return csin(x + kTwoPi / 4); }
+
+template <class F, int... I>
+__device__ __forceinline__ void unroll_seq(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>()), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void unroll(F&& f) {
+  unroll_seq(f, std::make_integer_sequence<int, N>());
+}
+
+// Factors of the composite radices: R = Ra Rb.
+template <int R> struct Split;
+template <> struct Split<6> { static constexpr int a = 2, b = 3; };
+template <> struct Split<8> { static constexpr int a = 2, b = 4; };
+template <> struct Split<9> { static constexpr int a = 3, b = 3; };
+template <> struct Split<10> { static constexpr int a = 2, b = 5; };
+template <> struct Split<12> { static constexpr int a = 3, b = 4; };
+template <> struct Split<15> { static constexpr int a = 3, b = 5; };
+
+template <int R, bool kInv>
+__device__ __forceinline__ void dft_any(float2 (&v)[R]);
+
+// R-point DFT for R = Ra Rb in registers (Cooley-Tukey): input n = Rb n1 + n2,
+// Ra-point DFTs over n1, twiddles exp(sg 2 pi i n2 k1 / R), Rb-point DFTs over
+// n2, output k = k1 + Ra k2 (natural order).
+template <int Ra, int Rb, bool kInv>
+__device__ __forceinline__ void dft_comp(float2 (&v)[Ra * Rb]) {
+  constexpr int R = Ra * Rb;
+  constexpr double sg = kInv ? 1.0 : -1.0;
+  float2 y[Ra][Rb];
+  unroll<Rb>([&](auto n2c) {
+    constexpr int n2 = decltype(n2c)::value;
+    float2 t[Ra];
+    unroll<Ra>([&](auto n1c) { t[decltype(n1c)::value] = v[Rb * decltype(n1c)::value + n2]; });
+    dft_any<Ra, kInv>(t);
+    unroll<Ra>([&](auto k1c) {
+      constexpr int k1 = decltype(k1c)::value;
+      constexpr int e = (n2 * k1) % R;
+      if constexpr (e == 0) {
+        y[k1][n2] = t[k1];
+      } else {
+        constexpr float c = (float)ccos(kTwoPi * e / R);
+        constexpr float sn = (float)csin(sg * kTwoPi * e / R);
+        y[k1][n2] = cmul(t[k1], make_float2(c, sn));
+      }
+    });
+  });
+  unroll<Ra>([&](auto k1c) {
+    constexpr int k1 = decltype(k1c)::value;
+    float2 t[Rb];
+    unroll<Rb>([&](auto n2c) { t[decltype(n2c)::value] = y[k1][decltype(n2c)::value]; });
+    dft_any<Rb, kInv>(t);
+    unroll<Rb>([&](auto k2c) { v[k1 + Ra * decltype(k2c)::value] = t[decltype(k2c)::value]; });
+  });
+}
+
+template <int R, bool kInv>
+__device__ __forceinline__ void dft_any(float2 (&v)[R]) {
+  if constexpr (R <= 5) dft<R, kInv>(v);
+  else dft_comp<Split<R>::a, Split<R>::b, kInv>(v);
+}
+
+// Element t of transform b: rows (b = row pair, along x) or virtual columns
+// (b = virtual column, along z).
+struct RowAddr {
+  int stride;
+  __device__ __forceinline__ int operator()(int b, int t) const { return b * stride + t; }
+};
+struct ColAddr {
+  int stride, H;
+  const int* vc1;
+  const int* vc2;
+  __device__ __forceinline__ int operator()(int b, int t) const {
+    return t < H ? t * stride + vc1[b] : (t - H) * stride + vc2[b];
+  }
+};
+
+// Stage twiddles w[r] = tw[r d] = exp(-2 pi i r d / N) for r < R (w[0] unused).
+// For R = Ra Rb, r = k1 + Ra k2: w[r] = tw[k1 d] tw[Ra k2 d], Ra + Rb - 2
+// table reads instead of R - 1 (one more FP32 rounding per twiddle).
+template <int R>
+__device__ __forceinline__ void stage_twiddles(float2 (&w)[R], const float2* tw, int d) {
+  if constexpr (R <= 5) {
+#pragma unroll
+    for (int r = 1; r < R; ++r) w[r] = tw[r * d];
+  } else {
+    constexpr int Ra = Split<R>::a, Rb = Split<R>::b;
+    float2 ta[Ra], tb[Rb];
+#pragma unroll
+    for (int k1 = 1; k1 < Ra; ++k1) ta[k1] = tw[k1 * d];
+#pragma unroll
+    for (int k2 = 1; k2 < Rb; ++k2) tb[k2] = tw[Ra * k2 * d];
+#pragma unroll
+    for (int k2 = 0; k2 < Rb; ++k2)
+#pragma unroll
+      for (int k1 = 0; k1 < Ra; ++k1) {
+        const int r = k1 + Ra * k2;
+        if (r == 0) continue;
+        w[r] = k2 == 0 ? ta[k1] : (k1 == 0 ? tb[k2] : cmul(ta[k1], tb[k2]));
+      }
+  }
+}
+
+
+// The adjoint of replicate padding on one inverse-transformed plane:
+// u[k][i] = sum of the padded plane g over the padded rows that clamp onto k
+// and the padded columns that clamp onto i, written to out[k * rs + i].
+// Columns first (into `fold`, (nz + 2 hb) x nx floats), then rows; the edge
+// sums (ha + 1 or hb + 1 terms) run on lanes of their own so that no wave
+// waits on one long sum.
+template <class G>
+__device__ __forceinline__ void fold_store(const float2* A, float* fold, int nx, int nz, int ha,
+                                           int hb, float* out, size_t rs, G&& g, int T) {
+  const int KZ = nz + 2 * hb;
+  const int inner_x = nx > 2 ? nx - 2 : 0, edges_x = nx > 1 ? 2 : 1;
+  for (int e = threadIdx.x; e < KZ * inner_x; e += T) {
+    const int zz = e / inner_x, i = 1 + e - zz * inner_x;
+    fold[zz * nx + i] = g(A, zz, i + ha);
+  }
+  for (int e = threadIdx.x; e < KZ * edges_x; e += T) {
+    const int zz = e / edges_x, side = e - zz * edges_x;
+    const int i = side ? nx - 1 : 0;
+    const int xl = side ? nx - 1 + ha : 0;
+    const int xh = (side || nx == 1) ? nx - 1 + 2 * ha : ha;
+    float a = 0.0f;
+    for (int xx = xl; xx <= xh; ++xx) a += g(A, zz, xx);
+    fold[zz * nx + i] = a;
+  }
+  __syncthreads();
+  const int inner_z = nz > 2 ? nz - 2 : 0, edges_z = nz > 1 ? 2 : 1;
+  for (int e = threadIdx.x; e < inner_z * nx; e += T) {
+    const int k = 1 + e / nx, i = e - (k - 1) * nx;
+    out[(size_t)k * rs + i] = fold[(k + hb) * nx + i];
+  }
+  for (int e = threadIdx.x; e < edges_z * nx; e += T) {
+    const int side = e / nx, i = e - side * nx;
+    const int k = side ? nz - 1 : 0;
+    const int zl = side ? nz - 1 + hb : 0;
+    const int zh = (side || nz == 1) ? nz - 1 + 2 * hb : hb;
+    float a = 0.0f;
+    for (int zz = zl; zz <= zh; ++zz) a += fold[zz * nx + i];
+    out[(size_t)k * rs + i] = a;
+  }
+}
+
+}  // namespace fft
+}  // namespace spect

@@ -97,8 +97,11 @@ struct FftShape {
   int NR, NS;             // regular spectrum slots, all slots (complex) per plane
   float r_lx, r_lh, r_lh1, r_nx;  // 1 / Lx, 1 / Lh, 1 / (Lh - 1), 1 / nx
   int nchunk, nchunk_back;
+  int cfg;                // transform sizes fixed at compile time (conv_fft_fixed.hip), 0: none
   bool ok;                // fits the kernels' registers and LDS
 };
+// The FFT convolution's kernels (launch_fft_fixed's `which`).
+enum FftKernel { kFftSpectra = 0, kFftForward, kFftFinish, kFftBackPrep, kFftBack };
 
 // Per-view geometry tables, on the device (inside the workspace).
 //   quarter[l]             : m, number of quarter turns (0..3)
@@ -323,6 +326,10 @@ hipError_t launch_add(float* a, const float* b, size_t n, hipStream_t s);
 hipError_t launch_em_reg_update(float* x, const float* e, const float* sens, const float* u,
                                 float beta, size_t n, hipStream_t s);
 FftShape make_fft_shape(const spect_geom& g);
+// Which compile-time configuration holds these transform sizes (0: none).
+int fft_fixed_config(const FftShape& s);
+hipError_t launch_fft_fixed(const Plan& p, int which, const void* in, void* out, int view0, int nvb,
+                            hipStream_t s);
 void tune_fft_chunks(FftShape& s, int views);
 hipError_t launch_fft_psf_spectra(const Plan& p, hipStream_t s);
 hipError_t launch_conv_fwd_fft(const Plan& p, const float* W, int view0, int nvb, hipStream_t s);
