@@ -739,7 +739,7 @@ void tune_fft_chunks(FftShape& s, int views) {
       nb < 1)
     nb = 1;
   s.nchunk = fft_pick_chunks(s.ny, views, (long long)cus * nb, false);
-  s.nchunk_back = fft_pick_chunks(s.ny, views, (long long)cus * nb, true);
+  s.nchunk_back = fft_pick_chunks(s.ny, views, (long long)cus * nb, false);
 }
 
 hipError_t launch_fft_psf_spectra(const Plan& p, hipStream_t st) {

@@ -25,16 +25,16 @@ namespace {
 
 using namespace fft;
 
-constexpr int kT = 512;
 
-template <int LX, int LZ, int RX0, int RX1, int RZ0, int RZ1>
+template <int LX, int LZ, int RX0, int RX1, int RZ0, int RZ1, int THREADS>
 struct Cfg {
+  static constexpr int T = THREADS;
   static constexpr int Lx = LX, Lz = LZ, Lh = LX / 2, H = LZ / 2, ST = LX + 1;
   static constexpr int Rx0 = RX0, Rx1 = RX1, Rz0 = RZ0, Rz1 = RZ1;
   static constexpr int Sx = LX / RX0, Sz = LZ / RZ0;
   static constexpr int HR = RX1 / 2;               // also the column of frequency Lx/2
   static constexpr int NR = H * (LX - 2), NS = NR + 2 * (H + 1);
-  static constexpr int KS = (NR + kT - 1) / kT;
+  static constexpr int KS = (NR + T - 1) / T;
   static_assert(RX0 * RX1 == LX && RZ0 * RZ1 == LZ && RX1 % 2 == 0 && LZ % 2 == 0, "config");
   __device__ static int posx(int f) { return (f % RX0) * Sx + f / RX0; }
   __device__ static int posz(int q) { return (q % RZ0) * Sz + q / RZ0; }
@@ -55,12 +55,15 @@ struct Cfg {
   }
 };
 
-// C2 workload planes (128 x 80, 37 x 37 PSF) and the 64 x 40 / 19 x 19 serving planes.
-using Cfg180x120 = Cfg<180, 120, 15, 12, 12, 10>;
-using Cfg90x60 = Cfg<90, 60, 9, 10, 10, 6>;
+// C2 workload planes (128 x 80, 37 x 37 PSF) and the 64 x 40 / 19 x 19 serving
+// planes; the adjoint keeps two spectra per thread in registers (the view's
+// projection and the next plane's PSF), so it runs 512 threads, the others 1024.
+template <int T> using Cfg180x120 = Cfg<180, 120, 15, 12, 12, 10, T>;
+template <int T> using Cfg90x60 = Cfg<90, 60, 9, 10, 10, 6, T>;
 
+template <int T>
 __device__ __forceinline__ void init_tw(float2* tw, int N) {
-  for (int t = threadIdx.x; t < N; t += kT) {
+  for (int t = threadIdx.x; t < N; t += T) {
     double sn, cs;
     sincospi(-2.0 * (double)t / (double)N, &sn, &cs);
     tw[t] = make_float2((float)cs, (float)sn);
@@ -79,7 +82,7 @@ __device__ __forceinline__ void pass(float2* A, const float2* tw) {
   constexpr int S = Ns / R, Nb = N / R, B = batch * Nb, step = N / Ns;
   constexpr bool tmajor = S < 16;
 #pragma unroll 1
-  for (int b = threadIdx.x; b < B; b += kT) {
+  for (int b = threadIdx.x; b < B; b += C::T) {
     int tb, j;
     if (tmajor) { j = b / batch; tb = b - j * batch; }
     else { tb = b / Nb; j = b - tb * Nb; }
@@ -118,7 +121,7 @@ __device__ __forceinline__ void pass(float2* A, const float2* tw) {
 // unpack_rows in conv_fft.hip); lanes take consecutive row pairs.
 template <class C>
 __device__ __forceinline__ void unpack_rows(float2* A) {
-  for (int e = threadIdx.x; e < C::H * C::Lh; e += kT) {
+  for (int e = threadIdx.x; e < C::H * C::Lh; e += C::T) {
     const int f = e / C::H, p = e - f * C::H;
     float2* row = A + p * C::ST;
     if (f == 0) {
@@ -137,7 +140,7 @@ __device__ __forceinline__ void unpack_rows(float2* A) {
 
 template <class C>
 __device__ __forceinline__ void repack_rows(float2* A) {
-  for (int e = threadIdx.x; e < C::H * C::Lh; e += kT) {
+  for (int e = threadIdx.x; e < C::H * C::Lh; e += C::T) {
     const int f = e / C::H, p = e - f * C::H;
     float2* row = A + p * C::ST;
     if (f == 0) {
@@ -199,8 +202,8 @@ __device__ __forceinline__ void pack_col0(float2* A, int zq, float2 x0, float2 x
 
 template <class C>
 __device__ __forceinline__ void store_slots(const float2* A, float2* out, float scale) {
-  for (int q = threadIdx.x; q < C::NR; q += kT) out[q] = cscale(A[C::slot(q)], scale);
-  for (int zq = threadIdx.x; zq <= C::H; zq += kT) {
+  for (int q = threadIdx.x; q < C::NR; q += C::T) out[q] = cscale(A[C::slot(q)], scale);
+  for (int zq = threadIdx.x; zq <= C::H; zq += C::T) {
     float2 x0, xn;
     unpack_col0<C>(A, zq, &x0, &xn);
     out[C::NR + 2 * zq] = cscale(x0, scale);
@@ -230,8 +233,8 @@ struct Lds {
     extra = reinterpret_cast<float*>(twz + C::Lz);
   }
   __device__ void setup() const {
-    init_tw(twx, C::Lx);
-    init_tw(twz, C::Lz);
+    init_tw<C::T>(twx, C::Lx);
+    init_tw<C::T>(twz, C::Lz);
   }
 };
 
@@ -243,14 +246,14 @@ constexpr size_t smem_bytes(int extra_floats) {
 // ---------------------------------------------------------------- kernels
 
 template <class C>
-__global__ __launch_bounds__(kT) void psf_spectra_c(const float* __restrict__ psf,
+__global__ __launch_bounds__(C::T) void psf_spectra_c(const float* __restrict__ psf,
                                                     float2* __restrict__ P, FftShape s) {
   extern __shared__ float2 sm2[];
   const Lds<C> m(sm2);
   const int jl = blockIdx.x;
   const float* p = psf + (size_t)jl * s.pz * s.px;
   m.setup();
-  for (int e = threadIdx.x; e < C::H * C::Lx; e += kT) {
+  for (int e = threadIdx.x; e < C::H * C::Lx; e += C::T) {
     const int r = e / C::Lx, c = e - r * C::Lx;
     const float lo = (r < s.pz && c < s.px) ? p[r * s.px + c] : 0.0f;
     const float hi = (r + C::H < s.pz && c < s.px) ? p[(r + C::H) * s.px + c] : 0.0f;
@@ -262,7 +265,7 @@ __global__ __launch_bounds__(kT) void psf_spectra_c(const float* __restrict__ ps
 }
 
 template <class C>
-__global__ __launch_bounds__(kT) void conv_fwd_fft_c(const float* __restrict__ W,
+__global__ __launch_bounds__(C::T) void conv_fwd_fft_c(const float* __restrict__ W,
                                                      const float2* __restrict__ P,
                                                      float2* __restrict__ part, FftShape s,
                                                      int view0, int nvb) {
@@ -279,17 +282,30 @@ __global__ __launch_bounds__(kT) void conv_fwd_fft_c(const float* __restrict__ W
   float2 acc[C::KS], a0 = make_float2(0.f, 0.f), an = make_float2(0.f, 0.f);
 #pragma unroll
   for (int q = 0; q < C::KS; ++q) acc[q] = make_float2(0.f, 0.f);
+  constexpr int kStageGroups = C::T / C::Lx;                   // threads per column
+  constexpr int kStageRows = (C::H + kStageGroups - 1) / kStageGroups;
   // plane j of W straight into the raw LDS region (lane L of a wave writes
   // the wave's base + 4 L bytes: 64 consecutive elements of the [nz][nx] plane)
   auto load_plane = [&](int j) {
     const int lane = tid & 63, wbase = tid - lane;
-    for (int e0 = wbase; e0 < plane; e0 += kT) {
-      const int e = e0 + lane;
-      if (e < plane) {
-        const int k = fdiv(e, rnx), i = e - k * nx;
-        __builtin_amdgcn_global_load_lds(Wl + (size_t)k * rs + (size_t)j * nx + i,
+    if (nx % 64 == 0) {
+      // each wave's 64 elements lie in one row: row and column offsets are uniform
+      for (int e0 = wbase; e0 < plane; e0 += C::T) {
+        const int k = __builtin_amdgcn_readfirstlane(e0 / nx);
+        const int i0 = __builtin_amdgcn_readfirstlane(e0 - k * nx);
+        __builtin_amdgcn_global_load_lds(Wl + (size_t)k * rs + (size_t)j * nx + i0 + lane,
                                          (__attribute__((address_space(3))) void*)(m.extra + e0),
                                          4, 0, 0);
+      }
+    } else {
+      for (int e0 = wbase; e0 < plane; e0 += C::T) {
+        const int e = e0 + lane;
+        if (e < plane) {
+          const int k = fdiv(e, rnx), i = e - k * nx;
+          __builtin_amdgcn_global_load_lds(Wl + (size_t)k * rs + (size_t)j * nx + i,
+                                           (__attribute__((address_space(3))) void*)(m.extra + e0),
+                                           4, 0, 0);
+        }
       }
     }
   };
@@ -301,7 +317,7 @@ __global__ __launch_bounds__(kT) void conv_fwd_fft_c(const float* __restrict__ W
     auto load_p = [&] {
 #pragma unroll
       for (int q = 0; q < C::KS; ++q) {
-        const int sl = tid + q * kT;
+        const int sl = tid + q * C::T;
         if (sl < C::NR) pr[q] = Pj[sl];
       }
       if (tid <= C::H) {
@@ -311,22 +327,28 @@ __global__ __launch_bounds__(kT) void conv_fwd_fft_c(const float* __restrict__ W
     };
     __builtin_amdgcn_s_waitcnt(0);                 // this plane's loads into raw landed
     __syncthreads();                               // raw complete, A free, twiddles ready
-    for (int e = tid; e < C::H * C::Lx; e += kT) {
-      const int r = e / C::Lx, cc = e - r * C::Lx;
-      float lo = 0.0f, hi = 0.0f;
-      if (cc < IX) {
-        const int ii = clampi(cc - s.ha, 0, nx - 1);
-        if (r < KZ) lo = m.extra[clampi(r - s.hb, 0, nz - 1) * nx + ii];
-        if (r + C::H < KZ) hi = m.extra[clampi(r + C::H - s.hb, 0, nz - 1) * nx + ii];
+    // lanes on consecutive columns; each thread one column and a run of rows
+    if (tid < kStageGroups * C::Lx) {
+      const int cc = tid % C::Lx, grp = tid / C::Lx;
+      const int ii = clampi(cc - s.ha, 0, nx - 1);
+      const bool in_col = cc < IX;
+      const int r0 = grp * kStageRows, r1 = min(r0 + kStageRows, C::H);
+#pragma unroll 2
+      for (int r = r0; r < r1; ++r) {
+        float lo = 0.0f, hi = 0.0f;
+        if (in_col) {
+          if (r < KZ) lo = m.extra[clampi(r - s.hb, 0, nz - 1) * nx + ii];
+          if (r + C::H < KZ) hi = m.extra[clampi(r + C::H - s.hb, 0, nz - 1) * nx + ii];
+        }
+        m.A[r * C::ST + cc] = make_float2(lo, hi);
       }
-      m.A[r * C::ST + cc] = make_float2(lo, hi);
     }
     __syncthreads();                               // raw consumed
     if (j + 1 < j1) load_plane(j + 1);
     fft2_fwd<C>(m.A, m.twx, m.twz, load_p);
 #pragma unroll
     for (int q = 0; q < C::KS; ++q) {
-      const int sl = tid + q * kT;
+      const int sl = tid + q * C::T;
       if (sl < C::NR) {
         const float2 f = m.A[C::slot(sl)];
         acc[q].x += pr[q].x * f.x - pr[q].y * f.y;
@@ -343,7 +365,7 @@ __global__ __launch_bounds__(kT) void conv_fwd_fft_c(const float* __restrict__ W
   float2* out = part + ((size_t)c * nvb + lb) * C::NS;
 #pragma unroll
   for (int q = 0; q < C::KS; ++q) {
-    const int sl = tid + q * kT;
+    const int sl = tid + q * C::T;
     if (sl < C::NR) out[sl] = acc[q];
   }
   if (tid <= C::H) {
@@ -353,19 +375,19 @@ __global__ __launch_bounds__(kT) void conv_fwd_fft_c(const float* __restrict__ W
 }
 
 template <class C>
-__global__ __launch_bounds__(kT) void fwd_fft_finish_c(const float2* __restrict__ part,
+__global__ __launch_bounds__(C::T) void fwd_fft_finish_c(const float2* __restrict__ part,
                                                        float* __restrict__ v, FftShape s,
                                                        int view0, int nvb) {
   extern __shared__ float2 sm2[];
   const Lds<C> m(sm2);
   const int lb = blockIdx.x, l = view0 + lb, tid = threadIdx.x;
   m.setup();
-  for (int q = tid; q < C::NR; q += kT) {
+  for (int q = tid; q < C::NR; q += C::T) {
     float2 a = make_float2(0.f, 0.f);
     for (int c = 0; c < s.nchunk; ++c) a = cadd(a, part[((size_t)c * nvb + lb) * C::NS + q]);
     m.A[C::slot(q)] = a;
   }
-  for (int zq = tid; zq <= C::H; zq += kT) {
+  for (int zq = tid; zq <= C::H; zq += C::T) {
     float2 a0 = make_float2(0.f, 0.f), an = make_float2(0.f, 0.f);
     for (int c = 0; c < s.nchunk; ++c) {
       const float2* src = part + ((size_t)c * nvb + lb) * C::NS + C::NR + 2 * zq;
@@ -377,14 +399,14 @@ __global__ __launch_bounds__(kT) void fwd_fft_finish_c(const float2* __restrict_
   __syncthreads();
   fft2_inv<C>(m.A, m.twx, m.twz);
   const float rnx = 1.0f / (float)s.nx;
-  for (int e = tid; e < s.nz * s.nx; e += kT) {
+  for (int e = tid; e < s.nz * s.nx; e += C::T) {
     const int k = fdiv(e, rnx), i = e - k * s.nx;
     v[((size_t)l * s.nz + k) * s.nx + i] = plane_at<C>(m.A, k + 2 * s.hb, i + 2 * s.ha);
   }
 }
 
 template <class C>
-__global__ __launch_bounds__(kT) void back_fft_prep_c(const float* __restrict__ v,
+__global__ __launch_bounds__(C::T) void back_fft_prep_c(const float* __restrict__ v,
                                                       float2* __restrict__ V, FftShape s,
                                                       int view0) {
   extern __shared__ float2 sm2[];
@@ -392,7 +414,7 @@ __global__ __launch_bounds__(kT) void back_fft_prep_c(const float* __restrict__ 
   const int lb = blockIdx.x, l = view0 + lb;
   m.setup();
   const float* vl = v + (size_t)l * s.nz * s.nx;
-  for (int e = threadIdx.x; e < C::H * C::Lx; e += kT) {
+  for (int e = threadIdx.x; e < C::H * C::Lx; e += C::T) {
     const int r = e / C::Lx, cc = e - r * C::Lx;
     const int i = cc - 2 * s.ha, k1 = r - 2 * s.hb, k2 = r + C::H - 2 * s.hb;
     const bool in_i = i >= 0 && i < s.nx;
@@ -406,7 +428,7 @@ __global__ __launch_bounds__(kT) void back_fft_prep_c(const float* __restrict__ 
 }
 
 template <class C>
-__global__ __launch_bounds__(kT) void conv_back_fft_c(const float2* __restrict__ V,
+__global__ __launch_bounds__(C::T) void conv_back_fft_c(const float2* __restrict__ V,
                                                       const float2* __restrict__ P,
                                                       float* __restrict__ U, FftShape s, int view0,
                                                       int nvb) {
@@ -417,11 +439,13 @@ __global__ __launch_bounds__(kT) void conv_back_fft_c(const float2* __restrict__
   chunk_range(c, s.nchunk_back, s.ny, j0, j1);
   m.setup();
   const int tid = threadIdx.x, nx = s.nx, nz = s.nz;
+  // the view's projection spectrum stays in registers; the PSF spectrum of
+  // the next plane is loaded into registers during this plane's transform
   const float2* Vl = V + (size_t)lb * C::NS;
   float2 vr[C::KS], v0 = make_float2(0.f, 0.f), vn = make_float2(0.f, 0.f);
 #pragma unroll
   for (int q = 0; q < C::KS; ++q) {
-    const int sl = tid + q * kT;
+    const int sl = tid + q * C::T;
     if (sl < C::NR) vr[q] = Vl[sl];
   }
   if (tid <= C::H) {
@@ -435,7 +459,7 @@ __global__ __launch_bounds__(kT) void conv_back_fft_c(const float2* __restrict__
     const float2* Pj = P + ((size_t)l * s.ny + j) * C::NS;
 #pragma unroll
     for (int q = 0; q < C::KS; ++q) {
-      const int sl = tid + q * kT;
+      const int sl = tid + q * C::T;
       if (sl < C::NR) pr[q] = Pj[sl];
     }
     if (tid <= C::H) {
@@ -448,7 +472,7 @@ __global__ __launch_bounds__(kT) void conv_back_fft_c(const float2* __restrict__
     __syncthreads();                               // A and the folded plane free
 #pragma unroll
     for (int q = 0; q < C::KS; ++q) {
-      const int sl = tid + q * kT;
+      const int sl = tid + q * C::T;
       if (sl < C::NR) m.A[C::slot(sl)] = cmulc(vr[q], pr[q]);
     }
     if (tid <= C::H) pack_col0<C>(m.A, tid, cmulc(v0, p0), cmulc(vn, pn));
@@ -456,7 +480,7 @@ __global__ __launch_bounds__(kT) void conv_back_fft_c(const float2* __restrict__
     if (j + 1 < j1) load_p(j + 1);                 // the next plane's spectrum, during this one
     fft2_inv<C>(m.A, m.twx, m.twz);
     fold_store(m.A, m.extra, nx, nz, s.ha, s.hb, Ul + (size_t)j * nx, rs,
-               [](const float2* A, int k, int c) { return plane_at<C>(A, k, c); }, kT);
+               [](const float2* A, int k, int c) { return plane_at<C>(A, k, c); }, C::T);
   }
 }
 
@@ -464,9 +488,11 @@ hipError_t set_smem(const void* fn, size_t sm) {
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
 }
 
-template <class C>
+template <template <int> class CF>
 hipError_t launch_c(const Plan& p, int which, const void* in, void* out, int view0, int nvb,
                     hipStream_t st) {
+  using CW = CF<1024>;   // transforms of one plane per workgroup pass
+  using CB = CF<512>;    // adjoint
   const FftShape& s = p.fft;
   char* ws = p.ws;
   const float2* P = reinterpret_cast<const float2*>(ws + p.lay.fft_spectra);
@@ -475,38 +501,38 @@ hipError_t launch_c(const Plan& p, int which, const void* in, void* out, int vie
   hipError_t e = hipSuccess;
   switch (which) {
     case kFftSpectra: {
-      const size_t sm = smem_bytes<C>(0);
-      if ((e = set_smem((const void*)psf_spectra_c<C>, sm)) != hipSuccess) return e;
-      hipLaunchKernelGGL(psf_spectra_c<C>, dim3((unsigned)(p.g.nview * p.g.ny)), dim3(kT), sm, st,
-                         p.psf, reinterpret_cast<float2*>(ws + p.lay.fft_spectra), s);
+      const size_t sm = smem_bytes<CW>(0);
+      if ((e = set_smem((const void*)psf_spectra_c<CW>, sm)) != hipSuccess) return e;
+      hipLaunchKernelGGL(psf_spectra_c<CW>, dim3((unsigned)(p.g.nview * p.g.ny)), dim3(CW::T), sm,
+                         st, p.psf, reinterpret_cast<float2*>(ws + p.lay.fft_spectra), s);
       break;
     }
     case kFftForward: {
-      const size_t sm = smem_bytes<C>(s.nz * s.nx);
-      if ((e = set_smem((const void*)conv_fwd_fft_c<C>, sm)) != hipSuccess) return e;
-      hipLaunchKernelGGL(conv_fwd_fft_c<C>, dim3((unsigned)(nvb * s.nchunk)), dim3(kT), sm, st,
+      const size_t sm = smem_bytes<CW>(s.nz * s.nx);
+      if ((e = set_smem((const void*)conv_fwd_fft_c<CW>, sm)) != hipSuccess) return e;
+      hipLaunchKernelGGL(conv_fwd_fft_c<CW>, dim3((unsigned)(nvb * s.nchunk)), dim3(CW::T), sm, st,
                          static_cast<const float*>(in), P, part, s, view0, nvb);
       break;
     }
     case kFftFinish: {
-      const size_t sm = smem_bytes<C>(0);
-      if ((e = set_smem((const void*)fwd_fft_finish_c<C>, sm)) != hipSuccess) return e;
-      hipLaunchKernelGGL(fwd_fft_finish_c<C>, dim3((unsigned)nvb), dim3(kT), sm, st, part,
+      const size_t sm = smem_bytes<CW>(0);
+      if ((e = set_smem((const void*)fwd_fft_finish_c<CW>, sm)) != hipSuccess) return e;
+      hipLaunchKernelGGL(fwd_fft_finish_c<CW>, dim3((unsigned)nvb), dim3(CW::T), sm, st, part,
                          static_cast<float*>(out), s, view0, nvb);
       break;
     }
     case kFftBackPrep: {
-      const size_t sm = smem_bytes<C>(0);
-      if ((e = set_smem((const void*)back_fft_prep_c<C>, sm)) != hipSuccess) return e;
-      hipLaunchKernelGGL(back_fft_prep_c<C>, dim3((unsigned)nvb), dim3(kT), sm, st,
+      const size_t sm = smem_bytes<CW>(0);
+      if ((e = set_smem((const void*)back_fft_prep_c<CW>, sm)) != hipSuccess) return e;
+      hipLaunchKernelGGL(back_fft_prep_c<CW>, dim3((unsigned)nvb), dim3(CW::T), sm, st,
                          static_cast<const float*>(in), V, s, view0);
       break;
     }
     case kFftBack: {
-      const size_t sm = smem_bytes<C>((s.nz + 2 * s.hb) * s.nx);
-      if ((e = set_smem((const void*)conv_back_fft_c<C>, sm)) != hipSuccess) return e;
-      hipLaunchKernelGGL(conv_back_fft_c<C>, dim3((unsigned)(nvb * s.nchunk_back)), dim3(kT), sm,
-                         st, V, P, static_cast<float*>(out), s, view0, nvb);
+      const size_t sm = smem_bytes<CB>((s.nz + 2 * s.hb) * s.nx);
+      if ((e = set_smem((const void*)conv_back_fft_c<CB>, sm)) != hipSuccess) return e;
+      hipLaunchKernelGGL(conv_back_fft_c<CB>, dim3((unsigned)(nvb * s.nchunk_back)), dim3(CB::T),
+                         sm, st, V, P, static_cast<float*>(out), s, view0, nvb);
       break;
     }
     default: return hipErrorInvalidValue;
@@ -524,8 +550,8 @@ bool fits(const FftShape& s) {
 }  // namespace
 
 int fft_fixed_config(const FftShape& s) {
-  if (fits<Cfg180x120>(s)) return 1;
-  if (fits<Cfg90x60>(s)) return 2;
+  if (fits<Cfg180x120<512>>(s)) return 1;
+  if (fits<Cfg90x60<512>>(s)) return 2;
   return 0;
 }
 

@@ -209,7 +209,8 @@ __device__ __forceinline__ void stage_twiddles(float2 (&w)[R], const float2* tw,
 }
 
 
-// The adjoint of replicate padding on one inverse-transformed plane:
+// The adjoint of replicate padding on one inverse-transformed plane (planes
+// of at most 2^16 padded values, for fdiv):
 // u[k][i] = sum of the padded plane g over the padded rows that clamp onto k
 // and the padded columns that clamp onto i, written to out[k * rs + i].
 // Columns first (into `fold`, (nz + 2 hb) x nx floats), then rows; the edge
@@ -220,8 +221,9 @@ __device__ __forceinline__ void fold_store(const float2* A, float* fold, int nx,
                                            int hb, float* out, size_t rs, G&& g, int T) {
   const int KZ = nz + 2 * hb;
   const int inner_x = nx > 2 ? nx - 2 : 0, edges_x = nx > 1 ? 2 : 1;
+  const float r_in = inner_x ? 1.0f / (float)inner_x : 0.0f, r_nx = 1.0f / (float)nx;
   for (int e = threadIdx.x; e < KZ * inner_x; e += T) {
-    const int zz = e / inner_x, i = 1 + e - zz * inner_x;
+    const int zz = fdiv(e, r_in), i = 1 + e - zz * inner_x;
     fold[zz * nx + i] = g(A, zz, i + ha);
   }
   for (int e = threadIdx.x; e < KZ * edges_x; e += T) {
@@ -236,7 +238,7 @@ __device__ __forceinline__ void fold_store(const float2* A, float* fold, int nx,
   __syncthreads();
   const int inner_z = nz > 2 ? nz - 2 : 0, edges_z = nz > 1 ? 2 : 1;
   for (int e = threadIdx.x; e < inner_z * nx; e += T) {
-    const int k = 1 + e / nx, i = e - (k - 1) * nx;
+    const int k = 1 + fdiv(e, r_nx), i = e - (k - 1) * nx;
     out[(size_t)k * rs + i] = fold[(k + hb) * nx + i];
   }
   for (int e = threadIdx.x; e < edges_z * nx; e += T) {
