@@ -39,6 +39,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--method", default="fft", choices=["fft", "direct"],
+                    help="PSF convolution of the timed pair: FP32 FFTs (the paper's method, "
+                         "SPECT_CONV_FFT) or the direct sum on the FP32 matrix cores")
+    ap.add_argument("--direct-steps", type=int, default=10,
+                    help="timed pairs of the other FP32 convolution method (0: skip)")
     ap.add_argument("--cache-mubar", type=int, default=1,
                     help="1: keep the Eq. (1) attenuation factor of all views in HBM (plan flag)")
     ap.add_argument("--em-recons", type=int, default=5, help="EM reconstructions timed for latency")
@@ -74,6 +79,11 @@ def parse():
     return ap.parse_args()
 
 
+def note(stage):
+    """One progress line per bench stage, on stderr (the JSON line is stdout)."""
+    print(f"bench: {stage}", file=sys.stderr, flush=True)
+
+
 def pct(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -107,6 +117,55 @@ def traffic_for(kernel):
         return rec["hbm_bytes_per_launch"]
     except Exception:
         return None
+
+
+def fft_flop_per_plane(Lx, Lz, mac):
+    """Algorithmic work of one plane of the FFT convolution: the real
+    two-dimensional transform of Lx x Lz points counted as 2.5 N log2 N
+    (N = Lx Lz), plus the spectral product over the Lz (Lx/2 + 1) bins of the
+    half spectrum (8 FLOP with accumulation, 6 without)."""
+    import math
+    n = Lx * Lz
+    return 2.5 * n * math.log2(n) + (8.0 if mac else 6.0) * Lz * (Lx // 2 + 1)
+
+
+def conv_roofline(kern_name, avg_ms, sel, nview, ny, op_flops, conv_flops, mirror):
+    """Roofline of a convolution kernel: FP32 matrix cores for the direct sum,
+    the FP32 vector ALUs (no packed FP32) for the FFT form."""
+    if kern_name in ("conv_fwd_fft", "conv_back_fft"):
+        Lx, Lz = (int(t) for t in sel["fft_size"].split("x"))
+        flops = nview * ny * fft_flop_per_plane(Lx, Lz, kern_name == "conv_fwd_fft")
+        a = flops / (avg_ms * 1e-3) / 1e12
+        return {"kernel": kern_name, "bound": "alu", "achieved": a, "peak": FP32_VALU_TFLOPS,
+                "unit": "TFLOP/s", "frac": a / FP32_VALU_TFLOPS, "traffic": traffic_for(kern_name),
+                "algorithmic_per_launch": flops, "avg_launch_ms": avg_ms,
+                "form": f"FFT {Lx}x{Lz} per plane (2.5 N log2 N + spectral product)"}
+    a = conv_flops / (avg_ms * 1e-3) / 1e12
+    return {"kernel": kern_name, "bound": "mfma", "achieved": a, "peak": FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": a / FP32_PEAK_TFLOPS, "traffic": traffic_for(kern_name),
+            "algorithmic_per_launch": conv_flops, "avg_launch_ms": avg_ms,
+            "form": "mirror-paired taps" if mirror else "all taps",
+            "operator_flop_per_launch": op_flops}
+
+
+def time_pairs(torch, pl, xd, steps, warmup, vd_shape):
+    """ms per pair and per-kernel ms per launch of `steps` forward + back pairs."""
+    v2 = torch.empty(vd_shape, dtype=torch.float32, device=xd.device)
+    b2 = torch.empty_like(xd)
+    for _ in range(warmup):
+        pl.forward(xd, out=v2)
+        pl.back(v2, out=b2)
+    torch.cuda.synchronize()
+    pl.profile_start(max_launches=64 * steps + 64)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        pl.forward(xd, out=v2)
+        pl.back(v2, out=b2)
+    b.record()
+    torch.cuda.synchronize()
+    kt = pl.profile_stop()
+    return a.elapsed_time(b) / steps, {k: v["total_ms"] / v["launches"] for k, v in kt.items()}
 
 
 def cpu_baseline(x, mu, psf, dy, nviews_sample, seed):
@@ -175,9 +234,8 @@ def main():
     xd = torch.from_numpy(x).to(dev)
     mud = torch.from_numpy(mu).to(dev)
     psfd = torch.from_numpy(psf).to(dev)
-    plan = spect.Plan(mud, psfd, dy, cache_mubar=bool(args.cache_mubar))
+    plan = spect.Plan(mud, psfd, dy, cache_mubar=bool(args.cache_mubar), method=args.method)
     sel = plan.describe()            # kernels chosen (the Gaussian PSF rows are symmetric in x)
-    mirror = sel.get("mirror") == "1"
     vd = torch.empty(plan.proj_shape, dtype=torch.float32, device=dev)
     bd = torch.empty(plan.vol_shape, dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
@@ -207,24 +265,21 @@ def main():
     ms_per_step = total_ms / K
     value = 1000.0 / ms_per_step
 
-    # dominant kernel and its roofline (algorithmic FLOPs per launch / average duration)
+    # dominant kernel and its roofline (algorithmic work per launch / average duration)
     N = nx * ny * nz
     views_per_launch = plan.nview  # one launch covers all views (view_batch = all)
-    # the operator's products: 2 px pz FLOP per voxel per view; with mirror-image
-    # tap pairing the matrix cores take 2 (px + 1) / 2 pz (the pre-adds of the
-    # two input columns run on the vector ALUs)
+    # the direct operator's products: 2 px pz FLOP per voxel per view; with
+    # mirror-image tap pairing the matrix cores take 2 (px + 1) / 2 pz (the
+    # pre-adds of the two input columns run on the vector ALUs)
     op_flops = 2.0 * px * pz * N * views_per_launch
-    conv_flops = 2.0 * ((px + 1) // 2) * pz * N * views_per_launch if mirror else op_flops
+    sym_x = bool(np.array_equal(psf, psf[..., ::-1]))
+    paired_flops = 2.0 * ((px + 1) // 2) * pz * N * views_per_launch
+    mirror = sel.get("mirror") == "1"
+    conv_flops = paired_flops if mirror else op_flops
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     avg_ms = {k: v["total_ms"] / v["launches"] for k, v in kern.items()}
-    if dom in ("conv_fwd", "conv_back"):
-        achieved = conv_flops / (avg_ms[dom] * 1e-3) / 1e12
-        roof = {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
-                "traffic": traffic_for(dom),
-                "algorithmic_per_launch": conv_flops, "avg_launch_ms": avg_ms[dom],
-                "form": "mirror-paired taps" if mirror else "all taps",
-                "operator_flop_per_launch": op_flops}
+    if dom in ("conv_fwd", "conv_back", "conv_fwd_fft", "conv_back_fft"):
+        roof = conv_roofline(dom, avg_ms[dom], sel, nview, ny, op_flops, conv_flops, mirror)
     else:
         byts = 3.0 * 4 * N * views_per_launch
         achieved = byts / (avg_ms[dom] * 1e-3) / 1e9
@@ -234,10 +289,13 @@ def main():
 
     # EM reconstruction latency (not part of `value`)
     em = None
+    note("em_recons")
     if args.em_recons > 0:
         ones = torch.ones(plan.proj_shape, dtype=torch.float32, device=dev)
         sens = plan.back(ones)
-        yd = torch.poisson(vd * 1.0)
+        # the FFT convolution leaves rounding-level negatives where the exact
+        # projection is zero; a Poisson rate must be nonnegative
+        yd = torch.poisson(vd.clamp_min(0.0))
         rd = torch.full_like(yd, 0.05 * float(yd.mean()))
         lat = []
         for _ in range(args.em_recons):
@@ -280,10 +338,35 @@ def main():
         os_.close()
         del os_
 
-    # The same pair with every PSF tap taken separately (SPECT_PSF_ALL_TAPS):
-    # the path for PSFs that are not symmetric in x (not part of `value`).
+    # The other FP32 convolution method on the same pair (not part of `value`):
+    # the direct sum on the matrix cores (mirror-paired taps for these
+    # symmetric PSFs) when the headline runs the FFTs, and the other way round.
+    other = None
+    note("direct_steps")
+    if args.direct_steps > 0:
+        om = "direct" if args.method == "fft" else "fft"
+        pl = spect.Plan(mud, psfd, dy, cache_mubar=bool(args.cache_mubar), method=om)
+        osel = pl.describe()
+        ms, kav = time_pairs(torch, pl, xd, args.direct_steps, args.warmup, vd.shape)
+        v2 = pl.forward(xd)
+        b2 = pl.back(vd)
+        torch.cuda.synchronize()
+        odom = max((k for k in kav if k.startswith("conv_")), key=lambda k: kav[k])
+        other = {"method": om, "pairs_per_s": 1000.0 / ms, "ms_per_pair": ms, "plan": osel,
+                 "rel_l2_forward_vs_headline": float((v2.double() - vd.double()).norm() / vd.double().norm()),
+                 "rel_l2_back_vs_headline": float((b2.double() - bd.double()).norm() / bd.double().norm()),
+                 "kernels_ms_per_launch": kav,
+                 "conv_roofline": conv_roofline(odom, kav[odom], osel, nview, ny, op_flops,
+                                                paired_flops if osel.get("mirror") == "1" else op_flops,
+                                                osel.get("mirror") == "1")}
+        pl.close()
+        del pl, v2, b2
+
+    # The direct pair with every PSF tap taken separately (SPECT_PSF_ALL_TAPS):
+    # the direct path for PSFs that are not symmetric in x (not part of `value`).
     all_taps = None
-    if args.all_taps_steps > 0 and mirror:
+    note("all_taps_steps")
+    if args.all_taps_steps > 0 and sym_x:
         pl = spect.Plan(mud, psfd, dy, cache_mubar=bool(args.cache_mubar), mirror="off")
         v2 = torch.empty_like(vd)
         b2 = torch.empty_like(bd)
@@ -306,8 +389,8 @@ def main():
         torch.cuda.synchronize()
         kav = {k: v["total_ms"] / v["launches"] for k, v in kt.items()}
         all_taps = {"pairs_per_s": 1000.0 / ms, "ms_per_pair": ms, "plan": pl.describe(),
-                    "rel_l2_forward_vs_paired": float((v2.double() - vd.double()).norm() / vd.double().norm()),
-                    "rel_l2_back_vs_paired": float((b2.double() - bd.double()).norm() / bd.double().norm()),
+                    "rel_l2_forward_vs_headline": float((v2.double() - vd.double()).norm() / vd.double().norm()),
+                    "rel_l2_back_vs_headline": float((b2.double() - bd.double()).norm() / bd.double().norm()),
                     "kernels_ms_per_launch": kav,
                     "conv_fwd_tflops": op_flops / (kav["conv_fwd"] * 1e-3) / 1e12,
                     "conv_back_tflops": op_flops / (kav["conv_back"] * 1e-3) / 1e12}
@@ -318,8 +401,9 @@ def main():
     # Eq. (1) factor is recomputed from mu for every view in every call, as in
     # the paper's memory-saving design, and the workspace shrinks by the cache.
     uncached = None
+    note("uncached_steps")
     if args.uncached_steps > 0:
-        pl = spect.Plan(mud, psfd, dy, cache_mubar=False)
+        pl = spect.Plan(mud, psfd, dy, cache_mubar=False, method=args.method)
         v2 = torch.empty_like(vd)
         b2 = torch.empty_like(bd)
         for _ in range(args.warmup):
@@ -349,6 +433,7 @@ def main():
     # BF16 products per FP32 product), their speed and distance from the FP32
     # path (itself within 1e-5 of the FP64 oracle).
     lp = None
+    note("precision_steps")
     if args.precision_steps > 0:
         lp = {}
         ref_v = vd.double()
@@ -402,8 +487,10 @@ def main():
     # `value`; a different operator, so its distance from the 3-pass pair is
     # the difference between the two interpolations, not an error).
     bil = None
+    note("bilinear_steps")
     if args.bilinear_steps > 0:
-        pl = spect.Plan(mud, psfd, dy, cache_mubar=bool(args.cache_mubar), rotation="bilinear")
+        pl = spect.Plan(mud, psfd, dy, cache_mubar=bool(args.cache_mubar), rotation="bilinear",
+                        method=args.method)
         v2 = torch.empty_like(vd)
         b2 = torch.empty_like(bd)
         for _ in range(args.warmup):
@@ -432,6 +519,7 @@ def main():
     # (SPECT_PSF_SEPARABLE): the same operator up to the rounding of the
     # factors, two 1-D passes per plane (not part of `value`).
     sep = None
+    note("separable_steps")
     if args.separable_steps > 0:
         cfg = synth.CONFIGS["paper"]
         fz, fx = synth.gaussian_psf_factors(px, pz, ny, nview, *cfg["sigma"])
@@ -473,6 +561,7 @@ def main():
     # Distances are to the FP32 results, which the tests hold within 1e-5 of
     # the FP64 oracle at this size.
     large = None
+    note("large_steps")
     if args.large_steps > 0:
         xl, mul, psfl, dyl = synth.config_inputs("large", seed=args.seed)
         xld, muld, psfld = (torch.from_numpy(a).to(dev) for a in (xl, mul, psfl))
@@ -514,13 +603,14 @@ def main():
     # Differentiation through unrolled EM (not part of `value`): MSE against the
     # phantom backpropagated to x0 and y through `grad_iters` EM updates.
     grad = None
+    note("grad_iters")
     if args.grad_iters > 0:
         from paper_2301_09710_amd import autograd as sag
         ones = torch.ones(plan.proj_shape, dtype=torch.float32, device=dev)
         sens = plan.back(ones)
         yc = plan.forward(xd)
         rg = torch.full_like(yc, 0.05 * float(yc.mean()))
-        yg = torch.poisson(yc + rg)
+        yg = torch.poisson((yc + rg).clamp_min(0.0))
         x0 = torch.full_like(xd, float(xd.mean()))
         # one untimed pass so that the timed one sees warm allocator pools
         xw = x0.clone().requires_grad_(True)
@@ -549,19 +639,22 @@ def main():
     # reconstructions of three sizes, 8 EM iterations each.
     serving = None
     precs = [p_ for p_ in args.serve_precisions.split(",") if p_]
+    note("serve_requests")
     if args.serve_requests > 0 and precs:
         from paper_2301_09710_amd import serve as sv
         trace0 = sv.poisson_trace(args.serve_requests, args.serve_rate, seed=args.seed + 1)
+        # FP32 requests use the headline's convolution method; BF16 / FP16 the direct one
         t_gen = time.perf_counter()
         data = {r.rid: sv.RequestData(r, dev) for r in trace0}
         t_gen = time.perf_counter() - t_gen
         serving = {}
         for prec in precs:
             trace = sv.poisson_trace(args.serve_requests, args.serve_rate, seed=args.seed + 1,
-                                     precision=prec)
+                                     precision=prec,
+                                     method=args.method if prec == "fp32" else "direct")
             budget = int(0.5 * torch.cuda.get_device_properties(dev).total_memory)
             sched = sv.Scheduler(budget, args.serve_slots,
-                                 lambda r: sv.request_bytes(r.size, r.precision))
+                                 lambda r: sv.request_bytes(r.size, r.precision, method=r.method))
             ex = sv.GpuExecutor(dev, data, max_slots=args.serve_slots, keep_results=False)
             torch.cuda.synchronize()
             base = torch.cuda.memory_allocated(dev)
@@ -572,7 +665,7 @@ def main():
             wall_s = time.perf_counter() - t_s
             rec = sv.summarize(done, wall_s)
             rec.update({"rate_req_s": args.serve_rate, "slots": args.serve_slots,
-                        "precision": prec, "iters": trace[0].iters,
+                        "precision": prec, "method": trace[0].method, "iters": trace[0].iters,
                         "budget_gb": budget / 1e9, "peak_admitted_gb": sched.peak / 1e9,
                         "peak_measured_gb": (torch.cuda.max_memory_allocated(dev) - base) / 1e9,
                         "wall_s": wall_s, "trace_s": trace[-1].arrival,
@@ -591,6 +684,7 @@ def main():
         del src, dstb
 
     cpu = None
+    note("cpu_views")
     if args.cpu_views > 0:
         cpu = cpu_baseline(x, mu, psf, dy, args.cpu_views, args.seed)
 
@@ -609,11 +703,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": "paper-scale FP32 projector pair: 128x128x80 volume (4.8 mm), "
                                "128 views over 360 deg, 37x37 depth/view-dependent Gaussian PSF",
+                   "method": args.method,
                    "nx": nx, "ny": ny, "nz": nz, "nview": nview, "px": px, "pz": pz,
                    "cache_mubar": bool(args.cache_mubar), "plan": sel,
                    "workspace_bytes": plan.ws_bytes,
                    "mubar_cache_bytes": (nview * nx * ny * nz * 4) if args.cache_mubar else 0},
         "uncached_mubar": uncached,
+        "other_method": other,
         "pair_latency_ms": {"p50": pct(step_ms, 50), "p99": pct(step_ms, 99),
                             "p10": pct(step_ms, 10), "p90": pct(step_ms, 90)},
         "wall_s_timed": wall,
@@ -627,12 +723,13 @@ def main():
         "serving": serving,
         "kernels_ms_per_launch": avg_ms,
         "roofline": roof,
-        # the direct operator's products per pair (forward and back convolution,
+        # the direct sum's products per pair (forward and back convolution,
         # 2 px pz FLOP per voxel per view each) over the measured pair time: the
         # rate a direct all-taps implementation would need to match this pair
-        "operator_rate": {"flop_per_pair": 2 * op_flops,
-                          "tflops": 2 * op_flops / (ms_per_step * 1e-3) / 1e12,
-                          "frac_of_fp32_peak": 2 * op_flops / (ms_per_step * 1e-3) / 1e12 / FP32_PEAK_TFLOPS},
+        # (above the FP32 matrix-core peak when the FFTs run the convolution)
+        "direct_sum_equivalent": {"flop_per_pair": 2 * op_flops,
+                                  "tflops": 2 * op_flops / (ms_per_step * 1e-3) / 1e12,
+                                  "fp32_mfma_peak_tflops": FP32_PEAK_TFLOPS},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -118,7 +118,11 @@ typedef enum {
                                    Lz >= nz+pz-1 the smallest even products of 2, 3, 5) and
                                    keeps them in the workspace.  FP32 only, not with
                                    SPECT_PSF_SEPARABLE; planes whose transform does not fit
-                                   the kernels' LDS give SPECT_ERR_UNSUPPORTED. */
+                                   the kernels' LDS give SPECT_ERR_UNSUPPORTED.  Where the
+                                   exact result is zero (bins outside the body's shadow),
+                                   outputs carry rounding noise of either sign, of the order
+                                   of 1e-7 times the largest output: clamp them before a use
+                                   that needs nonnegative values (a Poisson rate). */
 
 /* Geometry of one plan (host struct, copied by spect_plan_create). */
 typedef struct {
@@ -271,7 +275,9 @@ const char* spect_version(void);
  * hold: pz >= 67) | separable | bf16 | fp16 | bf16x3, mirror = 1 when the FP32 4x4-block
  * convolution pairs mirror-image taps (see spect_plan_create), rotation =
  * 3pass | bilinear, view_batch, nchunk, rot_views (views per workgroup of
- * the forward rotation).  Host only. */
+ * the forward rotation); with SPECT_CONV_FFT also fft_size = LxxLz (the
+ * transform size) and fft_fixed (nonzero when kernels compiled for that size
+ * run).  Host only. */
 spect_status spect_plan_describe(spect_plan plan, char* buf, size_t len);
 
 #ifdef __cplusplus

@@ -316,9 +316,11 @@ spect_status spect_plan_describe(spect_plan plan, char* buf, size_t len) {
                      : p->use_mfma  ? "fp32-16x16"
                                     : "fp32-direct";
   const bool mirror = p->use_m4 && p->conv_precision == SPECT_CONV_FP32 && p->m4.mirror;
-  std::snprintf(buf, len, "conv=%s mirror=%d rotation=%s view_batch=%d nchunk=%d rot_views=%d",
-                conv, mirror ? 1 : 0, p->bilinear ? "bilinear" : "3pass", p->view_batch, p->nchunk,
-                p->rot_fwd_vg);
+  int n = std::snprintf(buf, len, "conv=%s mirror=%d rotation=%s view_batch=%d nchunk=%d rot_views=%d",
+                        conv, mirror ? 1 : 0, p->bilinear ? "bilinear" : "3pass", p->view_batch,
+                        p->nchunk, p->rot_fwd_vg);
+  if (p->use_fft && n > 0 && (size_t)n < len)
+    std::snprintf(buf + n, len - n, " fft_size=%dx%d fft_fixed=%d", p->fft.Lx, p->fft.Lz, p->fft.cfg);
   return SPECT_OK;
 }
 

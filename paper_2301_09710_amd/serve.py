@@ -43,6 +43,7 @@ class Request:
     arrival: float            # seconds after the start of the trace
     iters: int = 8
     precision: str = "fp32"
+    method: str = "direct"    # PSF convolution: "direct" or "fft" (FP32 only)
 
 
 @dataclasses.dataclass
@@ -60,14 +61,14 @@ class Done:
 
 
 def poisson_trace(n: int, rate: float, seed: int = 0, iters: int = 8,
-                  sizes=SIZES, precision: str = "fp32") -> List[Request]:
+                  sizes=SIZES, precision: str = "fp32", method: str = "direct") -> List[Request]:
     """n requests with exponential inter-arrival times (mean 1/rate) and sizes
     drawn uniformly from ``sizes``; each request's phantom, attenuation map
     and Poisson data come from its own seed."""
     rng = np.random.default_rng(seed)
     t = np.cumsum(rng.exponential(1.0 / rate, size=n))
     pick = rng.integers(0, len(sizes), size=n)
-    return [Request(i, sizes[int(pick[i])], seed * 100003 + i, float(t[i]), iters, precision)
+    return [Request(i, sizes[int(pick[i])], seed * 100003 + i, float(t[i]), iters, precision, method)
             for i in range(n)]
 
 
@@ -82,14 +83,16 @@ ALLOC_ROUND = 2 << 20
 REQUEST_BUFFERS = 8
 
 
-def request_bytes(size: str, precision: str = "fp32", cache_mubar: bool = True) -> int:
+def request_bytes(size: str, precision: str = "fp32", cache_mubar: bool = True,
+                  method: str = "direct") -> int:
     """Device memory one admitted request holds: the plan workspace and the
     request's buffers (mu, PSFs, sinogram, background, image, sensitivity and
     the projection of ones the sensitivity is made from), each rounded up as
     the caching allocator rounds it."""
     nx, ny, nz, nview, px, pz, dy = geometry_of(size)
     g, _ = spect.make_geom(nx, ny, nz, nview, px, pz, dy,
-                           flags=spect.SPECT_CACHE_MUBAR if cache_mubar else 0,
+                           flags=(spect.SPECT_CACHE_MUBAR if cache_mubar else 0) |
+                           spect.METHODS[method],
                            conv_precision=spect.PRECISIONS[precision])
     N, M = nx * ny * nz, nview * nz * nx
     bufs = [spect.spect_workspace_bytes(g), 4 * N, 4 * N, 4 * N, 4 * M, 4 * M, 4 * M,
@@ -200,7 +203,7 @@ class RequestData:
         yc = plan.forward(torch.from_numpy(x).to(device))
         r = torch.full_like(yc, 0.05 * float(yc.mean()))
         gen = torch.Generator(device=device).manual_seed(req.seed)
-        y = torch.poisson(yc + r, generator=gen)
+        y = torch.poisson((yc + r).clamp_min(0.0), generator=gen)
         torch.cuda.synchronize(device)
         self.y = y.cpu().numpy()
         self.r = r.cpu().numpy()
@@ -243,7 +246,7 @@ class GpuExecutor:
             mu, psf, y, r = (d.pinned[k].to(self.device, non_blocking=True)
                              for k in ("mu", "psf", "y", "r"))
             plan = spect.Plan(mu, psf, d.dy, cache_mubar=self.cache_mubar, precision=req.precision,
-                              mirror="assume" if d.symmetric_x else "off")
+                              mirror="assume" if d.symmetric_x else "off", method=req.method)
             sens = plan.back(torch.ones(plan.proj_shape, dtype=torch.float32, device=self.device))
             x = torch.ones(plan.vol_shape, dtype=torch.float32, device=self.device)
         self.slots[req.rid] = _Slot(req, plan, stream, x, y, r, sens, now)

@@ -174,7 +174,7 @@ def test_unrolled_gradient_paper_size_directional():
     with torch.no_grad():
         yc = plan.forward(xt)
         r = torch.full_like(yc, 0.05 * float(yc.mean()))
-        y = torch.poisson(yc * 5.0 + r)
+        y = torch.poisson((yc * 5.0 + r).clamp_min(0.0))
         sens = plan.back(torch.ones_like(yc))
     x0 = torch.full_like(xt, float(xt.mean()))
 

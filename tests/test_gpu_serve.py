@@ -30,14 +30,17 @@ def mix():
              sv.Request(1, "serve96", 12, 0.002, iters=3),
              sv.Request(2, "serve64", 13, 0.004, iters=5),
              sv.Request(3, "paper", 14, 0.006, iters=2),
-             sv.Request(4, "serve64", 15, 0.008, iters=4, precision="bf16")]
+             sv.Request(4, "serve64", 15, 0.008, iters=4, precision="bf16"),
+             sv.Request(5, "serve64", 16, 0.010, iters=3, method="fft"),
+             sv.Request(6, "serve96", 17, 0.012, iters=2, method="fft")]
     say("serve: generating request data")
     data = {r.rid: sv.RequestData(r, DEV) for r in trace}
     return trace, data
 
 
 def _run(trace, data, slots, budget):
-    sched = sv.Scheduler(budget, slots, lambda r: sv.request_bytes(r.size, r.precision))
+    sched = sv.Scheduler(budget, slots,
+                         lambda r: sv.request_bytes(r.size, r.precision, method=r.method))
     ex = sv.GpuExecutor(DEV, data, max_slots=slots)
     done = sv.serve(trace, sched, ex)
     torch.cuda.synchronize()
@@ -51,8 +54,8 @@ def test_results_same_alone_and_in_mix(mix):
     assert sorted(together) == [r.rid for r in trace]
     for r in trace:
         say(f"serve: request {r.rid} alone")
-        alone, _ = _run([sv.Request(r.rid, r.size, r.seed, 0.0, r.iters, r.precision)], data, 1,
-                        64 << 30)
+        alone, _ = _run([sv.Request(r.rid, r.size, r.seed, 0.0, r.iters, r.precision, r.method)],
+                        data, 1, 64 << 30)
         np.testing.assert_array_equal(alone[r.rid].x, together[r.rid].x)
 
 
@@ -78,7 +81,7 @@ def test_memory_budget_respected_under_pressure(mix):
     torch's allocator counts it (live buffers, already rounded to its 2 MiB
     granules), not only for the scheduler's own bookkeeping."""
     trace, data = mix
-    need = {r.rid: sv.request_bytes(r.size, r.precision) for r in trace}
+    need = {r.rid: sv.request_bytes(r.size, r.precision, method=r.method) for r in trace}
     budget = int(max(need.values()) * 1.2)          # the largest fits, never two large ones
     say(f"serve: budget {budget / 2 ** 30:.2f} GiB")
     torch.cuda.synchronize()
@@ -97,12 +100,14 @@ def test_request_bytes_counts_what_a_request_allocates(mix):
     """request_bytes is an upper bound on the device memory one admitted
     request allocates (measured around a served request alone)."""
     trace, data = mix
-    for r in (trace[0], trace[3], trace[4]):
+    for r in (trace[0], trace[3], trace[4], trace[6]):
         torch.cuda.synchronize()
         base = torch.cuda.memory_allocated(DEV)
         torch.cuda.reset_peak_memory_stats(DEV)
-        _run([sv.Request(r.rid, r.size, r.seed, 0.0, r.iters, r.precision)], data, 1, 64 << 30)
+        _run([sv.Request(r.rid, r.size, r.seed, 0.0, r.iters, r.precision, r.method)], data, 1,
+             64 << 30)
         measured = torch.cuda.max_memory_allocated(DEV) - base
-        say(f"serve: {r.size}/{r.precision}: measured {measured / 2 ** 20:.1f} MiB, "
-            f"request_bytes {sv.request_bytes(r.size, r.precision) / 2 ** 20:.1f} MiB")
-        assert measured <= sv.request_bytes(r.size, r.precision)
+        need = sv.request_bytes(r.size, r.precision, method=r.method)
+        say(f"serve: {r.size}/{r.precision}/{r.method}: measured {measured / 2 ** 20:.1f} MiB, "
+            f"request_bytes {need / 2 ** 20:.1f} MiB")
+        assert measured <= need
