@@ -55,8 +55,8 @@ struct Cfg {
   }
 };
 
-// C2 workload planes (128 x 80, 37 x 37 PSF) and the 64 x 40 / 19 x 19 serving
-// planes; the adjoint keeps two spectra per thread in registers (the view's
+// 128 x 80 planes with 37 x 37 PSFs, and 64 x 40 planes with 19 x 19 PSFs;
+// the adjoint keeps two spectra per thread in registers (the view's
 // projection and the next plane's PSF), so it runs 512 threads, the others 1024.
 template <int T> using Cfg180x120 = Cfg<180, 120, 15, 12, 12, 10, T>;
 template <int T> using Cfg90x60 = Cfg<90, 60, 9, 10, 10, 6, T>;
