@@ -71,16 +71,23 @@ __device__ __forceinline__ void ct_pass(float2* A, Addr addr, int N, int batch, 
     float2 v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = A[addr(tb, base + r * S)];
-    float2 w[R];
-    stage_twiddles<R>(w, tw, k * step);
+    // the last pass (S = 1) has no twiddles
     if (kInv) {
+      if (S > 1) {
+        float2 w[R];
+        stage_twiddles<R>(w, tw, k * step);
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[r] = cmulc(v[r], w[r]);
+        for (int r = 1; r < R; ++r) v[r] = cmulc(v[r], w[r]);
+      }
       dft_any<R, true>(v);
     } else {
       dft_any<R, false>(v);
+      if (S > 1) {
+        float2 w[R];
+        stage_twiddles<R>(w, tw, k * step);
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], w[r]);
+        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], w[r]);
+      }
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) A[addr(tb, base + r * S)] = v[r];

@@ -25,6 +25,13 @@ namespace {
 
 using namespace fft;
 
+__device__ __forceinline__ int clampi(int q, int lo, int hi) { return q < lo ? lo : (q > hi ? hi : q); }
+
+// Row stride (floats) of the raw W plane in LDS: odd when whole waves load
+// whole row segments (nx a multiple of 64), so that the lanes of the first x
+// pass, on consecutive rows, read distinct banks; packed otherwise.
+__host__ __device__ __forceinline__ int raw_stride(int nx) { return nx % 64 == 0 ? nx + 1 : nx; }
+
 
 template <int LX, int LZ, int RX0, int RX1, int RZ0, int RZ1, int THREADS>
 struct Cfg {
@@ -55,9 +62,11 @@ struct Cfg {
   }
 };
 
-// 128 x 80 planes with 37 x 37 PSFs, and 64 x 40 planes with 19 x 19 PSFs;
-// the adjoint keeps two spectra per thread in registers (the view's
-// projection and the next plane's PSF), so it runs 512 threads, the others 1024.
+// 128 x 80 planes with 37 x 37 PSFs, and 64 x 40 planes with 19 x 19 PSFs.
+// The convolution kernels keep spectra per thread in registers (the forward
+// its accumulators and the next PSF spectrum, the adjoint the view's
+// projection and the next PSF spectrum), so they run 768 and 512 threads
+// (170 and 256 registers per lane); the once-per-view kernels run 1024.
 template <int T> using Cfg180x120 = Cfg<180, 120, 15, 12, 12, 10, T>;
 template <int T> using Cfg90x60 = Cfg<90, 60, 9, 10, 10, 6, T>;
 
@@ -100,16 +109,21 @@ __device__ __forceinline__ void pass(float2* A, const float2* tw) {
     float2 v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = A[ad[r]];
+    // the last pass of an axis (S = 1) has no twiddles
     float2 w[R];
-    stage_twiddles<R>(w, tw, k * step);
-    if (kInv) {
+    if constexpr (S > 1) stage_twiddles<R>(w, tw, k * step);
+    if constexpr (kInv) {
+      if constexpr (S > 1) {
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[r] = cmulc(v[r], w[r]);
+        for (int r = 1; r < R; ++r) v[r] = cmulc(v[r], w[r]);
+      }
       dft_any<R, true>(v);
     } else {
       dft_any<R, false>(v);
+      if constexpr (S > 1) {
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], w[r]);
+        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], w[r]);
+      }
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) A[ad[r]] = v[r];
@@ -117,63 +131,154 @@ __device__ __forceinline__ void pass(float2* A, const float2* tw) {
   __syncthreads();
 }
 
-// Row pairs after the forward x transforms (R1 at f, R2 at -f; see
-// unpack_rows in conv_fft.hip); lanes take consecutive row pairs.
+// The last x pass (radix Rx1, no twiddles) fused with the unpack of the row
+// pairs (see unpack_rows in conv_fft.hip), and its inverse fused with the
+// repack.  After the pass, column o Rx1 + r of a row pair holds x frequency
+// f = o + Rx0 r; for o >= 1 its mirror Lx - f sits at (Rx0 - o, Rx1 - 1 - r),
+// and for o = 0 at (0, Rx1 - r).  So one thread takes butterflies u and
+// Rx0 - u of a row pair (Rx0 odd) and unpacks every pair in registers: the
+// member below Lx/2 (r < Rx1/2) gets R1 = (Z[f] + conj Z[-f]) / 2, the mirror
+// R2 = -i (Z[f] - conj Z[-f]) / 2; frequencies 0 and Lx/2 (column 0 and
+// Rx1/2) hold the two rows' real DC and Nyquist values.  Lanes take
+// consecutive row pairs.
 template <class C>
-__device__ __forceinline__ void unpack_rows(float2* A) {
-  for (int e = threadIdx.x; e < C::H * C::Lh; e += C::T) {
-    const int f = e / C::H, p = e - f * C::H;
-    float2* row = A + p * C::ST;
-    if (f == 0) {
-      const float2 z0 = row[0], zn = row[C::HR];
-      row[0] = make_float2(z0.x, zn.x);
-      row[C::HR] = make_float2(z0.y, zn.y);
+__device__ __forceinline__ void unpack_pair(float2& a, float2& b) {
+  const float2 zf = a, zm = cconj(b);
+  a = cscale(cadd(zf, zm), 0.5f);
+  b = cimul(csub(zf, zm), -0.5f);
+}
+
+template <class C>
+__device__ __forceinline__ void repack_pair(float2& a, float2& b) {
+  const float2 r1 = a, r2 = b;
+  a = cadd(r1, cimul(r2, 1.0f));
+  b = cadd(cconj(r1), cimul(cconj(r2), 1.0f));
+}
+
+template <class C, bool kInv>
+__device__ __forceinline__ void xpass_last_rows(float2* A) {
+  constexpr int R = C::Rx1, U = (C::Rx0 + 1) / 2, B = C::H * U, HR = R / 2;
+  static_assert(C::Rx0 % 2 == 1 && R % 2 == 0 && C::Rx1 * C::Rx0 == C::Lx, "row-pair split");
+#pragma unroll 1
+  for (int b = threadIdx.x; b < B; b += C::T) {
+    const int u = b / C::H, tb = b - u * C::H;
+    float2* row = A + tb * C::ST;
+    if (u == 0) {
+      float2 v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = row[r];
+      if constexpr (!kInv) {
+        dft_any<R, false>(v);
+        const float2 z0 = v[0], zn = v[HR];
+        v[0] = make_float2(z0.x, zn.x);
+        v[HR] = make_float2(z0.y, zn.y);
+#pragma unroll
+        for (int r = 1; r < HR; ++r) unpack_pair<C>(v[r], v[R - r]);
+      } else {
+        const float2 a = v[0], c = v[HR];
+        v[0] = make_float2(a.x, c.x);
+        v[HR] = make_float2(a.y, c.y);
+#pragma unroll
+        for (int r = 1; r < HR; ++r) repack_pair<C>(v[r], v[R - r]);
+        dft_any<R, true>(v);
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) row[r] = v[r];
     } else {
-      const int cf = C::posx(f), cm = C::posx(C::Lx - f);
-      const float2 zf = row[cf], zm = cconj(row[cm]);
-      row[cf] = cscale(cadd(zf, zm), 0.5f);
-      row[cm] = cimul(csub(zf, zm), -0.5f);
+      float2* p1 = row + u * R;
+      float2* p2 = row + (C::Rx0 - u) * R;
+      float2 v1[R], v2[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        v1[r] = p1[r];
+        v2[r] = p2[r];
+      }
+      if constexpr (!kInv) {
+        dft_any<R, false>(v1);
+        dft_any<R, false>(v2);
+#pragma unroll
+        for (int r = 0; r < HR; ++r) {
+          unpack_pair<C>(v1[r], v2[R - 1 - r]);
+          unpack_pair<C>(v2[r], v1[R - 1 - r]);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < HR; ++r) {
+          repack_pair<C>(v1[r], v2[R - 1 - r]);
+          repack_pair<C>(v2[r], v1[R - 1 - r]);
+        }
+        dft_any<R, true>(v1);
+        dft_any<R, true>(v2);
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        p1[r] = v1[r];
+        p2[r] = v2[r];
+      }
     }
   }
   __syncthreads();
 }
 
+// The first x pass of the forward transform (radix Rx0, stride Lx / Rx0,
+// twiddle exp(-2 pi i r k / Lx)) with its input read straight from a raw
+// nz x nx plane in LDS (rows of `rs` floats): element (row q, column c) of
+// the replicate-padded plane is raw[clamp(q - hb)][clamp(c - ha)] for
+// q < nz + 2 hb and c < nx + 2 ha, and 0 beyond; row pair tb holds rows tb
+// and tb + H.  Lanes take consecutive row pairs.
 template <class C>
-__device__ __forceinline__ void repack_rows(float2* A) {
-  for (int e = threadIdx.x; e < C::H * C::Lh; e += C::T) {
-    const int f = e / C::H, p = e - f * C::H;
-    float2* row = A + p * C::ST;
-    if (f == 0) {
-      const float2 a = row[0], b = row[C::HR];
-      row[0] = make_float2(a.x, b.x);
-      row[C::HR] = make_float2(a.y, b.y);
-    } else {
-      const int cf = C::posx(f), cm = C::posx(C::Lx - f);
-      const float2 r1 = row[cf], r2 = row[cm];
-      row[cf] = cadd(r1, cimul(r2, 1.0f));
-      row[cm] = cadd(cconj(r1), cimul(cconj(r2), 1.0f));
+__device__ __forceinline__ void xpass_first_from_raw(float2* A, const float2* tw, const float* raw,
+                                                     int rs, int nx, int nz, int ha, int hb) {
+  constexpr int R = C::Rx0, S = C::Lx / R, B = C::H * S;
+  const int KZ = nz + 2 * hb, IX = nx + 2 * ha;
+#pragma unroll 1
+  for (int b = threadIdx.x; b < B; b += C::T) {
+    const int k = b / C::H, tb = b - k * C::H;
+    const bool lo_ok = tb < KZ, hi_ok = tb + C::H < KZ;
+    const float* rlo = raw + clampi(tb - hb, 0, nz - 1) * rs;
+    const float* rhi = raw + clampi(tb + C::H - hb, 0, nz - 1) * rs;
+    float2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int c = k + r * S;
+      const int i = clampi(c - ha, 0, nx - 1);
+      const bool in_c = c < IX;
+      v[r] = make_float2(lo_ok && in_c ? rlo[i] : 0.0f, hi_ok && in_c ? rhi[i] : 0.0f);
     }
+    float2 w[R];
+    stage_twiddles<R>(w, tw, k);
+    dft_any<R, false>(v);
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], w[r]);
+    float2* row = A + tb * C::ST + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) row[r * S] = v[r];
   }
   __syncthreads();
+}
+
+// Forward 2-D transform after the first x pass; `before_last` runs before
+// the last z pass (the callers prefetch there).
+template <class C, class F>
+__device__ __forceinline__ void fft2_fwd_rest(float2* A, const float2* twz, F&& before_last) {
+  xpass_last_rows<C, false>(A);
+  pass<C, C::Rz0, C::Lz, true, false>(A, twz);
+  before_last();
+  pass<C, C::Rz1, C::Rz1, true, false>(A, twz);
 }
 
 template <class C, class F>
 __device__ __forceinline__ void fft2_fwd(float2* A, const float2* twx, const float2* twz,
                                          F&& before_last) {
   pass<C, C::Rx0, C::Lx, false, false>(A, twx);
-  pass<C, C::Rx1, C::Rx1, false, false>(A, twx);
-  unpack_rows<C>(A);
-  pass<C, C::Rz0, C::Lz, true, false>(A, twz);
-  before_last();
-  pass<C, C::Rz1, C::Rz1, true, false>(A, twz);
+  fft2_fwd_rest<C>(A, twz, before_last);
 }
 
 template <class C>
 __device__ __forceinline__ void fft2_inv(float2* A, const float2* twx, const float2* twz) {
   pass<C, C::Rz1, C::Rz1, true, true>(A, twz);
   pass<C, C::Rz0, C::Lz, true, true>(A, twz);
-  repack_rows<C>(A);
-  pass<C, C::Rx1, C::Rx1, false, true>(A, twx);
+  xpass_last_rows<C, true>(A);
   pass<C, C::Rx0, C::Lx, false, true>(A, twx);
 }
 
@@ -211,7 +316,6 @@ __device__ __forceinline__ void store_slots(const float2* A, float2* out, float 
   }
 }
 
-__device__ __forceinline__ int clampi(int q, int lo, int hi) { return q < lo ? lo : (q > hi ? hi : q); }
 
 __device__ __forceinline__ void chunk_range(int c, int nchunk, int ny, int& j0, int& j1) {
   j0 = (int)(((long long)c * ny) / nchunk);
@@ -282,19 +386,19 @@ __global__ __launch_bounds__(C::T) void conv_fwd_fft_c(const float* __restrict__
   float2 acc[C::KS], a0 = make_float2(0.f, 0.f), an = make_float2(0.f, 0.f);
 #pragma unroll
   for (int q = 0; q < C::KS; ++q) acc[q] = make_float2(0.f, 0.f);
-  constexpr int kStageGroups = C::T / C::Lx;                   // threads per column
-  constexpr int kStageRows = (C::H + kStageGroups - 1) / kStageGroups;
+  const int rrs = raw_stride(nx);
   // plane j of W straight into the raw LDS region (lane L of a wave writes
   // the wave's base + 4 L bytes: 64 consecutive elements of the [nz][nx] plane)
   auto load_plane = [&](int j) {
     const int lane = tid & 63, wbase = tid - lane;
     if (nx % 64 == 0) {
-      // each wave's 64 elements lie in one row: row and column offsets are uniform
+      // each wave's 64 elements lie in one row: row and column offsets are
+      // uniform; rows are rrs = nx + 1 floats apart in LDS
       for (int e0 = wbase; e0 < plane; e0 += C::T) {
         const int k = __builtin_amdgcn_readfirstlane(e0 / nx);
         const int i0 = __builtin_amdgcn_readfirstlane(e0 - k * nx);
         __builtin_amdgcn_global_load_lds(Wl + (size_t)k * rs + (size_t)j * nx + i0 + lane,
-                                         (__attribute__((address_space(3))) void*)(m.extra + e0),
+                                         (__attribute__((address_space(3))) void*)(m.extra + k * rrs + i0),
                                          4, 0, 0);
       }
     } else {
@@ -310,7 +414,6 @@ __global__ __launch_bounds__(C::T) void conv_fwd_fft_c(const float* __restrict__
     }
   };
   if (j0 < j1) load_plane(j0);
-  const int KZ = nz + 2 * s.hb, IX = nx + 2 * s.ha;
   for (int j = j0; j < j1; ++j) {
     const float2* Pj = P + ((size_t)l * s.ny + j) * C::NS;
     float2 pr[C::KS], p0 = make_float2(0.f, 0.f), pn = make_float2(0.f, 0.f);
@@ -327,25 +430,9 @@ __global__ __launch_bounds__(C::T) void conv_fwd_fft_c(const float* __restrict__
     };
     __builtin_amdgcn_s_waitcnt(0);                 // this plane's loads into raw landed
     __syncthreads();                               // raw complete, A free, twiddles ready
-    // lanes on consecutive columns; each thread one column and a run of rows
-    if (tid < kStageGroups * C::Lx) {
-      const int cc = tid % C::Lx, grp = tid / C::Lx;
-      const int ii = clampi(cc - s.ha, 0, nx - 1);
-      const bool in_col = cc < IX;
-      const int r0 = grp * kStageRows, r1 = min(r0 + kStageRows, C::H);
-#pragma unroll 2
-      for (int r = r0; r < r1; ++r) {
-        float lo = 0.0f, hi = 0.0f;
-        if (in_col) {
-          if (r < KZ) lo = m.extra[clampi(r - s.hb, 0, nz - 1) * nx + ii];
-          if (r + C::H < KZ) hi = m.extra[clampi(r + C::H - s.hb, 0, nz - 1) * nx + ii];
-        }
-        m.A[r * C::ST + cc] = make_float2(lo, hi);
-      }
-    }
-    __syncthreads();                               // raw consumed
-    if (j + 1 < j1) load_plane(j + 1);
-    fft2_fwd<C>(m.A, m.twx, m.twz, load_p);
+    xpass_first_from_raw<C>(m.A, m.twx, m.extra, rrs, nx, nz, s.ha, s.hb);  // ends with a barrier
+    if (j + 1 < j1) load_plane(j + 1);             // raw consumed
+    fft2_fwd_rest<C>(m.A, m.twz, load_p);
 #pragma unroll
     for (int q = 0; q < C::KS; ++q) {
       const int sl = tid + q * C::T;
@@ -492,6 +579,7 @@ template <template <int> class CF>
 hipError_t launch_c(const Plan& p, int which, const void* in, void* out, int view0, int nvb,
                     hipStream_t st) {
   using CW = CF<1024>;   // transforms of one plane per workgroup pass
+  using CFW = CF<768>;   // forward convolution
   using CB = CF<512>;    // adjoint
   const FftShape& s = p.fft;
   char* ws = p.ws;
@@ -508,9 +596,9 @@ hipError_t launch_c(const Plan& p, int which, const void* in, void* out, int vie
       break;
     }
     case kFftForward: {
-      const size_t sm = smem_bytes<CW>(s.nz * s.nx);
-      if ((e = set_smem((const void*)conv_fwd_fft_c<CW>, sm)) != hipSuccess) return e;
-      hipLaunchKernelGGL(conv_fwd_fft_c<CW>, dim3((unsigned)(nvb * s.nchunk)), dim3(CW::T), sm, st,
+      const size_t sm = smem_bytes<CFW>(s.nz * raw_stride(s.nx));
+      if ((e = set_smem((const void*)conv_fwd_fft_c<CFW>, sm)) != hipSuccess) return e;
+      hipLaunchKernelGGL(conv_fwd_fft_c<CFW>, dim3((unsigned)(nvb * s.nchunk)), dim3(CFW::T), sm, st,
                          static_cast<const float*>(in), P, part, s, view0, nvb);
       break;
     }
@@ -543,7 +631,7 @@ hipError_t launch_c(const Plan& p, int which, const void* in, void* out, int vie
 template <class C>
 bool fits(const FftShape& s) {
   return s.Lx == C::Lx && s.Lz == C::Lz && s.nz * s.nx <= 16384 &&
-         smem_bytes<C>(s.nz * s.nx) <= kLdsBytes &&
+         smem_bytes<C>(s.nz * raw_stride(s.nx)) <= kLdsBytes &&
          smem_bytes<C>((s.nz + 2 * s.hb) * s.nx) <= kLdsBytes;
 }
 

@@ -1,7 +1,8 @@
 // Building blocks of the FFT convolution kernels (conv_fft.hip,
 // conv_fft_fixed.hip): complex arithmetic, R-point DFTs in registers for
 // R = 2, 3, 4, 5 and the composites 6, 8, 9, 10, 12, 15, and the stage
-// twiddles of one in-place pass.  Device code only.
+// twiddles of one in-place pass.  The arithmetic helpers are host-callable
+// too, so that the DFTs can be checked on the CPU.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,24 +19,24 @@ namespace fft {
 // far less.
 __device__ __forceinline__ int fdiv(int q, float rd) { return (int)(((float)q + 0.5f) * rd); }
 
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+__host__ __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__host__ __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__host__ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 // a * conj(b)
-__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+__host__ __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
   return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
-__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__host__ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 // i s a
-__device__ __forceinline__ float2 cimul(float2 a, float s) { return make_float2(-s * a.y, s * a.x); }
-__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__host__ __device__ __forceinline__ float2 cimul(float2 a, float s) { return make_float2(-s * a.y, s * a.x); }
+__host__ __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
 
 // R-point DFT in place, X[m] = sum_r v[r] exp(sg 2 pi i r m / R), sg = -1
 // (forward) or +1 (inverse).
 template <int R, bool kInv>
-__device__ __forceinline__ void dft(float2 (&v)[R]) {
+__host__ __device__ __forceinline__ void dft(float2 (&v)[R]) {
   constexpr float sg = kInv ? 1.0f : -1.0f;
   if constexpr (R == 2) {
     const float2 a = v[0], b = v[1];
@@ -107,11 +108,11 @@ constexpr double csin(double x) {
 constexpr double ccos(double x) { return csin(x + kTwoPi / 4); }
 
 template <class F, int... I>
-__device__ __forceinline__ void unroll_seq(F&& f, std::integer_sequence<int, I...>) {
+__host__ __device__ __forceinline__ void unroll_seq(F&& f, std::integer_sequence<int, I...>) {
   (f(std::integral_constant<int, I>()), ...);
 }
 template <int N, class F>
-__device__ __forceinline__ void unroll(F&& f) {
+__host__ __device__ __forceinline__ void unroll(F&& f) {
   unroll_seq(f, std::make_integer_sequence<int, N>());
 }
 
@@ -124,16 +125,41 @@ template <> struct Split<10> { static constexpr int a = 2, b = 5; };
 template <> struct Split<12> { static constexpr int a = 3, b = 4; };
 template <> struct Split<15> { static constexpr int a = 3, b = 5; };
 
+constexpr int gcd(int a, int b) { return b == 0 ? a : gcd(b, a % b); }
+// a^-1 mod m for gcd(a, m) = 1 (0 when m = 1).
+constexpr int modinv(int a, int m) {
+  for (int x = 1; x < m; ++x)
+    if ((a * x) % m == 1) return x;
+  return 0;
+}
+
 template <int R, bool kInv>
-__device__ __forceinline__ void dft_any(float2 (&v)[R]);
+__host__ __device__ __forceinline__ void dft_any(float2 (&v)[R]);
+
+// a exp(sg 2 pi i e / R) for a constant e, sg = -1 (forward) or +1 (inverse);
+// multiples of a quarter turn are exact sign changes and swaps.
+template <int e, int R, bool kInv>
+__host__ __device__ __forceinline__ float2 crot(float2 a) {
+  constexpr int q = e % R;
+  constexpr float sg = kInv ? 1.0f : -1.0f;
+  if constexpr (q == 0) {
+    return a;
+  } else if constexpr ((4 * q) % R == 0) {
+    constexpr int quarter = 4 * q / R;             // the angle is sg quarter pi / 2
+    if constexpr (quarter == 2) return make_float2(-a.x, -a.y);
+    else return cimul(a, quarter == 1 ? sg : -sg);
+  } else {
+    constexpr float c = (float)ccos(kTwoPi * q / R);
+    constexpr float sn = (float)csin((kInv ? 1.0 : -1.0) * kTwoPi * q / R);
+    return cmul(a, make_float2(c, sn));
+  }
+}
 
 // R-point DFT for R = Ra Rb in registers (Cooley-Tukey): input n = Rb n1 + n2,
 // Ra-point DFTs over n1, twiddles exp(sg 2 pi i n2 k1 / R), Rb-point DFTs over
 // n2, output k = k1 + Ra k2 (natural order).
 template <int Ra, int Rb, bool kInv>
-__device__ __forceinline__ void dft_comp(float2 (&v)[Ra * Rb]) {
-  constexpr int R = Ra * Rb;
-  constexpr double sg = kInv ? 1.0 : -1.0;
+__host__ __device__ __forceinline__ void dft_comp(float2 (&v)[Ra * Rb]) {
   float2 y[Ra][Rb];
   unroll<Rb>([&](auto n2c) {
     constexpr int n2 = decltype(n2c)::value;
@@ -142,14 +168,7 @@ __device__ __forceinline__ void dft_comp(float2 (&v)[Ra * Rb]) {
     dft_any<Ra, kInv>(t);
     unroll<Ra>([&](auto k1c) {
       constexpr int k1 = decltype(k1c)::value;
-      constexpr int e = (n2 * k1) % R;
-      if constexpr (e == 0) {
-        y[k1][n2] = t[k1];
-      } else {
-        constexpr float c = (float)ccos(kTwoPi * e / R);
-        constexpr float sn = (float)csin(sg * kTwoPi * e / R);
-        y[k1][n2] = cmul(t[k1], make_float2(c, sn));
-      }
+      y[k1][n2] = crot<n2 * k1, Ra * Rb, kInv>(t[k1]);
     });
   });
   unroll<Ra>([&](auto k1c) {
@@ -161,10 +180,47 @@ __device__ __forceinline__ void dft_comp(float2 (&v)[Ra * Rb]) {
   });
 }
 
+// R-point DFT for R = Ra Rb with coprime factors (Good-Thomas prime-factor
+// algorithm): input n = (Rb n1 + Ra n2) mod R, Ra-point DFTs over n1,
+// Rb-point DFTs over n2, output k = (Rb (Rb^-1 mod Ra) k1 + Ra (Ra^-1 mod Rb)
+// k2) mod R.  exp(2 pi i n k / R) then factors into exp(2 pi i n1 k1 / Ra)
+// exp(2 pi i n2 k2 / Rb): no twiddles between the two sets of DFTs.
+template <int Ra, int Rb, bool kInv>
+__host__ __device__ __forceinline__ void dft_pfa(float2 (&v)[Ra * Rb]) {
+  constexpr int R = Ra * Rb;
+  constexpr int ia = modinv(Rb % Ra, Ra), ib = modinv(Ra % Rb, Rb);
+  float2 y[Ra][Rb];
+  unroll<Rb>([&](auto n2c) {
+    constexpr int n2 = decltype(n2c)::value;
+    float2 t[Ra];
+    unroll<Ra>([&](auto n1c) {
+      constexpr int n1 = decltype(n1c)::value;
+      t[n1] = v[(Rb * n1 + Ra * n2) % R];
+    });
+    dft_any<Ra, kInv>(t);
+    unroll<Ra>([&](auto k1c) { y[decltype(k1c)::value][n2] = t[decltype(k1c)::value]; });
+  });
+  unroll<Ra>([&](auto k1c) {
+    constexpr int k1 = decltype(k1c)::value;
+    float2 t[Rb];
+    unroll<Rb>([&](auto n2c) { t[decltype(n2c)::value] = y[k1][decltype(n2c)::value]; });
+    dft_any<Rb, kInv>(t);
+    unroll<Rb>([&](auto k2c) {
+      constexpr int k2 = decltype(k2c)::value;
+      v[(Rb * ia * k1 + Ra * ib * k2) % R] = t[k2];
+    });
+  });
+}
+
 template <int R, bool kInv>
-__device__ __forceinline__ void dft_any(float2 (&v)[R]) {
-  if constexpr (R <= 5) dft<R, kInv>(v);
-  else dft_comp<Split<R>::a, Split<R>::b, kInv>(v);
+__host__ __device__ __forceinline__ void dft_any(float2 (&v)[R]) {
+  if constexpr (R <= 5) {
+    dft<R, kInv>(v);
+  } else {
+    constexpr int a = Split<R>::a, b = Split<R>::b;
+    if constexpr (gcd(a, b) == 1) dft_pfa<a, b, kInv>(v);
+    else dft_comp<a, b, kInv>(v);
+  }
 }
 
 // Element t of transform b: rows (b = row pair, along x) or virtual columns
@@ -182,30 +238,12 @@ struct ColAddr {
   }
 };
 
-// Stage twiddles w[r] = tw[r d] = exp(-2 pi i r d / N) for r < R (w[0] unused).
-// For R = Ra Rb, r = k1 + Ra k2: w[r] = tw[k1 d] tw[Ra k2 d], Ra + Rb - 2
-// table reads instead of R - 1 (one more FP32 rounding per twiddle).
+// Stage twiddles w[r] = tw[r d] = exp(-2 pi i r d / N) for r < R (w[0] unused),
+// read from the table (r d < N for every stage of a length-N transform).
 template <int R>
 __device__ __forceinline__ void stage_twiddles(float2 (&w)[R], const float2* tw, int d) {
-  if constexpr (R <= 5) {
 #pragma unroll
-    for (int r = 1; r < R; ++r) w[r] = tw[r * d];
-  } else {
-    constexpr int Ra = Split<R>::a, Rb = Split<R>::b;
-    float2 ta[Ra], tb[Rb];
-#pragma unroll
-    for (int k1 = 1; k1 < Ra; ++k1) ta[k1] = tw[k1 * d];
-#pragma unroll
-    for (int k2 = 1; k2 < Rb; ++k2) tb[k2] = tw[Ra * k2 * d];
-#pragma unroll
-    for (int k2 = 0; k2 < Rb; ++k2)
-#pragma unroll
-      for (int k1 = 0; k1 < Ra; ++k1) {
-        const int r = k1 + Ra * k2;
-        if (r == 0) continue;
-        w[r] = k2 == 0 ? ta[k1] : (k1 == 0 ? tb[k2] : cmul(ta[k1], tb[k2]));
-      }
-  }
+  for (int r = 1; r < R; ++r) w[r] = tw[r * d];
 }
 
 
