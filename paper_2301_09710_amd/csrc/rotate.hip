@@ -546,13 +546,17 @@ __global__ __launch_bounds__(NT) void rot_fwd_kernel(const float* __restrict__ x
 // a view's attenuation factors are requested before its staging and first two
 // passes, which cover their latency.
 //
-// Guarded buffer: cell (i, j), -1 <= i, j <= n, at Yd[j S + i] with
-// Yd = Y + S + 1 and S = guarded_stride(n) (odd, >= n + 2): rows and columns
-// -1 and n are zero.
-__host__ __device__ __forceinline__ int guarded_stride(int n) { return (n + 2) | 1; }
-__host__ __device__ __forceinline__ int guarded_floats(int n) { return (n + 2) * guarded_stride(n); }
+// Guarded buffer: cell (i, j), -2 <= i, j <= n + 1, at Yd[j S + i] with
+// Yd = Y + 2 S + 2 and S = guarded_stride(n) (odd, >= n + 4): rows and
+// columns -2, -1, n and n + 1 are zero.  A two-tap sample at positions p and
+// p + 1 reads cells (c, c + 1) with c = clamp(p, -2, n): both taps are exact
+// (zero outside [0, n)) for every p, so one clamp serves both taps and the
+// two reads are adjacent.
+__host__ __device__ __forceinline__ int guarded_stride(int n) { return (n + 4) | 1; }
+__host__ __device__ __forceinline__ int guarded_floats(int n) { return (n + 4) * guarded_stride(n); }
+__host__ __device__ __forceinline__ int guarded_origin(int n) { return 2 * guarded_stride(n) + 2; }
 
-__device__ __forceinline__ int clamp_guard(int q, int n) { return min(max(q, -1), n); }
+__device__ __forceinline__ int clamp_guard(int q, int n) { return min(max(q, -2), n); }
 
 // Cell of pixel (i, j) under P_m (the position quarter_dst gives) in a
 // buffer of row stride S: qb + qi i + qj j.
@@ -566,7 +570,8 @@ __device__ __forceinline__ void quarter_cell(int m, int n, int S, int& qb, int& 
 // In-place shear of the lines a wave owns (rows: along i with the per-row
 // entries, kRows = false: along j with the per-column entries), forward
 // (kSgn = +1: out[q] = w.x in[q + o] + w.y in[q + o + 1]) or transposed
-// (kSgn = -1: out[q] = w.x in[q - o] + w.y in[q - o - 1]).
+// (kSgn = -1: out[q] = w.x in[q - o] + w.y in[q - o - 1]); the lower tap of
+// the pair sits at c = clamp(q + o) or clamp(q - o - 1).
 template <int kSgn, bool kRows, int EPL, int LPW>
 __device__ __forceinline__ void guarded_pass(float* Yd, int n, int S, const TabEntry* lines) {
   const int lane = lane_id(), w = wave_id();
@@ -579,10 +584,10 @@ __device__ __forceinline__ void guarded_pass(float* Yd, int n, int S, const TabE
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
       const int q = lane + 64 * e;
-      const int qa = clamp_guard(q + kSgn * te.o, n), qb = clamp_guard(q + kSgn * (te.o + 1), n);
-      const float a = kRows ? Yd[L * S + qa] : Yd[qa * S + L];
-      const float b = kRows ? Yd[L * S + qb] : Yd[qb * S + L];
-      v[e] = te.w.x * a + te.w.y * b;
+      const int c = clamp_guard(kSgn > 0 ? q + te.o : q - te.o - 1, n);
+      const float lo = kRows ? Yd[L * S + c] : Yd[c * S + L];
+      const float hi = kRows ? Yd[L * S + c + 1] : Yd[(c + 1) * S + L];
+      v[e] = kSgn > 0 ? te.w.x * lo + te.w.y * hi : te.w.x * hi + te.w.y * lo;
     }
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
@@ -602,7 +607,7 @@ __global__ __launch_bounds__(NT) void rot_fwd_lines_kernel(const float* __restri
                                                            int view0, int nvb, int VG, Tables tab) {
   extern __shared__ float smem[];
   const int S = guarded_stride(n);
-  float* Yd = smem + S + 1;
+  float* Yd = smem + guarded_origin(n);
   ViewTab t = carve_tab(smem + round4(guarded_floats(n)), n);
   const int k = blockIdx.x, lane = lane_id(), w = wave_id();
   const size_t nn = (size_t)n * n, N = nn * nz;
@@ -656,8 +661,8 @@ __global__ __launch_bounds__(NT) void rot_fwd_lines_kernel(const float* __restri
 #pragma unroll
       for (int e = 0; e < EPL; ++e) {
         const int i = lane + 64 * e;
-        const int qa = clamp_guard(i + te.o, n), qb2 = clamp_guard(i + te.o + 1, n);
-        const float v = te.w.x * Yd[j * S + qa] + te.w.y * Yd[j * S + qb2];
+        const int c = clamp_guard(i + te.o, n);
+        const float v = te.w.x * Yd[j * S + c] + te.w.y * Yd[j * S + c + 1];
         if (i < n) dst[pix + NW * n * r + 64 * e] = v * mbv[r][e];
       }
     }
@@ -680,7 +685,7 @@ __global__ __launch_bounds__(NT) void rot_back_lines_kernel(const float* __restr
                                                             int accumulate, Tables tab) {
   extern __shared__ float smem[];
   const int S = guarded_stride(n);
-  float* Yd = smem + S + 1;
+  float* Yd = smem + guarded_origin(n);
   ViewTab t = carve_tab(smem + round4(guarded_floats(n)), n);
   const int k = blockIdx.x, g = blockIdx.y, lane = lane_id(), w = wave_id();
   const size_t nn = (size_t)n * n, N = nn * nz;
