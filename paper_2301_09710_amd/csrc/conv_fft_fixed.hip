@@ -64,9 +64,9 @@ struct Cfg {
 
 // 128 x 80 planes with 37 x 37 PSFs, and 64 x 40 planes with 19 x 19 PSFs.
 // The convolution kernels keep spectra per thread in registers (the forward
-// its accumulators and the next PSF spectrum, the adjoint the view's
-// projection and the next PSF spectrum), so they run 768 and 512 threads
-// (170 and 256 registers per lane); the once-per-view kernels run 1024.
+// its accumulators and the next PSF spectrum, the adjoint the next PSF
+// spectrum), so they run 768 threads (170 registers per lane); the
+// once-per-view kernels run 1024.
 template <int T> using Cfg180x120 = Cfg<180, 120, 15, 12, 12, 10, T>;
 template <int T> using Cfg90x60 = Cfg<90, 60, 9, 10, 10, 6, T>;
 
@@ -526,15 +526,11 @@ __global__ __launch_bounds__(C::T) void conv_back_fft_c(const float2* __restrict
   chunk_range(c, s.nchunk_back, s.ny, j0, j1);
   m.setup();
   const int tid = threadIdx.x, nx = s.nx, nz = s.nz;
-  // the view's projection spectrum stays in registers; the PSF spectrum of
-  // the next plane is loaded into registers during this plane's transform
+  // the PSF spectrum of the next plane is loaded into registers during this
+  // plane's transform; the view's projection spectrum (86 KB at 180 x 120)
+  // is read per plane, from L2 after the first
   const float2* Vl = V + (size_t)lb * C::NS;
-  float2 vr[C::KS], v0 = make_float2(0.f, 0.f), vn = make_float2(0.f, 0.f);
-#pragma unroll
-  for (int q = 0; q < C::KS; ++q) {
-    const int sl = tid + q * C::T;
-    if (sl < C::NR) vr[q] = Vl[sl];
-  }
+  float2 v0 = make_float2(0.f, 0.f), vn = make_float2(0.f, 0.f);
   if (tid <= C::H) {
     v0 = Vl[C::NR + 2 * tid];
     vn = Vl[C::NR + 2 * tid + 1];
@@ -560,7 +556,7 @@ __global__ __launch_bounds__(C::T) void conv_back_fft_c(const float2* __restrict
 #pragma unroll
     for (int q = 0; q < C::KS; ++q) {
       const int sl = tid + q * C::T;
-      if (sl < C::NR) m.A[C::slot(sl)] = cmulc(vr[q], pr[q]);
+      if (sl < C::NR) m.A[C::slot(sl)] = cmulc(Vl[sl], pr[q]);
     }
     if (tid <= C::H) pack_col0<C>(m.A, tid, cmulc(v0, p0), cmulc(vn, pn));
     __syncthreads();
@@ -580,7 +576,7 @@ hipError_t launch_c(const Plan& p, int which, const void* in, void* out, int vie
                     hipStream_t st) {
   using CW = CF<1024>;   // transforms of one plane per workgroup pass
   using CFW = CF<768>;   // forward convolution
-  using CB = CF<512>;    // adjoint
+  using CB = CF<768>;    // adjoint
   const FftShape& s = p.fft;
   char* ws = p.ws;
   const float2* P = reinterpret_cast<const float2*>(ws + p.lay.fft_spectra);
