@@ -119,14 +119,17 @@ def traffic_for(kernel):
         return None
 
 
-def fft_flop_per_plane(Lx, Lz, mac):
+def fft_flop_per_plane(Lx, Lz, mac, real=False):
     """Algorithmic work of one plane of the FFT convolution: the real
     two-dimensional transform of Lx x Lz points counted as 2.5 N log2 N
     (N = Lx Lz), plus the spectral product over the Lz (Lx/2 + 1) bins of the
-    half spectrum (8 FLOP with accumulation, 6 without)."""
+    half spectrum: a complex product (6 FLOP, 8 with the accumulation of the
+    depth sum) or, with the real spectra of symmetric PSFs, a real one (2,
+    or 4 with the accumulation)."""
     import math
     n = Lx * Lz
-    return 2.5 * n * math.log2(n) + (8.0 if mac else 6.0) * Lz * (Lx // 2 + 1)
+    per_bin = (4.0 if mac else 2.0) if real else (8.0 if mac else 6.0)
+    return 2.5 * n * math.log2(n) + per_bin * Lz * (Lx // 2 + 1)
 
 
 def conv_roofline(kern_name, avg_ms, sel, nview, ny, op_flops, conv_flops, mirror):
@@ -134,7 +137,8 @@ def conv_roofline(kern_name, avg_ms, sel, nview, ny, op_flops, conv_flops, mirro
     the FP32 vector ALUs (no packed FP32) for the FFT form."""
     if kern_name in ("conv_fwd_fft", "conv_back_fft"):
         Lx, Lz = (int(t) for t in sel["fft_size"].split("x"))
-        flops = nview * ny * fft_flop_per_plane(Lx, Lz, kern_name == "conv_fwd_fft")
+        flops = nview * ny * fft_flop_per_plane(Lx, Lz, kern_name == "conv_fwd_fft",
+                                                sel.get("fft_real") == "1")
         a = flops / (avg_ms * 1e-3) / 1e12
         return {"kernel": kern_name, "bound": "alu", "achieved": a, "peak": FP32_VALU_TFLOPS,
                 "unit": "TFLOP/s", "frac": a / FP32_VALU_TFLOPS, "traffic": traffic_for(kern_name),
@@ -234,8 +238,15 @@ def main():
     xd = torch.from_numpy(x).to(dev)
     mud = torch.from_numpy(mu).to(dev)
     psfd = torch.from_numpy(psf).to(dev)
-    plan = spect.Plan(mud, psfd, dy, cache_mubar=bool(args.cache_mubar), method=args.method)
-    sel = plan.describe()            # kernels chosen (the Gaussian PSF rows are symmetric in x)
+    # The Gaussian PSFs are symmetric in x and in z (checked here on the host,
+    # exactly): the plan is told so (SPECT_PSF_SYMMETRIC_X | _Z), which pairs
+    # mirror-image taps on the direct path and keeps real spectra on the FFT path.
+    sym_x = bool(np.array_equal(psf, psf[..., ::-1]))
+    sym_z = bool(np.array_equal(psf, psf[..., ::-1, :]))
+    sym_kw = dict(mirror="assume" if sym_x else "auto", symmetric_z=sym_z)
+    plan = spect.Plan(mud, psfd, dy, cache_mubar=bool(args.cache_mubar), method=args.method,
+                      **sym_kw)
+    sel = plan.describe()            # kernels chosen
     vd = torch.empty(plan.proj_shape, dtype=torch.float32, device=dev)
     bd = torch.empty(plan.vol_shape, dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
@@ -272,7 +283,6 @@ def main():
     # mirror-image tap pairing the matrix cores take 2 (px + 1) / 2 pz (the
     # pre-adds of the two input columns run on the vector ALUs)
     op_flops = 2.0 * px * pz * N * views_per_launch
-    sym_x = bool(np.array_equal(psf, psf[..., ::-1]))
     paired_flops = 2.0 * ((px + 1) // 2) * pz * N * views_per_launch
     mirror = sel.get("mirror") == "1"
     conv_flops = paired_flops if mirror else op_flops
@@ -345,7 +355,7 @@ def main():
     note("direct_steps")
     if args.direct_steps > 0:
         om = "direct" if args.method == "fft" else "fft"
-        pl = spect.Plan(mud, psfd, dy, cache_mubar=bool(args.cache_mubar), method=om)
+        pl = spect.Plan(mud, psfd, dy, cache_mubar=bool(args.cache_mubar), method=om, **sym_kw)
         osel = pl.describe()
         ms, kav = time_pairs(torch, pl, xd, args.direct_steps, args.warmup, vd.shape)
         v2 = pl.forward(xd)
@@ -403,7 +413,7 @@ def main():
     uncached = None
     note("uncached_steps")
     if args.uncached_steps > 0:
-        pl = spect.Plan(mud, psfd, dy, cache_mubar=False, method=args.method)
+        pl = spect.Plan(mud, psfd, dy, cache_mubar=False, method=args.method, **sym_kw)
         v2 = torch.empty_like(vd)
         b2 = torch.empty_like(bd)
         for _ in range(args.warmup):
@@ -490,7 +500,7 @@ def main():
     note("bilinear_steps")
     if args.bilinear_steps > 0:
         pl = spect.Plan(mud, psfd, dy, cache_mubar=bool(args.cache_mubar), rotation="bilinear",
-                        method=args.method)
+                        method=args.method, **sym_kw)
         v2 = torch.empty_like(vd)
         b2 = torch.empty_like(bd)
         for _ in range(args.warmup):
@@ -706,6 +716,7 @@ def main():
                    "method": args.method,
                    "nx": nx, "ny": ny, "nz": nz, "nview": nview, "px": px, "pz": pz,
                    "cache_mubar": bool(args.cache_mubar), "plan": sel,
+                   "psf_symmetry_stated": ("x" if sym_x else "") + ("z" if sym_z else ""),
                    "workspace_bytes": plan.ws_bytes,
                    "mubar_cache_bytes": (nview * nx * ny * nz * 4) if args.cache_mubar else 0},
         "uncached_mubar": uncached,

@@ -123,6 +123,18 @@ typedef enum {
                                    outputs carry rounding noise of either sign, of the order
                                    of 1e-7 times the largest output: clamp them before a use
                                    that needs nonnegative values (a Poisson rate). */
+#define SPECT_PSF_SYMMETRIC_Z 0x100u /* the caller states that every PSF column is its own
+                                        mirror image in z, p[b][a] == p[pz-1-b][a].  With
+                                        SPECT_CONV_FFT and SPECT_PSF_SYMMETRIC_X too, on the
+                                        transform sizes compiled in (spect_plan_describe
+                                        reports fft_fixed other than 0), the plan keeps the
+                                        spectra of the PSFs centred on the origin, which are
+                                        then real (one float per bin instead of two: half the
+                                        spectra's workspace and traffic, a real product per
+                                        bin).  With a PSF that is not symmetric in both, the
+                                        operator is that of its point-symmetric part
+                                        (p[b][a] + p[pz-1-b][px-1-a]) / 2.  Ignored
+                                        otherwise. */
 
 /* Geometry of one plan (host struct, copied by spect_plan_create). */
 typedef struct {
@@ -135,8 +147,8 @@ typedef struct {
                              during spect_plan_create */
   uint32_t flags;         /* SPECT_CACHE_MUBAR | SPECT_ROT_BILINEAR | SPECT_PSF_SEPARABLE |
                              SPECT_PSF_ALL_TAPS | SPECT_PSF_SYMMETRIC_X | SPECT_TILING_4X4 |
-                             SPECT_TILING_16X16 | SPECT_CONV_FFT, or 0; other bits give
-                             SPECT_ERR_VALUE */
+                             SPECT_TILING_16X16 | SPECT_CONV_FFT | SPECT_PSF_SYMMETRIC_Z,
+                             or 0; other bits give SPECT_ERR_VALUE */
   int32_t view_batch;     /* views processed per internal batch; 0 = all.
                              Smaller batches need less workspace. */
   int32_t conv_precision; /* SPECT_CONV_FP32 (0), SPECT_CONV_BF16, SPECT_CONV_FP16 or
@@ -228,7 +240,9 @@ spect_status spect_em_step_vjp(spect_plan plan, const float* d_x, const float* d
  * keeps the last call's contents: calls that overlap on one device race.
  * Restrictions: g->angles must be NULL (default angles; else
  * SPECT_ERR_UNSUPPORTED); SPECT_CACHE_MUBAR is ignored; mirror-image taps are
- * paired only with SPECT_PSF_SYMMETRIC_X (no device check).  d_mu
+ * paired only with SPECT_PSF_SYMMETRIC_X (no device check); with
+ * SPECT_CONV_FFT the PSF spectra are computed in the array on every call
+ * (they count in spect_workspace_bytes whatever the view batch).  d_mu
  * [nz][ny][nx], d_psf as for spect_plan_create, d_x [nz][ny][nx], d_v
  * [nview][nz][nx] (overwritten); all 4-byte aligned.  The first call on a
  * device looks up the array's address there (hipGetSymbolAddress). */

@@ -732,6 +732,7 @@ FftShape make_fft_shape(const spect_geom& g) {
             fft_smem(s, 2) <= kLdsBytes;
   s.cfg = fft_fixed_config(s);
   s.ok = ok || s.cfg != 0;
+  s.real = s.cfg != 0 && (g.flags & SPECT_PSF_SYMMETRIC_X) && (g.flags & SPECT_PSF_SYMMETRIC_Z);
   return s;
 }
 

@@ -305,6 +305,19 @@ __device__ __forceinline__ void pack_col0(float2* A, int zq, float2 x0, float2 x
   }
 }
 
+// Real spectra (PSFs symmetric in x and z, centred on the origin): the real
+// parts, one float per slot.
+template <class C>
+__device__ __forceinline__ void store_slots_real(const float2* A, float* out, float scale) {
+  for (int q = threadIdx.x; q < C::NR; q += C::T) out[q] = A[C::slot(q)].x * scale;
+  for (int zq = threadIdx.x; zq <= C::H; zq += C::T) {
+    float2 x0, xn;
+    unpack_col0<C>(A, zq, &x0, &xn);
+    out[C::NR + 2 * zq] = x0.x * scale;
+    out[C::NR + 2 * zq + 1] = xn.x * scale;
+  }
+}
+
 template <class C>
 __device__ __forceinline__ void store_slots(const float2* A, float2* out, float scale) {
   for (int q = threadIdx.x; q < C::NR; q += C::T) out[q] = cscale(A[C::slot(q)], scale);
@@ -348,29 +361,47 @@ constexpr size_t smem_bytes(int extra_floats) {
 }
 
 // ---------------------------------------------------------------- kernels
+// kReal: the PSFs are symmetric in x and in z.  Their spectra are then taken
+// of the PSF centred on the origin (tap (b, a) at ((b - hb) mod Lz,
+// (a - ha) mod Lx)), which are real and even, and kept as one float per
+// slot; the centring moves the kept bins of the forward from
+// (k + 2 hb, i + 2 ha) to (k + hb, i + ha) and the adjoint's projection
+// from (2 hb, 2 ha) to (hb, ha).  Otherwise complex spectra of the PSF at
+// the corner.
+template <bool kReal> using Spec = std::conditional_t<kReal, float, float2>;
+__device__ __forceinline__ float2 spec_mul(float p, float2 a) { return cscale(a, p); }
+__device__ __forceinline__ float2 spec_mul(float2 p, float2 a) { return cmul(p, a); }
+// a * conj(p)
+__device__ __forceinline__ float2 spec_mulc(float2 a, float p) { return cscale(a, p); }
+__device__ __forceinline__ float2 spec_mulc(float2 a, float2 p) { return cmulc(a, p); }
 
-template <class C>
+template <class C, bool kReal>
 __global__ __launch_bounds__(C::T) void psf_spectra_c(const float* __restrict__ psf,
-                                                    float2* __restrict__ P, FftShape s) {
+                                                    Spec<kReal>* __restrict__ P, FftShape s) {
   extern __shared__ float2 sm2[];
   const Lds<C> m(sm2);
   const int jl = blockIdx.x;
   const float* p = psf + (size_t)jl * s.pz * s.px;
   m.setup();
+  // tap row (column) of plane row q (column c): q itself, or (q + hb) mod Lz centred
+  auto tap = [](int q, int h, int L) { return kReal ? (q + h < L ? q + h : q + h - L) : q; };
   for (int e = threadIdx.x; e < C::H * C::Lx; e += C::T) {
     const int r = e / C::Lx, c = e - r * C::Lx;
-    const float lo = (r < s.pz && c < s.px) ? p[r * s.px + c] : 0.0f;
-    const float hi = (r + C::H < s.pz && c < s.px) ? p[(r + C::H) * s.px + c] : 0.0f;
+    const int a = tap(c, s.ha, C::Lx), b1 = tap(r, s.hb, C::Lz), b2 = tap(r + C::H, s.hb, C::Lz);
+    const float lo = (b1 < s.pz && a < s.px) ? p[b1 * s.px + a] : 0.0f;
+    const float hi = (b2 < s.pz && a < s.px) ? p[b2 * s.px + a] : 0.0f;
     m.A[r * C::ST + c] = make_float2(lo, hi);
   }
   __syncthreads();
   fft2_fwd<C>(m.A, m.twx, m.twz, [] {});
-  store_slots<C>(m.A, P + (size_t)jl * C::NS, 1.0f / ((float)C::Lx * (float)C::Lz));
+  const float scale = 1.0f / ((float)C::Lx * (float)C::Lz);
+  if constexpr (kReal) store_slots_real<C>(m.A, P + (size_t)jl * C::NS, scale);
+  else store_slots<C>(m.A, P + (size_t)jl * C::NS, scale);
 }
 
-template <class C>
+template <class C, bool kReal>
 __global__ __launch_bounds__(C::T) void conv_fwd_fft_c(const float* __restrict__ W,
-                                                     const float2* __restrict__ P,
+                                                     const Spec<kReal>* __restrict__ P,
                                                      float2* __restrict__ part, FftShape s,
                                                      int view0, int nvb) {
   extern __shared__ float2 sm2[];
@@ -415,8 +446,8 @@ __global__ __launch_bounds__(C::T) void conv_fwd_fft_c(const float* __restrict__
   };
   if (j0 < j1) load_plane(j0);
   for (int j = j0; j < j1; ++j) {
-    const float2* Pj = P + ((size_t)l * s.ny + j) * C::NS;
-    float2 pr[C::KS], p0 = make_float2(0.f, 0.f), pn = make_float2(0.f, 0.f);
+    const Spec<kReal>* Pj = P + ((size_t)l * s.ny + j) * C::NS;
+    Spec<kReal> pr[C::KS], p0 = Spec<kReal>{}, pn = Spec<kReal>{};
     auto load_p = [&] {
 #pragma unroll
       for (int q = 0; q < C::KS; ++q) {
@@ -438,15 +469,20 @@ __global__ __launch_bounds__(C::T) void conv_fwd_fft_c(const float* __restrict__
       const int sl = tid + q * C::T;
       if (sl < C::NR) {
         const float2 f = m.A[C::slot(sl)];
-        acc[q].x += pr[q].x * f.x - pr[q].y * f.y;
-        acc[q].y += pr[q].x * f.y + pr[q].y * f.x;
+        if constexpr (kReal) {
+          acc[q].x += pr[q] * f.x;
+          acc[q].y += pr[q] * f.y;
+        } else {
+          acc[q].x += pr[q].x * f.x - pr[q].y * f.y;
+          acc[q].y += pr[q].x * f.y + pr[q].y * f.x;
+        }
       }
     }
     if (tid <= C::H) {
       float2 x0, xn;
       unpack_col0<C>(m.A, tid, &x0, &xn);
-      a0 = cadd(a0, cmul(p0, x0));
-      an = cadd(an, cmul(pn, xn));
+      a0 = cadd(a0, spec_mul(p0, x0));
+      an = cadd(an, spec_mul(pn, xn));
     }
   }
   float2* out = part + ((size_t)c * nvb + lb) * C::NS;
@@ -461,7 +497,7 @@ __global__ __launch_bounds__(C::T) void conv_fwd_fft_c(const float* __restrict__
   }
 }
 
-template <class C>
+template <class C, bool kReal>
 __global__ __launch_bounds__(C::T) void fwd_fft_finish_c(const float2* __restrict__ part,
                                                        float* __restrict__ v, FftShape s,
                                                        int view0, int nvb) {
@@ -488,11 +524,12 @@ __global__ __launch_bounds__(C::T) void fwd_fft_finish_c(const float2* __restric
   const float rnx = 1.0f / (float)s.nx;
   for (int e = tid; e < s.nz * s.nx; e += C::T) {
     const int k = fdiv(e, rnx), i = e - k * s.nx;
-    v[((size_t)l * s.nz + k) * s.nx + i] = plane_at<C>(m.A, k + 2 * s.hb, i + 2 * s.ha);
+    v[((size_t)l * s.nz + k) * s.nx + i] =
+        plane_at<C>(m.A, k + (kReal ? 1 : 2) * s.hb, i + (kReal ? 1 : 2) * s.ha);
   }
 }
 
-template <class C>
+template <class C, bool kReal>
 __global__ __launch_bounds__(C::T) void back_fft_prep_c(const float* __restrict__ v,
                                                       float2* __restrict__ V, FftShape s,
                                                       int view0) {
@@ -503,7 +540,8 @@ __global__ __launch_bounds__(C::T) void back_fft_prep_c(const float* __restrict_
   const float* vl = v + (size_t)l * s.nz * s.nx;
   for (int e = threadIdx.x; e < C::H * C::Lx; e += C::T) {
     const int r = e / C::Lx, cc = e - r * C::Lx;
-    const int i = cc - 2 * s.ha, k1 = r - 2 * s.hb, k2 = r + C::H - 2 * s.hb;
+    const int oa = (kReal ? 1 : 2) * s.ha, ob = (kReal ? 1 : 2) * s.hb;
+    const int i = cc - oa, k1 = r - ob, k2 = r + C::H - ob;
     const bool in_i = i >= 0 && i < s.nx;
     const float lo = (in_i && k1 >= 0 && k1 < s.nz) ? vl[k1 * s.nx + i] : 0.0f;
     const float hi = (in_i && k2 >= 0 && k2 < s.nz) ? vl[k2 * s.nx + i] : 0.0f;
@@ -514,9 +552,9 @@ __global__ __launch_bounds__(C::T) void back_fft_prep_c(const float* __restrict_
   store_slots<C>(m.A, V + (size_t)lb * C::NS, 1.0f);
 }
 
-template <class C>
+template <class C, bool kReal>
 __global__ __launch_bounds__(C::T) void conv_back_fft_c(const float2* __restrict__ V,
-                                                      const float2* __restrict__ P,
+                                                      const Spec<kReal>* __restrict__ P,
                                                       float* __restrict__ U, FftShape s, int view0,
                                                       int nvb) {
   extern __shared__ float2 sm2[];
@@ -537,9 +575,9 @@ __global__ __launch_bounds__(C::T) void conv_back_fft_c(const float2* __restrict
   }
   const size_t rs = (size_t)s.ny * nx;
   float* Ul = U + (size_t)lb * nz * rs;
-  float2 pr[C::KS], p0 = make_float2(0.f, 0.f), pn = make_float2(0.f, 0.f);
+  Spec<kReal> pr[C::KS], p0 = Spec<kReal>{}, pn = Spec<kReal>{};
   auto load_p = [&](int j) {
-    const float2* Pj = P + ((size_t)l * s.ny + j) * C::NS;
+    const Spec<kReal>* Pj = P + ((size_t)l * s.ny + j) * C::NS;
 #pragma unroll
     for (int q = 0; q < C::KS; ++q) {
       const int sl = tid + q * C::T;
@@ -556,9 +594,9 @@ __global__ __launch_bounds__(C::T) void conv_back_fft_c(const float2* __restrict
 #pragma unroll
     for (int q = 0; q < C::KS; ++q) {
       const int sl = tid + q * C::T;
-      if (sl < C::NR) m.A[C::slot(sl)] = cmulc(Vl[sl], pr[q]);
+      if (sl < C::NR) m.A[C::slot(sl)] = spec_mulc(Vl[sl], pr[q]);
     }
-    if (tid <= C::H) pack_col0<C>(m.A, tid, cmulc(v0, p0), cmulc(vn, pn));
+    if (tid <= C::H) pack_col0<C>(m.A, tid, spec_mulc(v0, p0), spec_mulc(vn, pn));
     __syncthreads();
     if (j + 1 < j1) load_p(j + 1);                 // the next plane's spectrum, during this one
     fft2_inv<C>(m.A, m.twx, m.twz);
@@ -571,57 +609,65 @@ hipError_t set_smem(const void* fn, size_t sm) {
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
 }
 
-template <template <int> class CF>
-hipError_t launch_c(const Plan& p, int which, const void* in, void* out, int view0, int nvb,
-                    hipStream_t st) {
+template <template <int> class CF, bool kReal>
+hipError_t launch_cr(const Plan& p, int which, const void* in, void* out, int view0, int nvb,
+                     hipStream_t st) {
   using CW = CF<1024>;   // transforms of one plane per workgroup pass
   using CFW = CF<768>;   // forward convolution
   using CB = CF<768>;    // adjoint
   const FftShape& s = p.fft;
   char* ws = p.ws;
-  const float2* P = reinterpret_cast<const float2*>(ws + p.lay.fft_spectra);
+  Spec<kReal>* P = reinterpret_cast<Spec<kReal>*>(ws + p.lay.fft_spectra);
   float2* part = reinterpret_cast<float2*>(ws + p.lay.fft_part);
   float2* V = reinterpret_cast<float2*>(ws + p.lay.fft_vproj);
   hipError_t e = hipSuccess;
   switch (which) {
     case kFftSpectra: {
       const size_t sm = smem_bytes<CW>(0);
-      if ((e = set_smem((const void*)psf_spectra_c<CW>, sm)) != hipSuccess) return e;
-      hipLaunchKernelGGL(psf_spectra_c<CW>, dim3((unsigned)(p.g.nview * p.g.ny)), dim3(CW::T), sm,
-                         st, p.psf, reinterpret_cast<float2*>(ws + p.lay.fft_spectra), s);
+      if ((e = set_smem((const void*)psf_spectra_c<CW, kReal>, sm)) != hipSuccess) return e;
+      hipLaunchKernelGGL((psf_spectra_c<CW, kReal>), dim3((unsigned)(p.g.nview * p.g.ny)),
+                         dim3(CW::T), sm, st, p.psf, P, s);
       break;
     }
     case kFftForward: {
       const size_t sm = smem_bytes<CFW>(s.nz * raw_stride(s.nx));
-      if ((e = set_smem((const void*)conv_fwd_fft_c<CFW>, sm)) != hipSuccess) return e;
-      hipLaunchKernelGGL(conv_fwd_fft_c<CFW>, dim3((unsigned)(nvb * s.nchunk)), dim3(CFW::T), sm, st,
-                         static_cast<const float*>(in), P, part, s, view0, nvb);
+      if ((e = set_smem((const void*)conv_fwd_fft_c<CFW, kReal>, sm)) != hipSuccess) return e;
+      hipLaunchKernelGGL((conv_fwd_fft_c<CFW, kReal>), dim3((unsigned)(nvb * s.nchunk)),
+                         dim3(CFW::T), sm, st, static_cast<const float*>(in), P, part, s, view0,
+                         nvb);
       break;
     }
     case kFftFinish: {
       const size_t sm = smem_bytes<CW>(0);
-      if ((e = set_smem((const void*)fwd_fft_finish_c<CW>, sm)) != hipSuccess) return e;
-      hipLaunchKernelGGL(fwd_fft_finish_c<CW>, dim3((unsigned)nvb), dim3(CW::T), sm, st, part,
-                         static_cast<float*>(out), s, view0, nvb);
+      if ((e = set_smem((const void*)fwd_fft_finish_c<CW, kReal>, sm)) != hipSuccess) return e;
+      hipLaunchKernelGGL((fwd_fft_finish_c<CW, kReal>), dim3((unsigned)nvb), dim3(CW::T), sm, st,
+                         part, static_cast<float*>(out), s, view0, nvb);
       break;
     }
     case kFftBackPrep: {
       const size_t sm = smem_bytes<CW>(0);
-      if ((e = set_smem((const void*)back_fft_prep_c<CW>, sm)) != hipSuccess) return e;
-      hipLaunchKernelGGL(back_fft_prep_c<CW>, dim3((unsigned)nvb), dim3(CW::T), sm, st,
+      if ((e = set_smem((const void*)back_fft_prep_c<CW, kReal>, sm)) != hipSuccess) return e;
+      hipLaunchKernelGGL((back_fft_prep_c<CW, kReal>), dim3((unsigned)nvb), dim3(CW::T), sm, st,
                          static_cast<const float*>(in), V, s, view0);
       break;
     }
     case kFftBack: {
       const size_t sm = smem_bytes<CB>((s.nz + 2 * s.hb) * s.nx);
-      if ((e = set_smem((const void*)conv_back_fft_c<CB>, sm)) != hipSuccess) return e;
-      hipLaunchKernelGGL(conv_back_fft_c<CB>, dim3((unsigned)(nvb * s.nchunk_back)), dim3(CB::T),
-                         sm, st, V, P, static_cast<float*>(out), s, view0, nvb);
+      if ((e = set_smem((const void*)conv_back_fft_c<CB, kReal>, sm)) != hipSuccess) return e;
+      hipLaunchKernelGGL((conv_back_fft_c<CB, kReal>), dim3((unsigned)(nvb * s.nchunk_back)),
+                         dim3(CB::T), sm, st, V, P, static_cast<float*>(out), s, view0, nvb);
       break;
     }
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <template <int> class CF>
+hipError_t launch_c(const Plan& p, int which, const void* in, void* out, int view0, int nvb,
+                    hipStream_t st) {
+  return p.fft.real ? launch_cr<CF, true>(p, which, in, out, view0, nvb, st)
+                    : launch_cr<CF, false>(p, which, in, out, view0, nvb, st);
 }
 
 template <class C>

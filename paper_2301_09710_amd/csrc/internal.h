@@ -98,6 +98,7 @@ struct FftShape {
   float r_lx, r_lh, r_lh1, r_nx;  // 1 / Lx, 1 / Lh, 1 / (Lh - 1), 1 / nx
   int nchunk, nchunk_back;
   int cfg;                // transform sizes fixed at compile time (conv_fft_fixed.hip), 0: none
+  bool real;              // PSFs symmetric in x and z (flags), fixed sizes: real spectra
   bool ok;                // fits the kernels' registers and LDS
 };
 // The FFT convolution's kernels (launch_fft_fixed's `which`).

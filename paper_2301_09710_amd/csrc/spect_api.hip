@@ -21,7 +21,7 @@ static spect_status validate(const spect_geom* g) {
   if (!(std::isfinite(g->dy) && g->dy > 0.0)) return SPECT_ERR_VALUE;
   if (g->flags & ~(SPECT_CACHE_MUBAR | SPECT_ROT_BILINEAR | SPECT_PSF_SEPARABLE |
                    SPECT_PSF_ALL_TAPS | SPECT_PSF_SYMMETRIC_X | SPECT_TILING_4X4 |
-                   SPECT_TILING_16X16 | SPECT_CONV_FFT))
+                   SPECT_TILING_16X16 | SPECT_CONV_FFT | SPECT_PSF_SYMMETRIC_Z))
     return SPECT_ERR_VALUE;
   if ((g->flags & SPECT_PSF_ALL_TAPS) && (g->flags & SPECT_PSF_SYMMETRIC_X)) return SPECT_ERR_VALUE;
   if ((g->flags & SPECT_TILING_4X4) && (g->flags & SPECT_TILING_16X16)) return SPECT_ERR_VALUE;
@@ -85,7 +85,7 @@ spect_status compute_layout(const spect_geom& g, Layout* lay, int* view_batch, i
     const FftShape fs = make_fft_shape(g);
     const size_t ns = (size_t)fs.NS * sizeof(float2);
     lay->fft_tables = take((size_t)(2 * fs.Lx + fs.Lz) * sizeof(int));
-    lay->fft_spectra = take((size_t)g.nview * g.ny * ns);
+    lay->fft_spectra = take((size_t)g.nview * g.ny * fs.NS * (fs.real ? sizeof(float) : sizeof(float2)));
     lay->fft_part = take((size_t)kMaxChunks * vb * ns);
     lay->fft_vproj = take((size_t)vb * ns);
   }
@@ -320,7 +320,8 @@ spect_status spect_plan_describe(spect_plan plan, char* buf, size_t len) {
                         conv, mirror ? 1 : 0, p->bilinear ? "bilinear" : "3pass", p->view_batch,
                         p->nchunk, p->rot_fwd_vg);
   if (p->use_fft && n > 0 && (size_t)n < len)
-    std::snprintf(buf + n, len - n, " fft_size=%dx%d fft_fixed=%d", p->fft.Lx, p->fft.Lz, p->fft.cfg);
+    std::snprintf(buf + n, len - n, " fft_size=%dx%d fft_fixed=%d fft_real=%d", p->fft.Lx,
+                  p->fft.Lz, p->fft.cfg, p->fft.real ? 1 : 0);
   return SPECT_OK;
 }
 

@@ -183,9 +183,11 @@ class RequestData:
     GPU projector once, before the trace starts (the request arrives with its
     measured data).  The inputs are kept in pinned host memory, so that
     admitting the request copies them to the device asynchronously on its
-    own stream; ``symmetric_x`` records whether every PSF row equals its
-    mirror image in x (checked here, on the host), which lets the plan pair
-    taps without a device check."""
+    own stream; ``symmetric_x`` and ``symmetric_z`` record whether every PSF
+    equals its mirror image in x and in z (checked here, on the host), which
+    lets the plan pair taps without a device check (direct) or keep real
+    spectra (FFT); ``request_bytes`` counts the complex spectra, an upper
+    bound."""
 
     _psf_cache: Dict[str, np.ndarray] = {}
 
@@ -209,6 +211,7 @@ class RequestData:
         self.r = r.cpu().numpy()
         plan.close()
         self.symmetric_x = bool(np.array_equal(psf, psf[..., ::-1]))
+        self.symmetric_z = bool(np.array_equal(psf, psf[..., ::-1, :]))
         self.pinned = {k: torch.from_numpy(getattr(self, k)).pin_memory()
                        for k in ("mu", "psf", "y", "r")}
 
@@ -246,7 +249,8 @@ class GpuExecutor:
             mu, psf, y, r = (d.pinned[k].to(self.device, non_blocking=True)
                              for k in ("mu", "psf", "y", "r"))
             plan = spect.Plan(mu, psf, d.dy, cache_mubar=self.cache_mubar, precision=req.precision,
-                              mirror="assume" if d.symmetric_x else "off", method=req.method)
+                              mirror="assume" if d.symmetric_x else "off", method=req.method,
+                              symmetric_z=d.symmetric_z)
             sens = plan.back(torch.ones(plan.proj_shape, dtype=torch.float32, device=self.device))
             x = torch.ones(plan.vol_shape, dtype=torch.float32, device=self.device)
         self.slots[req.rid] = _Slot(req, plan, stream, x, y, r, sens, now)

@@ -26,6 +26,7 @@ SPECT_PSF_SYMMETRIC_X = 0x10
 SPECT_TILING_4X4 = 0x20
 SPECT_TILING_16X16 = 0x40
 SPECT_CONV_FFT = 0x80
+SPECT_PSF_SYMMETRIC_Z = 0x100
 METHODS = {"direct": 0, "fft": SPECT_CONV_FFT}
 MIRRORS = {"auto": 0, "off": SPECT_PSF_ALL_TAPS, "assume": SPECT_PSF_SYMMETRIC_X}
 TILINGS = {"auto": 0, "4x4": SPECT_TILING_4X4, "16x16": SPECT_TILING_16X16}
@@ -249,12 +250,14 @@ class Plan:
     (SPECT_PSF_SYMMETRIC_X: the caller states the symmetry; no check, no
     wait).  tiling: "auto", "4x4" or "16x16" (the FP32 convolution's blocks).
     method: "direct" (the convolution sum on the matrix cores) or "fft"
-    (SPECT_CONV_FFT: FP32 FFTs, the same operator).
+    (SPECT_CONV_FFT: FP32 FFTs, the same operator).  symmetric_z: the caller
+    states that every PSF column is symmetric in z (SPECT_PSF_SYMMETRIC_Z);
+    with method="fft" and mirror="assume" the plan keeps real PSF spectra.
     """
 
     def __init__(self, mu, psf, dy, angles=None, cache_mubar=False, view_batch=0,
                  precision="fp32", rotation="3pass", mirror="auto", tiling="auto",
-                 method="direct"):
+                 method="direct", symmetric_z=False):
         import torch
         self.device = mu.device
         if self.device.type != "cuda":
@@ -291,7 +294,7 @@ class Plan:
         self.method = method
         flags = ((SPECT_CACHE_MUBAR if cache_mubar else 0) | ROTATIONS[rotation] |
                  (SPECT_PSF_SEPARABLE if sep else 0) | MIRRORS[mirror] | TILINGS[tiling] |
-                 METHODS[method])
+                 METHODS[method] | (SPECT_PSF_SYMMETRIC_Z if symmetric_z else 0))
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
         self.precision = precision

@@ -51,7 +51,7 @@ def test_status_strings():
     (dict(nview=0), 2),
     (dict(dy=0.0), 3),
     (dict(dy=float("nan")), 3),
-    (dict(flags=0x100), 3),           # unknown flag bit
+    (dict(flags=0x200), 3),           # unknown flag bit
     (dict(flags=0x18), 3),            # all taps and stated symmetry together
     (dict(flags=0x60), 3),            # both FP32 tilings together
     (dict(flags=0x4, conv_precision=1), 5),   # separable PSFs: FP32 only
@@ -206,3 +206,23 @@ def test_fft_flag_validation_and_workspace():
     with pytest.raises(spect.SpectError) as e:      # 300 x 200 transforms exceed LDS
         spect.spect_workspace_bytes(g)
     assert e.value.status == 5
+
+
+def test_fft_real_spectra_workspace():
+    """SPECT_PSF_SYMMETRIC_X | SPECT_PSF_SYMMETRIC_Z with SPECT_CONV_FFT on a
+    compiled-in transform size keeps one float per spectrum bin: the
+    workspace shrinks by exactly half the spectra; on a run-time size (or
+    with one of the two flags) nothing changes; without SPECT_CONV_FFT the
+    flag is accepted and changes nothing."""
+    sym = spect.SPECT_PSF_SYMMETRIC_X | spect.SPECT_PSF_SYMMETRIC_Z
+    def ws(nx, nz, nview, p, flags):
+        g, _ = spect.make_geom(nx, nx, nz, nview, p, p, 4.8, flags=flags)
+        return spect.spect_workspace_bytes(g)
+    F = spect.SPECT_CONV_FFT
+    full, real = ws(128, 80, 128, 37, F), ws(128, 80, 128, 37, F | sym)
+    spectra = 128 * 128 * (89 * 120 + 122) * 8                # complex, 256-byte aligned
+    assert abs((full - real) - spectra // 2) <= 512
+    assert ws(128, 80, 128, 37, F | spect.SPECT_PSF_SYMMETRIC_X) == full
+    assert ws(128, 80, 128, 37, F | spect.SPECT_PSF_SYMMETRIC_Z) == full
+    assert ws(32, 20, 16, 7, F | sym) == ws(32, 20, 16, 7, F)  # 40 x 30: run-time sizes
+    assert ws(32, 20, 16, 7, spect.SPECT_PSF_SYMMETRIC_Z) == ws(32, 20, 16, 7, 0)

@@ -191,3 +191,57 @@ def test_fft_paper_sampled_views(paper):
         f"vs direct forward {ev:.2e} back {ebd:.2e}")
     assert eb <= TOL and abs(lhs - rhs) <= TOL * abs(lhs)
     assert ev <= 2e-6 and ebd <= 2e-6
+
+
+@pytest.mark.parametrize("nx,nz,nview,p", [(64, 40, 12, 19), (60, 37, 5, 23)])
+def test_fft_real_spectra(nx, nz, nview, p):
+    """PSFs symmetric in x and z, stated with SPECT_PSF_SYMMETRIC_X | _Z: the
+    plan keeps the real spectra of the centred PSFs (90 x 60 transforms, both
+    shapes) and computes the same operator."""
+    say(f"fft real {nx}x{nz} views {nview} psf {p}")
+    x = synth.random_volume(nx, nx, nz, seed=nx)
+    mu = synth.random_volume(nx, nx, nz, seed=nx + 1, high=0.05)
+    psf = synth.random_psf(p, p, nx, nview, seed=nx + 2, symmetric=True)
+    assert np.array_equal(psf, psf[..., ::-1]) and np.array_equal(psf, psf[..., ::-1, :])
+    g = Geometry(nx, nx, nz, nview, p, p, 1.1)
+    y = synth.random_volume(nx, nz, nview, seed=nx + 3)
+    v_ref, b_ref = oracle.forward(x, mu, psf, g), oracle.back(y, mu, psf, g)
+    plan = spect.Plan(to_dev(mu), to_dev(psf), 1.1, method="fft", mirror="assume", symmetric_z=True)
+    d = plan.describe()
+    assert d["fft_real"] == "1" and d["fft_fixed"] != "0", d
+    ef = rel_l2(host(plan.forward(to_dev(x))), v_ref)
+    eb = rel_l2(host(plan.back(to_dev(y))), b_ref)
+    lhs = spect.dot_f64(plan.forward(to_dev(x)), to_dev(y))
+    rhs = spect.dot_f64(to_dev(x), plan.back(to_dev(y)))
+    full = spect.Plan(to_dev(mu), to_dev(psf), 1.1, method="fft")
+    assert full.describe()["fft_real"] == "0"
+    ev = rel_l2(host(plan.forward(to_dev(x))), host(full.forward(to_dev(x))))
+    say(f"  forward {ef:.2e}, back {eb:.2e}, adjoint gap {abs(lhs - rhs) / abs(lhs):.2e}, "
+        f"vs complex spectra {ev:.2e}; workspace {plan.ws_bytes} vs {full.ws_bytes}")
+    assert ef <= TOL and eb <= TOL and abs(lhs - rhs) <= TOL * abs(lhs) and ev <= 2e-6
+    assert plan.ws_bytes < full.ws_bytes
+
+
+def test_fft_real_spectra_paper(paper):
+    """The 128x128x80 / 128-view / 37x37 Gaussian PSFs (symmetric in x and z)
+    with real spectra (180 x 120 transforms): sampled views against the
+    oracle, the full-size adjoint identity, agreement with complex spectra."""
+    mud, psfd = to_dev(paper["mu"]), to_dev(paper["psf"])
+    plan = spect.Plan(mud, psfd, paper["dy"], cache_mubar=True, method="fft", mirror="assume",
+                      symmetric_z=True)
+    assert plan.describe()["fft_real"] == "1"
+    xd = to_dev(paper["x"])
+    v = host(plan.forward(xd))
+    views = [3, 64, 90]
+    ref = oracle.forward(paper["x"], paper["mu"], paper["psf"], paper["g"], views=views, conv="fft")
+    ef = max(rel_l2(v[l], ref[l]) for l in views)
+    yd = to_dev(np.random.default_rng(5).uniform(0.0, 1.0, (128, 80, 128)))
+    lhs = spect.dot_f64(plan.forward(xd), yd)
+    rhs = spect.dot_f64(xd, plan.back(yd))
+    full = spect.Plan(mud, psfd, paper["dy"], cache_mubar=True, method="fft")
+    ev = rel_l2(v, host(full.forward(xd)))
+    eb = rel_l2(host(plan.back(yd)), host(full.back(yd)))
+    say(f"fft real paper: forward {ef:.2e}, adjoint gap {abs(lhs - rhs) / abs(lhs):.2e}, "
+        f"vs complex spectra forward {ev:.2e} back {eb:.2e}")
+    assert ef <= TOL and abs(lhs - rhs) <= TOL * abs(lhs) and ev <= 2e-6 and eb <= 2e-6
+

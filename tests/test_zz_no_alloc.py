@@ -84,6 +84,8 @@ CASES = [
     ("16x16x8-asymmetric", "small", dict(mirror="off"), 0),
     ("tiny-bilinear", "tiny", dict(mirror="assume", rotation="bilinear"),
      spect.SPECT_PSF_SYMMETRIC_X | spect.SPECT_ROT_BILINEAR),
+    ("tiny-fft", "tiny", dict(method="fft"), spect.SPECT_CONV_FFT),
+    ("16x16x8-fft", "small", dict(method="fft"), spect.SPECT_CONV_FFT),
 ]
 
 
