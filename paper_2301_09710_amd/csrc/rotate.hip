@@ -599,7 +599,11 @@ __device__ __forceinline__ void guarded_pass(float* Yd, int n, int S, const TabE
 
 // grid (nz, ceil(nvb / VG)): W[lb][k] = (R_l x)[k] * mubar_l[k] for the views
 // of this group.  Thread (wave w, lane) owns pixels i = lane + 64 e,
-// j = w + NW r for staging, the last pass and the store.
+// j = w + NW r for staging, the last pass and the store.  The tables of all
+// the group's views are read into LDS once, at the start: a per-view table
+// read would wait for every memory operation in flight (the counter is in
+// order), i.e. for the previous view's stores and this view's attenuation
+// factors, which instead land while the view's first passes run.
 template <int EPL, int LPW>
 __global__ __launch_bounds__(NT) void rot_fwd_lines_kernel(const float* __restrict__ x,
                                                            const float* __restrict__ mb, int mb_off,
@@ -608,11 +612,12 @@ __global__ __launch_bounds__(NT) void rot_fwd_lines_kernel(const float* __restri
   extern __shared__ float smem[];
   const int S = guarded_stride(n);
   float* Yd = smem + guarded_origin(n);
-  ViewTab t = carve_tab(smem + round4(guarded_floats(n)), n);
+  float* tabs = smem + round4(guarded_floats(n));    // VG views' tables, 8 n floats each
   const int k = blockIdx.x, lane = lane_id(), w = wave_id();
   const size_t nn = (size_t)n * n, N = nn * nz;
   for (int p = threadIdx.x; p < guarded_floats(n); p += NT) smem[p] = 0.0f;
   const int lb0 = blockIdx.y * VG, lb1 = min(nvb, lb0 + VG);
+  for (int lb = lb0; lb < lb1; ++lb) load_tab(tab, view0 + lb, n, carve_tab(tabs + (lb - lb0) * 8 * n, n));
   // rows j = w + NW r with j < n (uniform per wave); columns i = lane + 64 e
   float xv[LPW][EPL], mbv[LPW][EPL];
   const int pix = w * n + lane;                   // offset of this thread's (r, e) = (0, 0) pixel
@@ -638,8 +643,8 @@ __global__ __launch_bounds__(NT) void rot_fwd_lines_kernel(const float* __restri
     int qb, qi, qj;
     quarter_cell(m, n, S, qb, qi, qj);
     const int sb = qb + qi * lane + qj * w;
+    const ViewTab t = carve_tab(tabs + (lb - lb0) * 8 * n, n);
     __syncthreads();                               // guards zeroed / previous view's readers done
-    load_tab(tab, l, n, t);
 #pragma unroll
     for (int r = 0; r < LPW; ++r) {
       if (w + NW * r >= n) break;
@@ -890,6 +895,9 @@ __global__ void back_reduce_kernel(const float* __restrict__ partial, float* __r
 }
 
 size_t tab_bytes(int n) { return (size_t)2 * n * sizeof(TabEntry); }
+constexpr int kMaxFwdViews = 16;   // views per workgroup of the forward line-pass kernel, at most
+// the forward line-pass kernel: the guarded slice and the tables of its VG views
+size_t fwd_lines_lds(int n, int VG) { return (size_t)round4(guarded_floats(n)) * 4 + VG * tab_bytes(n); }
 size_t slice_bytes(int n) { return (size_t)n * slice_stride(n) * 4; }
 
 hipError_t set_smem(const void* fn, size_t bytes) {
@@ -951,8 +959,8 @@ hipError_t launch_rot_fwd(const Plan& p, const float* x, const float* mb, int mb
   const int n = p.g.nx;
   const bool glob = n > kMaxLdsN;
   if (!glob && !p.bilinear) {
-    const size_t sm = (size_t)round4(guarded_floats(n)) * 4 + tab_bytes(n);
     const int VG = p.rot_fwd_vg > 0 ? p.rot_fwd_vg : kRotViewsPerGroup;
+    const size_t sm = fwd_lines_lds(n, VG);
     dim3 grid(p.g.nz, (nvb + VG - 1) / VG);
     return with_shape(n, [&](auto E, auto L, auto G) {
       if constexpr (G.value) {
@@ -992,7 +1000,7 @@ int tune_rot_fwd_views(const spect_geom& g, int nvb) {
   const int n = g.nx;
   if (n > kMaxLdsN || (g.flags & SPECT_ROT_BILINEAR)) return kRotViewsPerGroup;
   int dev = 0, cus = 0, per_cu = 0;
-  const size_t sm = (size_t)round4(guarded_floats(n)) * 4 + tab_bytes(n);
+  const size_t sm = fwd_lines_lds(n, kMaxFwdViews);
   hipError_t e = with_shape(n, [&](auto E, auto L, auto G) {
     if constexpr (G.value) {
       return hipErrorInvalidValue;
@@ -1012,7 +1020,7 @@ int tune_rot_fwd_views(const spect_geom& g, int nvb) {
   const long long slots = (long long)cus * per_cu;
   int best = kRotViewsPerGroup;
   double best_cost = -1.0;
-  for (int vg = 1; vg <= 16; ++vg) {
+  for (int vg = 1; vg <= kMaxFwdViews; ++vg) {
     const long long wgs = (long long)g.nz * ((nvb + vg - 1) / vg);
     const double cost = (double)((wgs + slots - 1) / slots) * (vg + 0.5);
     if (best_cost < 0 || cost < best_cost) { best_cost = cost; best = vg; }
