@@ -206,20 +206,30 @@ def test_fft_real_spectra(nx, nz, nview, p):
     g = Geometry(nx, nx, nz, nview, p, p, 1.1)
     y = synth.random_volume(nx, nz, nview, seed=nx + 3)
     v_ref, b_ref = oracle.forward(x, mu, psf, g), oracle.back(y, mu, psf, g)
-    plan = spect.Plan(to_dev(mu), to_dev(psf), 1.1, method="fft", mirror="assume", symmetric_z=True)
-    d = plan.describe()
-    assert d["fft_real"] == "1" and d["fft_fixed"] != "0", d
-    ef = rel_l2(host(plan.forward(to_dev(x))), v_ref)
-    eb = rel_l2(host(plan.back(to_dev(y))), b_ref)
-    lhs = spect.dot_f64(plan.forward(to_dev(x)), to_dev(y))
-    rhs = spect.dot_f64(to_dev(x), plan.back(to_dev(y)))
     full = spect.Plan(to_dev(mu), to_dev(psf), 1.1, method="fft")
     assert full.describe()["fft_real"] == "0"
-    ev = rel_l2(host(plan.forward(to_dev(x))), host(full.forward(to_dev(x))))
-    say(f"  forward {ef:.2e}, back {eb:.2e}, adjoint gap {abs(lhs - rhs) / abs(lhs):.2e}, "
-        f"vs complex spectra {ev:.2e}; workspace {plan.ws_bytes} vs {full.ws_bytes}")
-    assert ef <= TOL and eb <= TOL and abs(lhs - rhs) <= TOL * abs(lhs) and ev <= 2e-6
-    assert plan.ws_bytes < full.ws_bytes
+    for kw in (dict(), dict(cache_mubar=True, view_batch=max(1, nview // 3)),
+               dict(rotation="bilinear")):
+        plan = spect.Plan(to_dev(mu), to_dev(psf), 1.1, method="fft", mirror="assume",
+                          symmetric_z=True, **kw)
+        d = plan.describe()
+        assert d["fft_real"] == "1" and d["fft_fixed"] != "0", d
+        if "rotation" in kw:
+            gb = Geometry(nx, nx, nz, nview, p, p, 1.1, rotation="bilinear")
+            vr, br = oracle.forward(x, mu, psf, gb), oracle.back(y, mu, psf, gb)
+        else:
+            vr, br = v_ref, b_ref
+        ef = rel_l2(host(plan.forward(to_dev(x))), vr)
+        eb = rel_l2(host(plan.back(to_dev(y))), br)
+        lhs = spect.dot_f64(plan.forward(to_dev(x)), to_dev(y))
+        rhs = spect.dot_f64(to_dev(x), plan.back(to_dev(y)))
+        say(f"  {kw}: forward {ef:.2e}, back {eb:.2e}, adjoint gap {abs(lhs - rhs) / abs(lhs):.2e}")
+        assert ef <= TOL and eb <= TOL and abs(lhs - rhs) <= TOL * abs(lhs)
+        if not kw:
+            ev = rel_l2(host(plan.forward(to_dev(x))), host(full.forward(to_dev(x))))
+            say(f"  vs complex spectra {ev:.2e}; workspace {plan.ws_bytes} vs {full.ws_bytes}")
+            assert ev <= 2e-6 and plan.ws_bytes < full.ws_bytes
+        plan.close()
 
 
 def test_fft_real_spectra_paper(paper):

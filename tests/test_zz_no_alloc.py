@@ -86,10 +86,15 @@ CASES = [
      spect.SPECT_PSF_SYMMETRIC_X | spect.SPECT_ROT_BILINEAR),
     ("tiny-fft", "tiny", dict(method="fft"), spect.SPECT_CONV_FFT),
     ("16x16x8-fft", "small", dict(method="fft"), spect.SPECT_CONV_FFT),
+    ("serve64-fft-real", "serve64-16", dict(method="fft", mirror="assume", symmetric_z=True),
+     spect.SPECT_CONV_FFT | spect.SPECT_PSF_SYMMETRIC_X | spect.SPECT_PSF_SYMMETRIC_Z),
 ]
 
 
 def _inputs(which):
+    if which == "serve64-16":      # the 64x64x40 / 19x19 size (90 x 60 transforms), 16 views
+        x, mu, psf, dy = synth.config_inputs("serve64", seed=1)
+        return x, mu, np.ascontiguousarray(psf[::4]), dy
     if which == "small":
         x = synth.random_volume(16, 16, 8, seed=3)
         mu = synth.random_volume(16, 16, 8, seed=4, high=0.05)
