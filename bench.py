@@ -7,11 +7,14 @@ A step is one forward projection plus one back projection (a "pair") of the
 paper-scale workload: 128x128x80 volume at 4.8 mm, 128 views over 360
 degrees, 37x37 depth/view-dependent Gaussian PSFs (sigma 1 -> 6 voxels), an
 ellipsoidal body phantom with hot lesions and a tissue/lung/bone attenuation
-map (synthetic, seeded).  Inputs are resident in HBM before the timed
-region.  Prints ONE JSON line with pairs/s, the per-pair latency
-distribution, EM reconstruction latency, the roofline of the dominant kernel
-(timed live with HIP events on the launch stream) and the FP64 oracle timed
-on the host cores on a bounded sample of views.
+map (synthetic, seeded).  The PSF convolution runs as FP32 FFTs (the
+paper's method); the PSFs are checked on the host to be symmetric in x and
+z, which the plan is told, so it keeps real spectra.  Inputs are resident in
+HBM before the timed region.  Prints ONE JSON line with pairs/s, the per-pair
+latency distribution, EM reconstruction latency, the roofline of the
+dominant kernel (timed live with HIP events on the launch stream), the same
+pair with the direct convolution and other plan variants beside it, and the
+FP64 oracle timed on the host cores.
 """
 from __future__ import annotations
 
