@@ -61,6 +61,7 @@ CASES = [
     (48, 41, 4, 19, 21, False, [0.1, 1.7, -2.5, 7.0]),
     (9, 12, 8, 5, 25, True, None),               # kernel taller than the volume, 45-degree ties
     (64, 40, 6, 19, 19, False, None),            # the 64x64x40 serving size
+    (144, 12, 3, 7, 5, False, None),             # slices above the rotation's LDS limit
 ]
 
 
