@@ -131,8 +131,10 @@ __device__ __forceinline__ float row_px(const float* Y, int n, int S, const View
   const int o = te.o;
   const float2 w = te.w;
   const int ia = i + kSgn * o, ib = ia + kSgn;
-  const float a = inside(ia, n) ? Y[j * S + ia] : 0.0f;
-  const float b = inside(ib, n) ? Y[j * S + ib] : 0.0f;
+  // unsigned offsets (nonnegative where read): a uniform base plus a 32-bit
+  // offset when Y is in global memory
+  const float a = inside(ia, n) ? Y[(unsigned)(j * S + ia)] : 0.0f;
+  const float b = inside(ib, n) ? Y[(unsigned)(j * S + ib)] : 0.0f;
   return w.x * a + w.y * b;
 }
 
@@ -291,6 +293,73 @@ __device__ void banded_col_pass(float* Y, int n, int S, const ViewTab& t, float*
       const int r = p / kBand, c = p - r * kBand;
       if (c0 + c < n) Y[r * S + c0 + c] = Bd[r * kBandStride + c];
     }
+  }
+  __syncthreads();
+}
+
+// Transposed passes 3 and 2 of one view for slices too large for LDS, band
+// by band (kBand columns): pass 3 transposed, a two-tap gather along each
+// row, is evaluated as the band is staged, straight from U and the
+// attenuation factors (lanes on consecutive columns, kStageRows rows' loads
+// issued first); pass 2 transposed then runs in place in the band, and the
+// band is written to the working slice Y (row stride S) in global memory.
+// Starts and ends with a workgroup barrier.
+constexpr int kStageRows = 4;
+template <int EPL>
+__device__ void banded_adj_passes(float* Y, const float* __restrict__ u,
+                                  const float* __restrict__ a, int n, int S, const ViewTab& t,
+                                  float* B) {
+  static_assert(kBand == 64, "one lane per band column");
+  float* Bd = B + kBandStride;
+  const int lane = lane_id(), w = wave_id();
+  for (int c0 = 0; c0 < n; c0 += kBand) {
+    __syncthreads();                               // previous band written back
+    const int q = c0 + lane;
+#pragma unroll 1
+    for (int r0 = w; r0 < n; r0 += NW * kStageRows) {
+      float ua[kStageRows], ma[kStageRows], ub[kStageRows], mb[kStageRows];
+#pragma unroll
+      for (int c = 0; c < kStageRows; ++c) {
+        const int r = r0 + c * NW;
+        const int ia = q - t.e13[r < n ? r : 0].o, ib = ia - 1;
+        const bool ok = r < n && q < n;
+        const int at = r * n + ia;                 // < n * n: 32-bit offsets
+        ua[c] = ok && inside(ia, n) ? u[at] : 0.0f;
+        ma[c] = ok && inside(ia, n) ? a[at] : 0.0f;
+        ub[c] = ok && inside(ib, n) ? u[at - 1] : 0.0f;
+        mb[c] = ok && inside(ib, n) ? a[at - 1] : 0.0f;
+      }
+#pragma unroll
+      for (int c = 0; c < kStageRows; ++c) {
+        const int r = r0 + c * NW;
+        if (r < n) {
+          const float2 wt = t.e13[r].w;
+          Bd[r * kBandStride + lane] = wt.x * (ua[c] * ma[c]) + wt.y * (ub[c] * mb[c]);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int c = w; c < kBand && c0 + c < n; c += NW) {
+      const TabEntry te = t.e2[c0 + c];
+      float v[EPL];
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        const int r = lane + 64 * e;
+        const int qa = min(max(r - te.o, -1), n);
+        const int qb = min(max(r - te.o - 1, -1), n);
+        v[e] = te.w.x * Bd[qa * kBandStride + c] + te.w.y * Bd[qb * kBandStride + c];
+      }
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        const int r = lane + 64 * e;
+        if (r < n) Bd[r * kBandStride + c] = v[e];
+      }
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int r = w; r < n; r += NW)
+      if (q < n) Y[r * S + q] = Bd[r * kBandStride + lane];
   }
   __syncthreads();
 }
@@ -763,8 +832,9 @@ __global__ __launch_bounds__(NT) void rot_back_lines_kernel(const float* __restr
 // grid (nz, G): partial[g][k] (+)= sum over views lb = g, g+G, ... of
 //   P_m^T S1^T S2^T S3^T (U[lb][k] * mubar_l[k]).
 // Output pixel (i, j) accumulates in wave j mod NW, lane i mod 64.
-// kGlobal: the working slice Y is the workgroup's own slice of `scratch`.
-constexpr int kStageRows = 4;
+// kGlobal: the working slice Y is the workgroup's own slice of `scratch`;
+// with the 3-pass rotation, passes 3 and 2 transposed run band by band
+// (banded_adj_passes) and pass 1 transposed gathers from Y.
 template <int EPL, int LPW, bool kGlobal, bool kBil>
 __global__ __launch_bounds__(NT) void rot_back_kernel(const float* __restrict__ U,
                                                       const float* __restrict__ mb, int mb_off,
@@ -792,7 +862,9 @@ __global__ __launch_bounds__(NT) void rot_back_kernel(const float* __restrict__ 
     load_tab(tab, l, n, t);
     const float* src = U + (size_t)lb * N + (size_t)k * nn;
     const float* mbs = mb + (size_t)(lb + mb_off) * N + (size_t)k * nn;
-    {
+    if (kGlobal && !kBil) {
+      banded_adj_passes<EPL>(Y, src, mbs, n, S, t, band);   // passes 3 and 2 transposed
+    } else {
       // stage U * mubar: a thread keeps column i = tid mod n and visits rows
       // j = tid / n + lpi r, with the loads of kStageRows rows issued first
       const int lpi = NT / n, i = threadIdx.x % n, v0 = threadIdx.x / n;
@@ -813,23 +885,21 @@ __global__ __launch_bounds__(NT) void rot_back_kernel(const float* __restrict__ 
           }
         }
       }
-    }
-    __syncthreads();
-    if (!kBil) {
-      line_pass<-1, true, EPL>(Y, n, S, t);            // pass 3 transpose
       __syncthreads();
-      if (kGlobal) {
-        banded_col_pass<-1, EPL>(Y, n, S, t, band);    // pass 2 transpose
-      } else {
+      if (!kBil) {
+        line_pass<-1, true, EPL>(Y, n, S, t);          // pass 3 transpose
+        __syncthreads();
         line_pass<-1, false, EPL>(Y, n, S, t);         // pass 2 transpose
         __syncthreads();
       }
     }
     const float2 cs = tab.rot[l];
     const float cc = 0.5f * (float)(n - 1);
-    if (kGlobal) {
-      // large slices: accumulate in this workgroup's own slice of `partial`
-      // (each pixel has one owner lane, so the order of additions is fixed)
+    if (kGlobal && kBil) {
+      // bilinear, large slices: accumulate in this workgroup's own slice of
+      // `partial` (each pixel has one owner lane, so the order of additions
+      // is fixed); the 9-candidate gather is too long to unroll over the 64
+      // pixels a lane owns
       float* dst = partial + (size_t)g * N + (size_t)k * nn;
       const bool first = lb == g;
 #pragma unroll 1
@@ -841,8 +911,7 @@ __global__ __launch_bounds__(NT) void rot_back_kernel(const float* __restrict__ 
           if (j < n && i < n) {
             int di, dj;
             quarter_dst(m, n, i, j, di, dj);
-            const float val = kBil ? bil_adj_px(Y, n, S, t, cs, cc, di, dj)
-                                   : row_px<-1>(Y, n, S, t, di, dj);
+            const float val = bil_adj_px(Y, n, S, t, cs, cc, di, dj);
             const float prev = (first && !accumulate) ? 0.0f : dst[j * n + i];
             dst[j * n + i] = prev + val;
           }
@@ -850,12 +919,16 @@ __global__ __launch_bounds__(NT) void rot_back_kernel(const float* __restrict__ 
       }
       continue;
     }
+    // pixel indices formed per view: hoisted out of the view loop, those of
+    // the 64 pixels a lane owns in large slices would spill the accumulators
+    int ln = lane, wv = w;
+    if (kGlobal) asm volatile("" : "+v"(ln), "+v"(wv));
 #pragma unroll
     for (int r = 0; r < LPW; ++r) {                    // pass 1 transpose, then P_m^T
-      const int j = w + NW * r;
+      const int j = wv + NW * r;
 #pragma unroll
       for (int e = 0; e < EPL; ++e) {
-        const int i = lane + 64 * e;
+        const int i = ln + 64 * e;
         if (j < n && i < n) {
           int di, dj;
           quarter_dst(m, n, i, j, di, dj);             // x(i, j) = h(P_m position)
@@ -863,9 +936,12 @@ __global__ __launch_bounds__(NT) void rot_back_kernel(const float* __restrict__ 
                             : row_px<-1>(Y, n, S, t, di, dj);
         }
       }
+      // Y in global memory: one line's loads in flight at a time, not all
+      // (their addresses and results would spill the accumulators)
+      if (kGlobal) __builtin_amdgcn_sched_barrier(0);
     }
   }
-  if (kGlobal) {
+  if (kGlobal && kBil) {
     // a workgroup with no view in this batch still owns its slice
     if (g >= nvb && !accumulate) {
       float* dst = partial + (size_t)g * N + (size_t)k * nn;

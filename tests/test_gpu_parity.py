@@ -282,11 +282,13 @@ def test_paper_adjoint_identity(paper):
 
 # ------------------------------------------------------------ slices larger than LDS
 
-@pytest.mark.parametrize("case", [(144, 6, 5, 5, 7), (200, 3, 3, 9, 5)])
+@pytest.mark.parametrize("case", [(144, 6, 5, 5, 7), (200, 3, 3, 9, 5), (256, 2, 5, 7, 5)])
 def test_large_slice_parity(case):
     """In-plane sizes above the LDS-resident limit (the rotation kernels then
-    keep their working slices in global scratch): full forward and back
-    against the oracle."""
+    keep their working slices in global scratch), up to the largest supported
+    slice: full forward and back against the oracle, with and without the
+    attenuation cache, and in view batches of 2 (the adjoint then adds each
+    batch onto the previous ones)."""
     nx, nz, nview, px, pz = case
     say(f"test_large_slice_parity {case}")
     seed = nx + nz
@@ -295,10 +297,9 @@ def test_large_slice_parity(case):
     psf = synth.random_psf(px, pz, nx, nview, seed=seed + 2, symmetric=False)
     dy = 1.0
     g = Geometry(nx, nx, nz, nview, px, pz, dy)
-    for cache in (True, False):
-        plan = make_plan(mu, psf, dy, cache_mubar=cache)
-        v = gpu_fwd(plan, x)
-        assert rel_l2(v, oracle.forward(x, mu, psf, g)) <= TOL
-        y = synth.random_volume(nx, nz, nview, seed=seed + 3)
-        b = gpu_back(plan, y)
-        assert rel_l2(b, oracle.back(y, mu, psf, g)) <= TOL
+    y = synth.random_volume(nx, nz, nview, seed=seed + 3)
+    ref_v, ref_b = oracle.forward(x, mu, psf, g), oracle.back(y, mu, psf, g)
+    for kw in (dict(cache_mubar=True), dict(cache_mubar=False), dict(view_batch=2)):
+        plan = make_plan(mu, psf, dy, **kw)
+        assert rel_l2(gpu_fwd(plan, x), ref_v) <= TOL
+        assert rel_l2(gpu_back(plan, y), ref_b) <= TOL
