@@ -251,27 +251,29 @@ __device__ __forceinline__ void line_pass(float* Y, int n, int S, const ViewTab&
 // ---------------------------------------------------------------- banded column pass
 // Column shear of a working slice Y in global memory (row stride S), for
 // slices too large for LDS.  Lanes along a column would touch one cache line
-// each, so the pass runs through LDS in bands of kBand columns: a band is
-// staged with coalesced row reads into B (rows -1 .. n, stride kBand + 1,
-// rows -1 and n zero: set once by the caller), each wave shears its columns
-// in place (lanes along the rows, one table read per column, sample positions
-// clamped into the zero rows), and the band is written back with coalesced
-// row writes.  Starts and ends with a workgroup barrier.
+// each, so the pass runs through LDS in bands of kBand columns: `stage`
+// fills a band B (rows -1 .. n, stride kBand + 1; rows -1 and n zero, set
+// once by the caller) with coalesced row accesses, each wave shears its
+// columns in place (lanes along the rows, one table read per column, sample
+// positions clamped into the zero rows), and the band goes to Y with
+// coalesced row writes.  stage(Bd, c0) writes rows 0 .. n-1 of columns
+// c0 .. c0 + kBand - 1 at Bd[r * kBandStride + c], zero beyond column n - 1.
+// Starts and ends with a workgroup barrier.
 constexpr int kBand = 64;
 constexpr int kBandStride = kBand + 1;
 __host__ __device__ __forceinline__ size_t band_floats(int n) { return (size_t)(n + 2) * kBandStride; }
 
-template <int kSgn, int EPL>
-__device__ void banded_col_pass(float* Y, int n, int S, const ViewTab& t, float* B) {
+template <int kSgn, int EPL, class F>
+__device__ __forceinline__ void banded_passes(float* Y, int n, int S, const ViewTab& t, float* B,
+                                              F&& stage) {
+  static_assert(kBand == 64, "one lane per band column");
   float* Bd = B + kBandStride;                     // row r of the band at Bd[r * kBandStride]
   const int lane = lane_id(), w = wave_id();
   for (int c0 = 0; c0 < n; c0 += kBand) {
-    __syncthreads();                               // Y written / previous band written back
-    for (int p = threadIdx.x; p < n * kBand; p += NT) {
-      const int r = p / kBand, c = p - r * kBand;
-      Bd[r * kBandStride + c] = c0 + c < n ? Y[r * S + c0 + c] : 0.0f;
-    }
+    __syncthreads();                               // inputs ready / previous band written back
+    stage(Bd, c0);
     __syncthreads();
+#pragma unroll 1
     for (int c = w; c < kBand && c0 + c < n; c += NW) {
       const TabEntry te = t.e2[c0 + c];
       float v[EPL];
@@ -289,32 +291,38 @@ __device__ void banded_col_pass(float* Y, int n, int S, const ViewTab& t, float*
       }
     }
     __syncthreads();
-    for (int p = threadIdx.x; p < n * kBand; p += NT) {
-      const int r = p / kBand, c = p - r * kBand;
-      if (c0 + c < n) Y[r * S + c0 + c] = Bd[r * kBandStride + c];
-    }
+    const int q = c0 + lane;
+#pragma unroll 4
+    for (int r = w; r < n; r += NW)
+      if (q < n) Y[r * S + q] = Bd[r * kBandStride + lane];
   }
   __syncthreads();
 }
 
-// Transposed passes 3 and 2 of one view for slices too large for LDS, band
-// by band (kBand columns): pass 3 transposed, a two-tap gather along each
-// row, is evaluated as the band is staged, straight from U and the
-// attenuation factors (lanes on consecutive columns, kStageRows rows' loads
-// issued first); pass 2 transposed then runs in place in the band, and the
-// band is written to the working slice Y (row stride S) in global memory.
-// Starts and ends with a workgroup barrier.
+// Column pass over a working slice already in Y.
+template <int kSgn, int EPL>
+__device__ void banded_col_pass(float* Y, int n, int S, const ViewTab& t, float* B) {
+  banded_passes<kSgn, EPL>(Y, n, S, t, B, [&](float* Bd, int c0) {
+    for (int p = threadIdx.x; p < n * kBand; p += NT) {
+      const int r = p / kBand, c = p - r * kBand;
+      Bd[r * kBandStride + c] = c0 + c < n ? Y[r * S + c0 + c] : 0.0f;
+    }
+  });
+}
+
+// Transposed passes 3 and 2 of one view for slices too large for LDS:
+// pass 3 transposed, a two-tap gather along each row, is evaluated as each
+// band is staged, straight from U and the attenuation factors (wave w takes
+// rows w, w + NW, ..., lane L column c0 + L, with the loads of kStageRows
+// rows issued before any is used); pass 2 transposed runs in the band; the
+// band goes to Y.
 constexpr int kStageRows = 4;
 template <int EPL>
 __device__ void banded_adj_passes(float* Y, const float* __restrict__ u,
                                   const float* __restrict__ a, int n, int S, const ViewTab& t,
                                   float* B) {
-  static_assert(kBand == 64, "one lane per band column");
-  float* Bd = B + kBandStride;
-  const int lane = lane_id(), w = wave_id();
-  for (int c0 = 0; c0 < n; c0 += kBand) {
-    __syncthreads();                               // previous band written back
-    const int q = c0 + lane;
+  banded_passes<-1, EPL>(Y, n, S, t, B, [&](float* Bd, int c0) {
+    const int lane = lane_id(), w = wave_id(), q = c0 + lane;
 #pragma unroll 1
     for (int r0 = w; r0 < n; r0 += NW * kStageRows) {
       float ua[kStageRows], ma[kStageRows], ub[kStageRows], mb[kStageRows];
@@ -338,30 +346,7 @@ __device__ void banded_adj_passes(float* Y, const float* __restrict__ u,
         }
       }
     }
-    __syncthreads();
-#pragma unroll 1
-    for (int c = w; c < kBand && c0 + c < n; c += NW) {
-      const TabEntry te = t.e2[c0 + c];
-      float v[EPL];
-#pragma unroll
-      for (int e = 0; e < EPL; ++e) {
-        const int r = lane + 64 * e;
-        const int qa = min(max(r - te.o, -1), n);
-        const int qb = min(max(r - te.o - 1, -1), n);
-        v[e] = te.w.x * Bd[qa * kBandStride + c] + te.w.y * Bd[qb * kBandStride + c];
-      }
-#pragma unroll
-      for (int e = 0; e < EPL; ++e) {
-        const int r = lane + 64 * e;
-        if (r < n) Bd[r * kBandStride + c] = v[e];
-      }
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int r = w; r < n; r += NW)
-      if (q < n) Y[r * S + q] = Bd[r * kBandStride + lane];
-  }
-  __syncthreads();
+  });
 }
 
 // Passes 1 and 2 of R_l X into Y (and pass 3 when kAllThree; otherwise the
