@@ -731,11 +731,11 @@ __global__ __launch_bounds__(NT) void rot_fwd_lines_kernel(const float* __restri
 // ---------------------------------------------------------------- back, line passes
 // grid (nz, G) on slices that fit LDS: partial[g][k] (+)= sum over views
 // lb = g, g+G, ... of P_m^T S1^T S2^T S3^T (U[lb][k] * mubar_l[k]).  Per view
-// the weighted slice is staged into the zero-guarded buffer, the transposed
-// shears run as in-place line passes (S3^T, S2^T, S1^T), and P_m^T gathers
-// the result into the accumulators (thread (w, lane) owns pixels
-// i = lane + 64 e, j = w + NW r).  The next view's U and mubar are loaded
-// during the passes.
+// the weighted slice is staged into the zero-guarded buffer, S3^T and S2^T
+// run as in-place line passes, and the accumulators (thread (w, lane) owns
+// pixels i = lane + 64 e, j = w + NW r) gather S1^T at the quarter-turned
+// positions, so that P_m^T S1^T costs no pass of its own.  The next view's U
+// and mubar are loaded during the passes.
 template <int EPL, int LPW>
 __global__ __launch_bounds__(NT) void rot_back_lines_kernel(const float* __restrict__ U,
                                                             const float* __restrict__ mb, int mb_off,
@@ -788,17 +788,30 @@ __global__ __launch_bounds__(NT) void rot_back_lines_kernel(const float* __restr
     __syncthreads();
     guarded_pass<-1, false, EPL, LPW>(Yd, n, S, t.e2);    // S2^T (along j)
     __syncthreads();
-    guarded_pass<-1, true, EPL, LPW>(Yd, n, S, t.e13);    // S1^T (along i)
-    __syncthreads();
-    int qb, qi, qj;                                       // x(i, j) += h(P_m (i, j))
-    quarter_cell(m, n, S, qb, qi, qj);
-    const int sb = qb + qi * lane + qj * w;
+    // S1^T (along i) evaluated where the accumulators gather it:
+    // x(i, j) += w.x Y[dj][di - o] + w.y Y[dj][di - o - 1] with (di, dj) the
+    // position of (i, j) under P_m, an affine map (a0 + ai i + aj j,
+    // b0 + bi i + bj j) whose indices are formed per view (hoisted out of the
+    // view loop, those of every pixel a lane owns would spill)
+    int ln = lane, wv = w;
+    asm volatile("" : "+v"(ln), "+v"(wv));
+    const int a0 = (m == 1 || m == 2) ? n - 1 : 0, b0 = (m >= 2) ? n - 1 : 0;
+    const int ai = m == 0 ? 1 : (m == 2 ? -1 : 0), aj = m == 1 ? -1 : (m == 3 ? 1 : 0);
+    const int bi = m == 1 ? 1 : (m == 3 ? -1 : 0), bj = m == 0 ? 1 : (m == 2 ? -1 : 0);
+    const int di0 = a0 + ai * ln + aj * wv, dj0 = b0 + bi * ln + bj * wv;
 #pragma unroll
     for (int r = 0; r < LPW; ++r) {
       if (w + NW * r >= n) break;
 #pragma unroll
-      for (int e = 0; e < EPL; ++e)
-        if (lane + 64 * e < n) acc[r][e] += Yd[sb + qi * 64 * e + qj * NW * r];
+      for (int e = 0; e < EPL; ++e) {
+        if (lane + 64 * e < n) {
+          const int di = di0 + ai * 64 * e + aj * NW * r, dj = dj0 + bi * 64 * e + bj * NW * r;
+          const TabEntry te = t.e13[dj];
+          const int c = clamp_guard(di - te.o - 1, n);
+          const float v = te.w.x * Yd[dj * S + c + 1] + te.w.y * Yd[dj * S + c];
+          acc[r][e] += v;
+        }
+      }
     }
   }
   float* dst = partial + (size_t)g * N + (size_t)k * nn;
