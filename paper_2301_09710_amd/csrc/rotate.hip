@@ -15,7 +15,8 @@
 // Slices that fit LDS (3-pass): rot_fwd_lines_kernel stages P_m x per view
 // into a zero-guarded buffer and runs the three passes in place, each wave
 // owning whole lines, with the attenuation weight fused into the last pass;
-// rot_back_lines_kernel (n <= 128) runs the transposed passes the same way.
+// rot_back_lines_kernel (n <= 128) runs the transposed passes the same way,
+// the last one (S1^T) inside the gather into its accumulators.
 // The attenuation kernel runs the passes in sequence on slices of odd row
 // stride n + 1 (row passes, column passes and quarter-turned reads are then
 // free of bank conflicts).
@@ -27,7 +28,7 @@
 // single staged slice, the three passes fused or the bilinear sample) and
 // rot_back_kernel (the passes in sequence) serve the bilinear rotation and
 // slices above the LDS limit, whose working slices then live in global
-// scratch.
+// scratch and whose column passes run through LDS in bands of columns.
 #include <algorithm>
 #include <type_traits>
 
