@@ -728,6 +728,7 @@ FftShape make_fft_shape(const spect_geom& g) {
   bool ok = s.nrx > 0 && s.nrz > 0 && s.H * s.Lx <= kMaxPlane &&
             s.Lx <= kMaxFftLen &&
             (s.NR + kFftThreads - 1) / kFftThreads <= kMaxSlots && s.H + 1 <= kFftThreads &&
+            g.nx <= kFftThreads &&
             g.nz * g.nx <= kMaxPlaneRegs * kFftThreads && fft_smem(s, 1) <= kLdsBytes &&
             fft_smem(s, 2) <= kLdsBytes;
   s.cfg = fft_fixed_config(s);

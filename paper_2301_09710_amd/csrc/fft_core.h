@@ -247,23 +247,23 @@ __device__ __forceinline__ void stage_twiddles(float2 (&w)[R], const float2* tw,
 }
 
 
-// The adjoint of replicate padding on one inverse-transformed plane (planes
-// of at most 2^16 padded values, for fdiv):
+// The adjoint of replicate padding on one inverse-transformed plane:
 // u[k][i] = sum of the padded plane g over the padded rows that clamp onto k
 // and the padded columns that clamp onto i, written to out[k * rs + i].
-// Columns first (into `fold`, (nz + 2 hb) x nx floats), then rows; the edge
-// sums (ha + 1 or hb + 1 terms) run on lanes of their own so that no wave
-// waits on one long sum.
+// Columns first (into `fold`, (nz + 2 hb) x nx floats), then rows.  Interior
+// bins are copies: a thread keeps one column (lanes on consecutive columns)
+// and steps over the rows, T / nx rows apart, so no index needs a division.
+// The edge sums (ha + 1 or hb + 1 terms) run on lanes of their own so that
+// no wave waits on one long sum.  Requires nx <= T.
 template <class G>
 __device__ __forceinline__ void fold_store(const float2* A, float* fold, int nx, int nz, int ha,
                                            int hb, float* out, size_t rs, G&& g, int T) {
   const int KZ = nz + 2 * hb;
-  const int inner_x = nx > 2 ? nx - 2 : 0, edges_x = nx > 1 ? 2 : 1;
-  const float r_in = inner_x ? 1.0f / (float)inner_x : 0.0f, r_nx = 1.0f / (float)nx;
-  for (int e = threadIdx.x; e < KZ * inner_x; e += T) {
-    const int zz = fdiv(e, r_in), i = 1 + e - zz * inner_x;
-    fold[zz * nx + i] = g(A, zz, i + ha);
-  }
+  const int RG = T / nx, c = threadIdx.x % nx, r0 = threadIdx.x / nx;
+  const bool mine = r0 < RG;                       // threads past RG * nx idle in the copies
+  if (mine && c >= 1 && c < nx - 1)
+    for (int zz = r0; zz < KZ; zz += RG) fold[zz * nx + c] = g(A, zz, c + ha);
+  const int edges_x = nx > 1 ? 2 : 1;
   for (int e = threadIdx.x; e < KZ * edges_x; e += T) {
     const int zz = e / edges_x, side = e - zz * edges_x;
     const int i = side ? nx - 1 : 0;
@@ -274,11 +274,9 @@ __device__ __forceinline__ void fold_store(const float2* A, float* fold, int nx,
     fold[zz * nx + i] = a;
   }
   __syncthreads();
-  const int inner_z = nz > 2 ? nz - 2 : 0, edges_z = nz > 1 ? 2 : 1;
-  for (int e = threadIdx.x; e < inner_z * nx; e += T) {
-    const int k = 1 + fdiv(e, r_nx), i = e - (k - 1) * nx;
-    out[(size_t)k * rs + i] = fold[(k + hb) * nx + i];
-  }
+  if (mine)
+    for (int k = 1 + r0; k < nz - 1; k += RG) out[(size_t)k * rs + c] = fold[(k + hb) * nx + c];
+  const int edges_z = nz > 1 ? 2 : 1;
   for (int e = threadIdx.x; e < edges_z * nx; e += T) {
     const int side = e / nx, i = e - side * nx;
     const int k = side ? nz - 1 : 0;
