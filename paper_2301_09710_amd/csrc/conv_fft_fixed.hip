@@ -27,9 +27,14 @@ using namespace fft;
 
 __device__ __forceinline__ int clampi(int q, int lo, int hi) { return q < lo ? lo : (q > hi ? hi : q); }
 
+// Threads of the forward convolution kernel.
+constexpr int kFwdThreads = 768;
+
 // Row stride (floats) of the raw W plane in LDS: odd when whole waves load
-// whole row segments (nx a multiple of 64), so that the lanes of the first x
-// pass, on consecutive rows, read distinct banks; packed otherwise.
+// whole row segments (nx a multiple of 64; fits() then also requires that the
+// forward's waves split evenly over a row's segments), so that the lanes of
+// the first x pass, on consecutive rows, read distinct banks; packed
+// otherwise.
 __host__ __device__ __forceinline__ int raw_stride(int nx) { return nx % 64 == 0 ? nx + 1 : nx; }
 
 
@@ -420,18 +425,23 @@ __global__ __launch_bounds__(C::T) void conv_fwd_fft_c(const float* __restrict__
   const int rrs = raw_stride(nx);
   // plane j of W straight into the raw LDS region (lane L of a wave writes
   // the wave's base + 4 L bytes: 64 consecutive elements of the [nz][nx] plane)
+  // nx a multiple of 64: every wave keeps one 64-element segment of a row
+  // (nx / 64 divides the wave count, which fits() checks) and walks its rows
+  // with uniform pointer steps, rows rrs floats apart in LDS; otherwise the
+  // plane is packed and each lane finds its element
+  const int segs = nx >> 6, nwv = C::T / 64;
+  const bool walk = nx % 64 == 0;
   auto load_plane = [&](int j) {
     const int lane = tid & 63, wbase = tid - lane;
-    if (nx % 64 == 0) {
-      // each wave's 64 elements lie in one row: row and column offsets are
-      // uniform; rows are rrs = nx + 1 floats apart in LDS
-      for (int e0 = wbase; e0 < plane; e0 += C::T) {
-        const int k = __builtin_amdgcn_readfirstlane(e0 / nx);
-        const int i0 = __builtin_amdgcn_readfirstlane(e0 - k * nx);
-        __builtin_amdgcn_global_load_lds(Wl + (size_t)k * rs + (size_t)j * nx + i0 + lane,
-                                         (__attribute__((address_space(3))) void*)(m.extra + k * rrs + i0),
-                                         4, 0, 0);
-      }
+    if (walk) {
+      const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+      const int seg = wv % segs, k0 = wv / segs, kstep = nwv / segs;
+      const float* g = Wl + (size_t)k0 * rs + (size_t)j * nx + seg * 64 + lane;
+      float* l = m.extra + k0 * rrs + seg * 64;
+      const size_t gstep = (size_t)kstep * rs;
+      const int lstep = kstep * rrs;
+      for (int k = k0; k < nz; k += kstep, g += gstep, l += lstep)
+        __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)l, 4, 0, 0);
     } else {
       for (int e0 = wbase; e0 < plane; e0 += C::T) {
         const int e = e0 + lane;
@@ -613,7 +623,7 @@ template <template <int> class CF, bool kReal>
 hipError_t launch_cr(const Plan& p, int which, const void* in, void* out, int view0, int nvb,
                      hipStream_t st) {
   using CW = CF<1024>;   // transforms of one plane per workgroup pass
-  using CFW = CF<768>;   // forward convolution
+  using CFW = CF<kFwdThreads>;   // forward convolution
   using CB = CF<768>;    // adjoint
   const FftShape& s = p.fft;
   char* ws = p.ws;
@@ -673,6 +683,7 @@ hipError_t launch_c(const Plan& p, int which, const void* in, void* out, int vie
 template <class C>
 bool fits(const FftShape& s) {
   return s.Lx == C::Lx && s.Lz == C::Lz && s.nz * s.nx <= 16384 &&
+         (s.nx % 64 != 0 || (kFwdThreads / 64) % (s.nx / 64) == 0) &&
          smem_bytes<C>(s.nz * raw_stride(s.nx)) <= kLdsBytes &&
          smem_bytes<C>((s.nz + 2 * s.hb) * s.nx) <= kLdsBytes;
 }
