@@ -365,6 +365,24 @@ constexpr size_t smem_bytes(int extra_floats) {
   return ((size_t)C::H * C::ST + C::Lx + C::Lz) * sizeof(float2) + (size_t)extra_floats * sizeof(float);
 }
 
+// Plane shape of the convolution kernels: read at run time (RunShape) or
+// fixed at compile time for the common workloads (FixShape), so that the
+// clamps of the replicate padding, the fold's loops and the plane loads work
+// on constants.
+struct RunShape {
+  __device__ static int nx(const FftShape& s) { return s.nx; }
+  __device__ static int nz(const FftShape& s) { return s.nz; }
+  __device__ static int ha(const FftShape& s) { return s.ha; }
+  __device__ static int hb(const FftShape& s) { return s.hb; }
+};
+template <int NX, int NZ, int HA, int HB>
+struct FixShape {
+  __device__ static constexpr int nx(const FftShape&) { return NX; }
+  __device__ static constexpr int nz(const FftShape&) { return NZ; }
+  __device__ static constexpr int ha(const FftShape&) { return HA; }
+  __device__ static constexpr int hb(const FftShape&) { return HB; }
+};
+
 // ---------------------------------------------------------------- kernels
 // kReal: the PSFs are symmetric in x and in z.  Their spectra are then taken
 // of the PSF centred on the origin (tap (b, a) at ((b - hb) mod Lz,
@@ -404,7 +422,7 @@ __global__ __launch_bounds__(C::T) void psf_spectra_c(const float* __restrict__ 
   else store_slots<C>(m.A, P + (size_t)jl * C::NS, scale);
 }
 
-template <class C, bool kReal>
+template <class C, bool kReal, class SH>
 __global__ __launch_bounds__(C::T) void conv_fwd_fft_c(const float* __restrict__ W,
                                                      const Spec<kReal>* __restrict__ P,
                                                      float2* __restrict__ part, FftShape s,
@@ -415,7 +433,8 @@ __global__ __launch_bounds__(C::T) void conv_fwd_fft_c(const float* __restrict__
   int j0, j1;
   chunk_range(c, s.nchunk, s.ny, j0, j1);
   m.setup();
-  const int tid = threadIdx.x, nx = s.nx, nz = s.nz, plane = nz * nx;
+  const int tid = threadIdx.x, nx = SH::nx(s), nz = SH::nz(s), plane = nz * nx;
+  const int ha = SH::ha(s), hb = SH::hb(s);
   const size_t rs = (size_t)s.ny * nx;
   const float* Wl = W + (size_t)lb * nz * rs;
   const float rnx = 1.0f / (float)nx;
@@ -471,7 +490,7 @@ __global__ __launch_bounds__(C::T) void conv_fwd_fft_c(const float* __restrict__
     };
     __builtin_amdgcn_s_waitcnt(0);                 // this plane's loads into raw landed
     __syncthreads();                               // raw complete, A free, twiddles ready
-    xpass_first_from_raw<C>(m.A, m.twx, m.extra, rrs, nx, nz, s.ha, s.hb);  // ends with a barrier
+    xpass_first_from_raw<C>(m.A, m.twx, m.extra, rrs, nx, nz, ha, hb);  // ends with a barrier
     if (j + 1 < j1) load_plane(j + 1);             // raw consumed
     fft2_fwd_rest<C>(m.A, m.twz, load_p);
 #pragma unroll
@@ -562,7 +581,7 @@ __global__ __launch_bounds__(C::T) void back_fft_prep_c(const float* __restrict_
   store_slots<C>(m.A, V + (size_t)lb * C::NS, 1.0f);
 }
 
-template <class C, bool kReal>
+template <class C, bool kReal, class SH>
 __global__ __launch_bounds__(C::T) void conv_back_fft_c(const float2* __restrict__ V,
                                                       const Spec<kReal>* __restrict__ P,
                                                       float* __restrict__ U, FftShape s, int view0,
@@ -573,7 +592,7 @@ __global__ __launch_bounds__(C::T) void conv_back_fft_c(const float2* __restrict
   int j0, j1;
   chunk_range(c, s.nchunk_back, s.ny, j0, j1);
   m.setup();
-  const int tid = threadIdx.x, nx = s.nx, nz = s.nz;
+  const int tid = threadIdx.x, nx = SH::nx(s), nz = SH::nz(s);
   // the PSF spectrum of the next plane is loaded into registers during this
   // plane's transform; the view's projection spectrum (86 KB at 180 x 120)
   // is read per plane, from L2 after the first
@@ -610,13 +629,25 @@ __global__ __launch_bounds__(C::T) void conv_back_fft_c(const float2* __restrict
     __syncthreads();
     if (j + 1 < j1) load_p(j + 1);                 // the next plane's spectrum, during this one
     fft2_inv<C>(m.A, m.twx, m.twz);
-    fold_store(m.A, m.extra, nx, nz, s.ha, s.hb, Ul + (size_t)j * nx, rs,
+    fold_store(m.A, m.extra, nx, nz, SH::ha(s), SH::hb(s), Ul + (size_t)j * nx, rs,
                [](const float2* A, int k, int c) { return plane_at<C>(A, k, c); }, C::T);
   }
 }
 
 hipError_t set_smem(const void* fn, size_t sm) {
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+}
+
+// The plane shapes compiled in: 128 x 80 with 37 x 37 PSFs on the 180 x 120
+// transforms, 64 x 40 with 19 x 19 PSFs on the 90 x 60 ones; others at run time.
+template <class C, class F>
+hipError_t with_plane_shape(const FftShape& s, F&& f) {
+  if constexpr (C::Lx == 180 && C::Lz == 120) {
+    if (s.nx == 128 && s.nz == 80 && s.ha == 18 && s.hb == 18) return f(FixShape<128, 80, 18, 18>());
+  } else if constexpr (C::Lx == 90 && C::Lz == 60) {
+    if (s.nx == 64 && s.nz == 40 && s.ha == 9 && s.hb == 9) return f(FixShape<64, 40, 9, 9>());
+  }
+  return f(RunShape());
 }
 
 template <template <int> class CF, bool kReal>
@@ -641,11 +672,15 @@ hipError_t launch_cr(const Plan& p, int which, const void* in, void* out, int vi
     }
     case kFftForward: {
       const size_t sm = smem_bytes<CFW>(s.nz * raw_stride(s.nx));
-      if ((e = set_smem((const void*)conv_fwd_fft_c<CFW, kReal>, sm)) != hipSuccess) return e;
-      hipLaunchKernelGGL((conv_fwd_fft_c<CFW, kReal>), dim3((unsigned)(nvb * s.nchunk)),
-                         dim3(CFW::T), sm, st, static_cast<const float*>(in), P, part, s, view0,
-                         nvb);
-      break;
+      return with_plane_shape<CFW>(s, [&](auto sh) {
+        using SH = decltype(sh);
+        hipError_t r = set_smem((const void*)conv_fwd_fft_c<CFW, kReal, SH>, sm);
+        if (r != hipSuccess) return r;
+        hipLaunchKernelGGL((conv_fwd_fft_c<CFW, kReal, SH>), dim3((unsigned)(nvb * s.nchunk)),
+                           dim3(CFW::T), sm, st, static_cast<const float*>(in), P, part, s, view0,
+                           nvb);
+        return hipGetLastError();
+      });
     }
     case kFftFinish: {
       const size_t sm = smem_bytes<CW>(0);
@@ -663,10 +698,14 @@ hipError_t launch_cr(const Plan& p, int which, const void* in, void* out, int vi
     }
     case kFftBack: {
       const size_t sm = smem_bytes<CB>((s.nz + 2 * s.hb) * s.nx);
-      if ((e = set_smem((const void*)conv_back_fft_c<CB, kReal>, sm)) != hipSuccess) return e;
-      hipLaunchKernelGGL((conv_back_fft_c<CB, kReal>), dim3((unsigned)(nvb * s.nchunk_back)),
-                         dim3(CB::T), sm, st, V, P, static_cast<float*>(out), s, view0, nvb);
-      break;
+      return with_plane_shape<CB>(s, [&](auto sh) {
+        using SH = decltype(sh);
+        hipError_t r = set_smem((const void*)conv_back_fft_c<CB, kReal, SH>, sm);
+        if (r != hipSuccess) return r;
+        hipLaunchKernelGGL((conv_back_fft_c<CB, kReal, SH>), dim3((unsigned)(nvb * s.nchunk_back)),
+                           dim3(CB::T), sm, st, V, P, static_cast<float*>(out), s, view0, nvb);
+        return hipGetLastError();
+      });
     }
     default: return hipErrorInvalidValue;
   }
