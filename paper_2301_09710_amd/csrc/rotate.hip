@@ -973,6 +973,20 @@ __global__ void back_reduce_kernel(const float* __restrict__ partial, float* __r
   x[p] = s;
 }
 
+// The same sums, four consecutive voxels per thread (N a multiple of 4, x
+// 16-byte aligned); each voxel adds its groups in the same order.
+__global__ void back_reduce4_kernel(const float4* __restrict__ partial, float4* __restrict__ x,
+                                    size_t N4, int G) {
+  const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N4) return;
+  float4 s = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  for (int g = 0; g < G; ++g) {
+    const float4 v = partial[(size_t)g * N4 + p];
+    s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
+  }
+  x[p] = s;
+}
+
 size_t tab_bytes(int n) { return (size_t)2 * n * sizeof(TabEntry); }
 constexpr int kMaxFwdViews = 16;   // views per workgroup of the forward line-pass kernel, at most
 // the forward line-pass kernel: the guarded slice and the tables of its VG views
@@ -1167,8 +1181,15 @@ hipError_t launch_rot_back(const Plan& p, const float* U, const float* mb, int m
 
 hipError_t launch_back_reduce(const Plan& p, const float* partial, float* x, hipStream_t s) {
   const size_t N = (size_t)p.g.nx * p.g.ny * p.g.nz;
-  hipLaunchKernelGGL(back_reduce_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s,
-                     partial, x, N, kBackGroups);
+  if (N % 4 == 0 && (uintptr_t)x % 16 == 0 && (uintptr_t)partial % 16 == 0) {
+    const size_t N4 = N / 4;
+    hipLaunchKernelGGL(back_reduce4_kernel, dim3((unsigned)((N4 + 255) / 256)), dim3(256), 0, s,
+                       reinterpret_cast<const float4*>(partial), reinterpret_cast<float4*>(x), N4,
+                       kBackGroups);
+  } else {
+    hipLaunchKernelGGL(back_reduce_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s,
+                       partial, x, N, kBackGroups);
+  }
   return hipGetLastError();
 }
 
