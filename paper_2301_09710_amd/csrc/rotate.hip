@@ -423,11 +423,12 @@ __device__ void mubar_scan(float* Y, double* seg, int n, int S, double dy) {
 // kGlobal (slices larger than LDS allows): the source slice is read in place
 // from mu and the working slice Y is the workgroup's own slice of `scratch`
 // (L2-resident); the scan segments and tables stay in LDS.
-template <int EPL, bool kGlobal, bool kBil>
+template <int EPL, bool kGlobal, bool kBil, int kN>
 __global__ __launch_bounds__(NT) void mubar_kernel(const float* __restrict__ mu,
-                                                   float* __restrict__ out, int n, int nz,
+                                                   float* __restrict__ out, int n_arg, int nz,
                                                    int view0, int nviews, int VG, int out_view0,
                                                    Tables tab, double dy, float* scratch) {
+  const int n = kN ? kN : n_arg;                   // kN: the slice size fixed at compile time
   extern __shared__ float smem[];
   const int S = slice_stride(n);
   const int k = blockIdx.x;
@@ -1050,15 +1051,18 @@ hipError_t launch_mubar(const Plan& p, float* out, int view0, int nviews, int ou
   const int VG = kRotViewsPerGroup;
   dim3 grid(p.g.nz, (nviews + VG - 1) / VG);
   return with_shape(n, [&](auto E, auto, auto G) {
-    auto go = [&](auto B) {
-      hipError_t e = set_smem((const void*)mubar_kernel<E.value, G.value, B.value>, sm);
+    auto go = [&](auto B, auto N) {
+      hipError_t e = set_smem((const void*)mubar_kernel<E.value, G.value, B.value, N.value>, sm);
       if (e != hipSuccess) return e;
-      hipLaunchKernelGGL((mubar_kernel<E.value, G.value, B.value>), grid, dim3(NT), sm, s, p.mu,
-                         out, n, p.g.nz, view0, nviews, VG, out_view0, p.tab, p.g.dy,
+      hipLaunchKernelGGL((mubar_kernel<E.value, G.value, B.value, N.value>), grid, dim3(NT), sm, s,
+                         p.mu, out, n, p.g.nz, view0, nviews, VG, out_view0, p.tab, p.g.dy,
                          p.rot_scratch);
       return hipGetLastError();
     };
-    return p.bilinear ? go(std::true_type()) : go(std::false_type());
+    if (p.bilinear) return go(std::true_type(), std::integral_constant<int, 0>());
+    if constexpr (!G.value)
+      return with_fixed_n(n, E, [&](auto N) { return go(std::false_type(), N); });
+    return go(std::false_type(), std::integral_constant<int, 0>());
   });
 }
 
